@@ -1,0 +1,437 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: the worked
+example (Sec. IV-B Example 1), the literal unrolled-mask construction of
+Sec. IV (built separately in numpy), brute force on tiny inputs, closed
+forms, the Boolean semantics (Sec. III-B), duality, associativity of
+logsumexp (Sec. IV-D) and central finite differences for every gradient.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import literal_mask as LM
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+RHO = 1e6
+
+
+def sig1(s):
+    """[1, L, 1] trajectory whose identity predicate is the signal s."""
+    return np.asarray(s, dtype=np.float64).reshape(1, -1, 1)
+
+
+S = {"op": "linear", "w": [1.0], "c": 0.0}
+
+
+def ev(child, a, b, **kw):
+    return dict({"op": "eventually", "a": a, "b": b, "child": child}, **kw)
+
+
+def al(child, a, b, **kw):
+    return dict({"op": "always", "a": a, "b": b, "child": child}, **kw)
+
+
+# --------------------------------------------------------------------------- Example 1
+
+def test_example1_golden(orc):
+    g = json.load(open(os.path.join(HERE, "golden", "example1.json")))
+    x = sig1(g["signal"])
+    for pad in ("last", "const"):
+        out = orc.forward(ev(S, g["a"], g["b"], pad=pad, pad_value=7.0), x)[0]
+        assert out.tolist() == g["pad_last_value_7"]
+    out = orc.forward(ev(S, g["a"], g["b"], pad="const", pad_value=-1e5), x)[0]
+    assert out.tolist() == g["by_definition_pad_minus_1e5"]
+    assert out.tolist() != g["paper_printed_pad_minus_1e5"]
+    out = orc.forward(ev(S, g["a"], g["b"]), x)[0]              # NEUTRAL: empty -> -rho_pad
+    assert out.tolist() == [3, 4, 5, 6, 7, 7, 7, -RHO]
+    # the literal unrolled-array construction gives the same vectors
+    assert LM.window_op(g["signal"], 1, 3, pad="const", pad_value=7.0).tolist() == g["pad_last_value_7"]
+    assert LM.window_op(g["signal"], 1, 3, pad="const", pad_value=-1e5).tolist() == g["by_definition_pad_minus_1e5"]
+
+
+# --------------------------------------------------------------------------- literal masks
+
+@pytest.mark.parametrize("smooth", [False, True])
+@pytest.mark.parametrize("kind", ["max", "min"])
+def test_windows_match_literal_masks(orc, smooth, kind):
+    rng = np.random.default_rng(11)
+    for L in (1, 2, 3, 7, 12):
+        for _ in range(6):
+            s = rng.normal(size=L) * 2
+            a = int(rng.integers(0, L + 2))
+            b = None if rng.random() < 0.25 else a + int(rng.integers(0, L + 2))
+            pads = ["neutral"] if b is None else ["neutral", "last", "const"]
+            for pad in pads:
+                pv = float(rng.normal())
+                spec = (ev if kind == "max" else al)(S, a, b, smooth=smooth, beta=3.0, pad=pad,
+                                                      pad_value=pv)
+                got = orc.forward(spec, sig1(s), rho_pad=LM.BIG)[0]
+                ref = LM.window_op(s, a, b, kind, smooth, 3.0, pad, pv)
+                np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("smooth", [False, True])
+def test_until_matches_literal_masks(orc, smooth):
+    rng = np.random.default_rng(12)
+    for L in (1, 2, 4, 9):
+        for _ in range(8):
+            phi, psi = rng.normal(size=L), rng.normal(size=L)
+            a = int(rng.integers(0, L + 1))
+            b = None if rng.random() < 0.25 else a + int(rng.integers(0, L + 1))
+            x = np.stack([phi, psi], -1)[None]
+            spec = {"op": "until", "a": a, "b": b, "smooth": smooth, "beta": 2.5,
+                    "left": {"op": "linear", "w": [1, 0], "c": 0},
+                    "right": {"op": "linear", "w": [0, 1], "c": 0}}
+            got = orc.forward(spec, x, rho_pad=LM.BIG)[0]
+            ref = LM.until_op(phi, psi, a, b, smooth, 2.5)
+            np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("smooth", [False, True])
+@pytest.mark.parametrize("kind", ["max", "min"])
+def test_smooth_mask_matches_literal(orc, smooth, kind):
+    rng = np.random.default_rng(13)
+    for L in (1, 5, 17, 40):
+        for (a, b, c, eps) in [(2.0, 9.0, 1.0, 1e-6), (0.3, 3.7, 4.0, 1e-3), (5.0, None, 0.7, 1e-6),
+                               (10.5, 12.5, 2.0, 1e-2)]:
+            s = rng.normal(size=L)
+            spec = {"op": "eventually" if kind == "max" else "always", "smooth": smooth, "beta": 4.0,
+                    "mask": {"a": a, "b": b, "c": c, "eps": eps}, "child": S}
+            got = orc.forward(spec, sig1(s), rho_pad=LM.BIG)[0]
+            ref = LM.smooth_mask_op(s, a, b, c, eps, kind, smooth, 4.0)
+            np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-11)
+
+
+# --------------------------------------------------------------------------- brute force
+
+def _until_triple(phi, psi, a, b, smooth, beta):
+    """O(L b^2) brute force of the Until definition (Sec. IV-C, first display)."""
+    L = len(phi)
+    out = np.full(L, -RHO)
+    for t in range(L):
+        vals = []
+        for i in range(a, (L - 1 - t if b is None else b) + 1):
+            if t + i > L - 1:
+                break
+            inner = [phi[t + k] for k in range(i + 1)]
+            if smooth:
+                allv = np.array(inner + [psi[t + i]])
+                vals.append(-np.log(np.exp(-beta * allv).sum()) / beta)
+            else:
+                vals.append(min(min(inner), psi[t + i]))
+        if vals:
+            out[t] = (np.log(np.exp(beta * np.array(vals)).sum()) / beta) if smooth else max(vals)
+    return out
+
+
+@pytest.mark.parametrize("smooth", [False, True])
+def test_until_running_min_vs_triple_loop(orc, smooth):
+    rng = np.random.default_rng(14)
+    for L in (3, 8, 20):
+        for (a, b) in [(0, 0), (0, 5), (2, 6), (3, None), (0, None), (4, 30)]:
+            phi, psi = rng.normal(size=L), rng.normal(size=L)
+            x = np.stack([phi, psi], -1)[None]
+            spec = {"op": "until", "a": a, "b": b, "smooth": smooth, "beta": 1.5,
+                    "left": {"op": "linear", "w": [1, 0], "c": 0},
+                    "right": {"op": "linear", "w": [0, 1], "c": 0}}
+            got = orc.forward(spec, x)[0]
+            np.testing.assert_allclose(got, _until_triple(phi, psi, a, b, smooth, 1.5), rtol=1e-12, atol=1e-12)
+
+
+def test_hard_window_brute_force_argmax_tiebreak(orc):
+    """Gradient of a hard window goes to the lowest-index maximiser (tie rule)."""
+    s = np.array([1.0, 3.0, 3.0, 0.0, 3.0, 2.0])
+    x = sig1(s)
+    G = np.zeros((1, 6))
+    G[0, 0] = 1.0                                  # window [0,5] of t=0: ties at 1, 2, 4
+    dx, _ = orc.backward(ev(S, 0, 5), x, G)
+    assert dx[0, :, 0].tolist() == [0, 1, 0, 0, 0, 0]
+    dx, _ = orc.backward(al(S, 3, 5), x, G)        # min over {0, 3, 2} -> index 3
+    assert dx[0, :, 0].tolist() == [0, 0, 0, 1, 0, 0]
+
+
+# --------------------------------------------------------------------------- closed forms
+
+def test_special_windows_closed_form(orc):
+    rng = np.random.default_rng(15)
+    s = rng.normal(size=50)
+    x = sig1(s)
+    assert np.array_equal(orc.forward(ev(S, 0, 0), x)[0], s)                  # [0,0] identity
+    out = orc.forward(ev(S, 4, 4, pad="const", pad_value=9.5), x)[0]        # [k,k] shift
+    assert np.array_equal(out, np.concatenate([s[4:], np.full(4, 9.5)]))
+    suf = np.maximum.accumulate(s[::-1])[::-1]                              # unbounded = suffix max
+    assert np.array_equal(orc.forward(ev(S, 0, None), x)[0], suf)
+    suf3 = np.concatenate([suf[3:], np.full(3, -RHO)])
+    assert np.array_equal(orc.forward(ev(S, 3, None), x)[0], suf3)
+    sufmin = np.minimum.accumulate(s[::-1])[::-1]
+    assert np.array_equal(orc.forward(al(S, 0, None), x)[0], sufmin)
+
+
+def test_lse_constant_window_and_bounds(orc):
+    beta = 10.0
+    x = sig1(np.full(30, 0.7))
+    out = orc.forward(ev(S, 2, 6, smooth=True, beta=beta), x)[0]
+    K = np.minimum(5, np.maximum(0, 30 - 2 - np.arange(30)))
+    np.testing.assert_allclose(out[K > 0], 0.7 + np.log(K[K > 0]) / beta, rtol=0, atol=1e-14)
+    rng = np.random.default_rng(16)
+    s = rng.normal(size=400)
+    hard = orc.forward(ev(S, 0, 299), sig1(s))[0]
+    soft = orc.forward(ev(S, 0, 299, smooth=True, beta=beta), sig1(s))[0]
+    n = np.minimum(300, 400 - np.arange(400))
+    assert np.all(hard <= soft + 1e-12)
+    assert np.all(soft <= hard + np.log(n) / beta + 1e-12)
+    smin = orc.forward(al(S, 0, 299, smooth=True, beta=beta), sig1(s))[0]
+    hmin = orc.forward(al(S, 0, 299), sig1(s))[0]
+    assert np.all(smin <= hmin + 1e-12) and np.all(smin >= hmin - np.log(n) / beta - 1e-12)
+
+
+def test_smooth_approaches_hard_as_temperature_vanishes(orc):
+    rng = np.random.default_rng(17)
+    x = rng.normal(size=(3, 60, 2))
+    spec_s = lambda beta: {"op": "and", "smooth": True, "beta": beta, "children": [
+        {"op": "always", "a": 0, "b": None, "smooth": True, "beta": beta,
+         "child": {"op": "eventually", "a": 2, "b": 9, "smooth": True, "beta": beta,
+                   "child": {"op": "linear", "w": [1, 0], "c": 0.1}}},
+        {"op": "until", "a": 1, "b": 12, "smooth": True, "beta": beta,
+         "left": {"op": "linear", "w": [0, -1], "c": -0.5}, "right": {"op": "linear", "w": [1, 1], "c": 0}}]}
+    hard = orc.forward(_harden(spec_s(1.0)), x)
+    prev = None
+    for beta in (10.0, 100.0, 1000.0, 10000.0):
+        err = np.abs(orc.forward(spec_s(beta), x) - hard).max()
+        # error bounded by depth * log(max window) / beta
+        assert err <= 3 * np.log(62) / beta + 1e-9
+        if prev is not None:
+            assert err < prev
+        prev = err
+
+
+def _harden(f):
+    g = {k: v for k, v in f.items()}
+    if "smooth" in g:
+        g["smooth"] = False
+    for k in ("child", "left", "right"):
+        if k in g:
+            g[k] = _harden(g[k])
+    if "children" in g:
+        g["children"] = [_harden(c) for c in g["children"]]
+    return g
+
+
+def test_duality_de_morgan(orc):
+    rng = np.random.default_rng(18)
+    s = rng.normal(size=(2, 40, 1))
+    neg = lambda f: {"op": "not", "child": f}
+    for smooth in (False, True):
+        for (a, b, pad) in [(0, 5, "neutral"), (3, 9, "last"), (2, None, "neutral"), (1, 4, "const")]:
+            kw = dict(smooth=smooth, beta=5.0, pad=pad, pad_value=0.25)
+            kw_neg = dict(kw, pad_value=-0.25)
+            box = orc.forward(al(S, a, b, **kw), s)
+            dia = orc.forward(neg(ev(neg(S), a, b, **kw_neg)), s)
+            if smooth:
+                np.testing.assert_allclose(box, dia, rtol=0, atol=1e-12)
+            else:
+                assert np.array_equal(box, dia)              # bit-exact for hard selection
+        # or(p, q) = not(and(not p, not q))
+        p, q = {"op": "linear", "w": [1.0], "c": 0.3}, {"op": "linear", "w": [-1.0], "c": 0.1}
+        o1 = orc.forward({"op": "or", "smooth": smooth, "beta": 5.0, "children": [p, q]}, s)
+        o2 = orc.forward(neg({"op": "and", "smooth": smooth, "beta": 5.0, "children": [neg(p), neg(q)]}), s)
+        np.testing.assert_allclose(o1, o2, rtol=0, atol=1e-12)
+
+
+def test_lse_flat_equals_nested(orc):
+    """Sec. IV-D: nesting logsumexp equals applying it once over all values."""
+    rng = np.random.default_rng(19)
+    x = rng.normal(size=(2, 25, 3))
+    ps = [{"op": "linear", "w": list(np.eye(3)[i]), "c": 0.0} for i in range(3)]
+    flat = orc.forward({"op": "and", "smooth": True, "beta": 7.0, "children": ps}, x)
+    nested = orc.forward({"op": "and", "smooth": True, "beta": 7.0, "children": [
+        ps[0], {"op": "and", "smooth": True, "beta": 7.0, "children": ps[1:]}]}, x)
+    np.testing.assert_allclose(flat, nested, rtol=0, atol=1e-12)
+    # ... and the smooth window equals nesting a window of length 1 chained (no overlap)
+    win = orc.forward(ev(ps[0], 0, 3, smooth=True, beta=7.0), x)
+    manual = np.log(sum(np.exp(7.0 * np.concatenate([x[:, k:, 0], np.full((2, k), -np.inf)], 1))
+                        for k in range(4))) / 7.0
+    np.testing.assert_allclose(win, manual, rtol=0, atol=1e-12)
+
+
+def test_until_identities(orc):
+    rng = np.random.default_rng(20)
+    x = rng.normal(size=(2, 30, 2))
+    phi = {"op": "linear", "w": [1, 0], "c": 0}
+    psi = {"op": "linear", "w": [0, 1], "c": 0}
+    for smooth in (False, True):
+        kw = dict(smooth=smooth, beta=6.0)
+        u00 = orc.forward(dict({"op": "until", "a": 0, "b": 0, "left": phi, "right": psi}, **kw), x)
+        conj = orc.forward(dict({"op": "and", "children": [phi, psi]}, **kw), x)
+        np.testing.assert_allclose(u00, conj, rtol=0, atol=1e-12)     # U_[0,0] = and
+        for (a, b) in [(0, 4), (2, 7), (1, None)]:
+            top = orc.forward(dict({"op": "until", "a": a, "b": b, "left": {"op": "true"}, "right": psi}, **kw), x)
+            eve = orc.forward(dict({"op": "eventually", "a": a, "b": b, "child": psi}, **kw), x)
+            np.testing.assert_allclose(top, eve, rtol=0, atol=1e-12)  # Eventually = True U psi
+    # hard Until = max_i min(Always_[0,i] phi, Always_[i,i] psi) (Sec. IV-C Step 2)
+    a, b = 2, 6
+    u = orc.forward({"op": "until", "a": a, "b": b, "left": phi, "right": psi}, x)
+    parts = []
+    for i in range(a, b + 1):
+        A = orc.forward(al(phi, 0, i, pad="const", pad_value=1e9), x)
+        P = orc.forward(al(psi, i, i), x)
+        parts.append(np.minimum(A, P))
+    dec = np.max(parts, axis=0)
+    L = x.shape[1]
+    dec[:, L - a:] = -RHO
+    assert np.array_equal(u, dec)
+
+
+def _bool_sat(spec, x):
+    """Boolean semantics (Sec. III-B) evaluated independently, per start time."""
+    L = x.shape[0]
+    op = spec["op"]
+    if op == "linear":
+        return x @ np.asarray(spec["w"]) - spec["c"] > 0
+    if op == "not":
+        return ~_bool_sat(spec["child"], x)
+    if op in ("and", "or"):
+        cs = [_bool_sat(c, x) for c in spec["children"]]
+        return np.logical_and.reduce(cs) if op == "and" else np.logical_or.reduce(cs)
+    if op in ("eventually", "always"):
+        c = _bool_sat(spec["child"], x)
+        out = np.zeros(L, bool)
+        for t in range(L):
+            hi = L - 1 - t if spec["b"] is None else min(spec["b"], L - 1 - t)
+            w = [c[t + i] for i in range(spec["a"], hi + 1)]
+            out[t] = (any(w) if op == "eventually" else all(w)) if w else (op == "always")
+        return out
+    if op == "until":
+        l, r = _bool_sat(spec["left"], x), _bool_sat(spec["right"], x)
+        out = np.zeros(L, bool)
+        for t in range(L):
+            hi = L - 1 - t if spec["b"] is None else min(spec["b"], L - 1 - t)
+            out[t] = any(r[t + i] and all(l[t:t + i + 1]) for i in range(spec["a"], hi + 1))
+        return out
+    raise ValueError(op)
+
+
+def test_robustness_sign_matches_boolean_semantics(orc):
+    rng = np.random.default_rng(21)
+    p = {"op": "linear", "w": [1, 0], "c": 0.1}
+    q = {"op": "linear", "w": [0, 1], "c": -0.2}
+    specs = [
+        {"op": "and", "children": [al(p, 0, 3), ev(q, 1, 5)]},
+        {"op": "or", "children": [{"op": "not", "child": p}, ev(al(q, 0, 2), 0, None)]},
+        {"op": "until", "a": 1, "b": 6, "left": p, "right": q},
+        al({"op": "until", "a": 0, "b": None, "left": q, "right": p}, 2, 8),
+    ]
+    for spec in specs:
+        for _ in range(10):
+            x = rng.normal(size=(25, 2))
+            rho = orc.forward(spec, x[None])[0]
+            sat = _bool_sat(spec, x)
+            ok = np.abs(rho) > 1e-12
+            assert np.array_equal((rho > 0)[ok], sat[ok]), spec["op"]
+
+
+# --------------------------------------------------------------------------- smooth mask
+
+def test_smooth_mask_closed_form_and_limits(orc):
+    a, b, c, eps = 100.0, 400.0, 1.0, 1e-6
+    w, da, db = orc.mask_weights(a, b, c, eps, 2048)
+    s = lambda z: 1 / (1 + np.exp(-z))
+    assert w[100] == pytest.approx(0.5 - s(-300.0) - eps, abs=1e-15)
+    assert w[400] == pytest.approx(s(300.0) - 0.5 - eps, abs=1e-15)
+    assert w[250] == pytest.approx(1 - 2 * s(-150.0) - eps, abs=1e-15)
+    nz = np.nonzero(w)[0]
+    assert (nz[0], nz[-1]) == (87, 413)                 # support under eps = 1e-6
+    assert da[100] == pytest.approx(-0.25, abs=1e-12) and db[400] == pytest.approx(0.25, abs=1e-12)
+    assert da[50] == 0 and db[450] == 0                 # clamp region has zero gradient
+    # c -> infinity with half-integer bounds: the smooth-mask LSE equals the
+    # integer-interval LSE on [a+0.5, b-0.5]
+    rng = np.random.default_rng(22)
+    sgl = rng.normal(size=(2, 80, 1))
+    m = orc.forward({"op": "eventually", "smooth": True, "beta": 10.0,
+                     "mask": {"a": 9.5, "b": 30.5, "c": 200.0, "eps": 1e-12}, "child": S}, sgl)
+    iv = orc.forward(ev(S, 10, 30, smooth=True, beta=10.0), sgl)
+    np.testing.assert_allclose(m, iv, rtol=0, atol=1e-10)
+    # the hard variant selects over the support {w > 0}
+    mh = orc.forward({"op": "always", "smooth": False, "mask": {"a": 9.5, "b": 30.5, "c": 3.0, "eps": 1e-6},
+                      "child": S}, sgl)
+    w2, _, _ = orc.mask_weights(9.5, 30.5, 3.0, 1e-6, 80)
+    nz = np.nonzero(w2)[0]
+    ih = orc.forward(al(S, int(nz[0]), int(nz[-1])), sgl)
+    assert np.array_equal(mh, ih)
+
+
+# --------------------------------------------------------------------------- gradients (FD)
+
+def _fd_check(orc, spec, x, G, params=None, h=1e-6, rtol=1e-6, names=()):
+    dx, dp = orc.backward(spec, x, G, params=params)
+    flat = x.reshape(-1)
+    idx = np.random.default_rng(0).choice(flat.size, size=min(40, flat.size), replace=False)
+    for i in idx:
+        xp, xm = flat.copy(), flat.copy()
+        xp[i] += h
+        xm[i] -= h
+        # difference the traces first: empty-window sentinels cancel exactly
+        fp = orc.forward(spec, xp.reshape(x.shape), params=params)
+        fm = orc.forward(spec, xm.reshape(x.shape), params=params)
+        fd = ((fp - fm) * G).sum() / (2 * h)
+        assert dx.reshape(-1)[i] == pytest.approx(fd, rel=rtol, abs=rtol * (1 + np.abs(dx).max()))
+    for nm in names:
+        hp = 1e-4
+        p1 = dict(params); p1[nm] += hp
+        p2 = dict(params); p2[nm] -= hp
+        fd = ((orc.forward(spec, x, params=p1) - orc.forward(spec, x, params=p2)) * G).sum() / (2 * hp)
+        assert dp[nm] == pytest.approx(fd, rel=1e-5, abs=1e-7)
+
+
+def test_fd_smooth_formula_gradients(orc):
+    rng = np.random.default_rng(23)
+    x = rng.normal(size=(2, 40, 4)) * 0.5
+    G = rng.normal(size=(2, 40))
+    import paper_2501_04194_amd.workloads as W
+    spec = W.cfg1_formula(4, beta=3.0)
+    spec["children"][1]["a"], spec["children"][1]["b"] = 2, 12
+    spec["children"][0]["child"]["b"] = 5
+    _fd_check(orc, spec, x, G)
+
+
+def test_fd_smooth_windows_pads_norm(orc):
+    rng = np.random.default_rng(24)
+    x = rng.normal(size=(2, 30, 2))
+    G = rng.normal(size=(2, 30))
+    nrm = {"op": "norm", "A": [[1, 0.5], [0, 1]], "p": [0.2, -0.1], "r": 0.3, "sign": -1.0}
+    for pad in ("neutral", "last", "const"):
+        spec = {"op": "or", "smooth": True, "beta": 4.0, "children": [
+            ev(nrm, 2, 7, smooth=True, beta=4.0, pad=pad, pad_value=0.3),
+            al({"op": "not", "child": {"op": "linear", "w": [1, -1], "c": 0.2}}, 0, 4, smooth=True,
+               beta=2.0, pad=pad, pad_value=-0.1)]}
+        _fd_check(orc, spec, x, G)
+
+
+def test_fd_hard_gradients_away_from_ties(orc):
+    rng = np.random.default_rng(25)
+    x = rng.normal(size=(2, 30, 2))
+    G = rng.normal(size=(2, 30))
+    spec = {"op": "and", "children": [
+        al(ev({"op": "linear", "w": [1, 0], "c": 0}, 1, 4, pad="last"), 0, None),
+        {"op": "until", "a": 1, "b": 9, "left": {"op": "linear", "w": [0, 1], "c": -0.5},
+         "right": {"op": "linear", "w": [1, 1], "c": 0}}]}
+    _fd_check(orc, spec, x, G, h=1e-7)
+
+
+def test_fd_mask_bounds_gradients(orc):
+    rng = np.random.default_rng(26)
+    x = np.cumsum(rng.normal(size=(3, 120, 2)) * 0.1, axis=1)
+    G = rng.normal(size=(3, 120))
+    import paper_2501_04194_amd.workloads as W
+    spec = W.cfg2_formula(beta=4.0)
+    params = {"ev_a": 10.3, "ev_b": 40.7, "ev_c": 1.0, "ev_eps": 1e-6,
+              "al_a": 5.2, "al_b": 30.1, "al_c": 0.5, "al_eps": 1e-4}
+    _fd_check(orc, spec, x, G, params=params, names=("ev_a", "ev_b", "al_a", "al_b"))
+    # unbounded smooth mask: only the lower bound is learnable
+    spec2 = {"op": "eventually", "smooth": True, "beta": 4.0, "mask": {"a": "a", "b": None, "c": 2.0,
+             "eps": 1e-6}, "child": {"op": "linear", "w": [1, 0], "c": 0}}
+    _fd_check(orc, spec2, x, G, params={"a": 7.4}, names=("a",))
