@@ -1,0 +1,232 @@
+/*
+ * stlmi.h -- C ABI of the MI355X (gfx950) STL robustness library.
+ *
+ * The library evaluates robustness traces of Signal Temporal Logic formulas
+ * over batches of trajectories, and their gradients, on the GPU, following
+ * the masking formulation of arXiv 2501.04194 ("STLCG++"):
+ *
+ *   robustness (quantitative semantics) ....... Sec. III-B, eq. (quantitative)
+ *   derived Or / Eventually / Always ........... Sec. III-B (after the grammar)
+ *   logsumexp smooth max / min ................ Sec. III-C
+ *   robustness trace (one value per suffix) ... Sec. III-D, Definition 1
+ *   Eventually / Always over [a,b] ............ Sec. IV-B
+ *   Until over [a,b] .......................... Sec. IV-C
+ *   smooth (sigmoid) time-interval mask ....... Sec. VI, eq. (smooth mask)
+ *
+ * Conventions shared by every entry point:
+ *  - A trajectory of length L has samples 0..L-1; its robustness trace has L
+ *    values, value t being the robustness of the suffix starting at t.
+ *  - Intervals [a,b] are inclusive offsets in timesteps (b = -1: unbounded,
+ *    i.e. up to the last sample).
+ *  - Smooth operators use beta = 1/temperature inside the exponent:
+ *    smax(V) = (1/beta) log sum exp(beta v), smin(V) = -smax(-V).
+ *  - Window positions past the end of a trajectory follow the node's pad
+ *    policy (STL_PAD_NEUTRAL drops them; an empty window yields -rho_pad for
+ *    Eventually/Or/Until and +rho_pad for Always/And).
+ *  - Smooth-mask nodes weight the terms of the logsumexp by
+ *    w_k = max(sig(c(k-a)) - sig(c(k-b)) - eps, 0), k = offset >= 0, with
+ *    a, b, c, eps read from the device parameter buffer at run time (so they
+ *    can be learned or annealed without recompiling the plan).  Their hard
+ *    variant takes max/min over the support {k : w_k > 0}.
+ *  - Hard min/max break ties toward the lowest time index (and the lowest
+ *    child index for n-ary And/Or; the phi side inside Until's min).
+ *
+ * Memory and ownership:
+ *  - A plan (stl_plan) is opaque, host-resident and immutable after
+ *    stl_compile; free it with stl_plan_destroy.  Concurrent calls sharing a
+ *    plan are safe if they use distinct workspaces.
+ *  - Every array passed to stl_forward / stl_backward is caller-owned device
+ *    memory on the current HIP device.  The library never allocates device
+ *    memory, never synchronises and launches only on the given stream, so
+ *    both calls can be captured in a HIP graph.
+ *  - Arguments are validated on the host before any launch; a failure
+ *    returns a negative stl_status and sets a thread-local message readable
+ *    with stl_last_error().  No call aborts or throws.
+ */
+#ifndef STLMI_H
+#define STLMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STL_OK = 0,
+    STL_E_ARG = -1,          /* null pointer, out-of-range index or size */
+    STL_E_FORMULA = -2,      /* malformed node array (cycle, dangling child, bad interval) */
+    STL_E_UNSUPPORTED = -3,  /* valid formula outside the library's limits */
+    STL_E_SHAPE = -4,        /* batch shape inconsistent with the plan */
+    STL_E_WORKSPACE = -5,    /* workspace too small */
+    STL_E_HIP = -6,          /* a HIP runtime call or kernel launch failed */
+    STL_E_NONFINITE = -7     /* reserved: non-finite input detected */
+} stl_status;
+
+typedef enum {
+    STL_TRUE = 0,            /* constant rho_max (Sec. III-B) */
+    STL_PRED_LINEAR = 1,     /* w . x_t - c (Sec. III-A/B, mu(x) - c) */
+    STL_PRED_NORM = 2,       /* sign * (||A x_t - p||_2 - r); gradient 0 where A x_t = p */
+    STL_NOT = 3,             /* -u_t */
+    STL_AND = 4,             /* min / smin over children at the same t */
+    STL_OR = 5,              /* max / smax over children at the same t */
+    STL_EVENTUALLY = 6,      /* max / smax of the child over the window [t+a, t+b] */
+    STL_ALWAYS = 7,          /* min / smin of the child over the window [t+a, t+b] */
+    STL_UNTIL = 8            /* max_{i in [a,b]} min(min_{k<=i} phi_{t+k}, psi_{t+i}) */
+} stl_op;
+
+typedef enum {
+    STL_PAD_NEUTRAL = 0,     /* positions past the end are dropped */
+    STL_PAD_LAST = 1,        /* positions past the end read u[L-1] */
+    STL_PAD_CONST = 2        /* positions past the end read pad_value */
+} stl_pad;
+
+#define STL_MAX_CHILDREN 8
+#define STL_MAX_D 16
+#define STL_MAX_NODES 48
+#define STL_MAX_PREDS 16
+
+/* One formula node.  Children are child_idx[child_off .. child_off+n_child). */
+typedef struct {
+    int32_t op;              /* stl_op */
+    int32_t n_child;         /* NOT/EVENTUALLY/ALWAYS: 1, UNTIL: 2 (phi, psi), AND/OR: 1..8 */
+    int32_t child_off;
+    int32_t smooth;          /* 0: hard min/max, 1: logsumexp */
+    int32_t a, b;            /* integer interval (temporal nodes); b = -1: unbounded */
+    int32_t mask_param;      /* -1: integer interval; else params[mask_param + 0..3] = (a, b, c, eps) */
+    int32_t mask_unbounded;  /* smooth mask with b = +inf (params[mask_param+1] ignored) */
+    int32_t beta_param;      /* smooth nodes: index of beta in params; ignored when hard */
+    int32_t pred;            /* PRED_*: index into the predicate array */
+    int32_t pad;             /* stl_pad (integer-interval EVENTUALLY / ALWAYS only) */
+    float pad_value;         /* STL_PAD_CONST value */
+} stl_node;
+
+/* A predicate mu(x_t) evaluated on the D-dimensional state. */
+typedef struct {
+    int32_t kind;            /* STL_PRED_LINEAR or STL_PRED_NORM */
+    int32_t m;               /* NORM: number of rows of A (1..4) */
+    float w[STL_MAX_D];      /* LINEAR: weights */
+    float c;                 /* LINEAR: offset */
+    float A[4 * STL_MAX_D];  /* NORM: A, m x D row-major */
+    float p[4];              /* NORM: centre */
+    float r;                 /* NORM: radius */
+    float sign;              /* NORM: +1 or -1 */
+} stl_pred;
+
+/* A batch of trajectories in device memory. */
+typedef struct {
+    const float* x;          /* dense: [B, T, D]; ragged: [N_total, D] (rows of trajectory b are
+                                offsets[b] .. offsets[b+1]-1) */
+    int64_t B;               /* number of trajectories */
+    int64_t T;               /* dense: length of every trajectory; ragged: upper bound on the
+                                lengths (sizes on-chip buffers; longer trajectories get NaN) */
+    int32_t D;               /* state dimension, must equal the plan's */
+    int32_t pad0;
+    const int64_t* offsets;  /* device int64[B+1]; NULL for a dense batch */
+    const int32_t* order;    /* device int32[B]: processing order of the persistent scheduler
+                                (e.g. from stl_lpt_order); NULL = 0..B-1 */
+} stl_batch;
+
+/* Launch configuration (NULL = library heuristic; see stl_autotune). */
+typedef struct {
+    int32_t threads;         /* work-group size: 64, 128, 256, 512 or 1024 */
+    int32_t wg_per_cu;       /* persistent grid size per compute unit (0 = one work-group per
+                                trajectory) */
+    int32_t global_slots;    /* 1: keep node traces in the workspace instead of LDS */
+    int32_t reserved;
+} stl_launch;
+
+typedef struct stl_plan stl_plan;
+
+/*
+ * Compile a formula (post-order not required; `root` names the top node)
+ * into an execution plan.  Host only: validates the node array (op codes,
+ * child counts and indices, acyclicity, intervals, predicate and parameter
+ * indices against n_params), orders nodes topologically, assigns on-chip
+ * trace slots by liveness and records the parameter layout.  rho_max is the
+ * value of STL_TRUE, rho_pad the magnitude of the empty-window value.
+ * Returns STL_OK and *out, or STL_E_ARG / STL_E_FORMULA / STL_E_UNSUPPORTED.
+ */
+stl_status stl_compile(const stl_node* nodes, int32_t n_nodes, const int32_t* child_idx,
+                       int32_t n_child_idx, int32_t root, const stl_pred* preds, int32_t n_preds,
+                       int32_t D, int32_t n_params, float rho_max, float rho_pad, stl_plan** out);
+
+/* Free a plan (NULL is accepted). */
+stl_status stl_plan_destroy(stl_plan* plan);
+
+/* Number of formula nodes and parameters the plan was compiled with. */
+stl_status stl_plan_info(const stl_plan* plan, int32_t* n_nodes, int32_t* n_params);
+
+/*
+ * Device workspace needed by stl_forward and stl_backward for this batch and
+ * launch configuration (NULL = heuristic).  Sizes are in bytes.
+ */
+stl_status stl_workspace_size(const stl_plan* plan, const stl_batch* batch, const stl_launch* cfg,
+                              size_t* fwd_bytes, size_t* bwd_bytes);
+
+/*
+ * Robustness traces: d_root receives the root trace ([B, T] dense or
+ * [N_total] ragged, float32).  d_node_traces, if not NULL, receives every
+ * node's trace as [n_nodes][N_total] in the caller's node numbering (debug and
+ * tests).  d_params holds the plan's n_params float32 scalars (beta of smooth
+ * nodes, (a, b, c, eps) of smooth masks).  Asynchronous on `stream`
+ * (a hipStream_t; NULL = default stream).
+ */
+stl_status stl_forward(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                       float* d_root, float* d_node_traces, void* d_ws, size_t ws_bytes,
+                       const stl_launch* cfg, void* stream);
+
+/*
+ * Gradients of sum_t G_t * root_t: d_grad_x (same layout as x) is
+ * overwritten; d_grad_params (n_params floats, may be NULL) is overwritten
+ * with d/da and d/db of every smooth-mask bound and 0 elsewhere.  The
+ * forward node traces are recomputed on chip, not stored.
+ */
+stl_status stl_backward(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                        const float* d_grad_root, float* d_grad_x, float* d_grad_params,
+                        void* d_ws, size_t ws_bytes, const stl_launch* cfg, void* stream);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* stl_last_error(void);
+
+/*
+ * Longest-processing-time order for a ragged batch: host_order[0..B) lists
+ * trajectory indices by decreasing length (ties by index), for
+ * stl_batch.order.  host_offsets is the host copy of the offsets.
+ */
+stl_status stl_lpt_order(const int64_t* host_offsets, int64_t B, int32_t* host_order);
+
+/*
+ * Time the candidate launch configurations on this batch (forward +
+ * backward, on `stream`) and return the fastest in *best (and its time in
+ * milliseconds).  Results are cached in memory per (plan, shape) and, when
+ * the STLMI_TUNE_CACHE environment variable names a file, in that JSON file.
+ * Every candidate computes the same result.  d_ws must be at least the
+ * largest workspace of any candidate (stl_workspace_size with cfg = NULL
+ * times 2 is enough).
+ */
+stl_status stl_autotune(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                        float* d_root, const float* d_grad_root, float* d_grad_x,
+                        float* d_grad_params, void* d_ws, size_t ws_bytes, void* stream,
+                        stl_launch* best, float* best_ms);
+
+/*
+ * Capture stl_forward followed by stl_backward (same arguments) into a HIP
+ * graph and instantiate it.  Replays read the current contents of every
+ * buffer, so new inputs or parameters need no re-capture; a new shape, plan
+ * or buffer address does.  The returned handle is freed by stl_graph_destroy.
+ */
+typedef struct stl_graph stl_graph;
+stl_status stl_graph_capture(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                             float* d_root, const float* d_grad_root, float* d_grad_x,
+                             float* d_grad_params, void* d_ws, size_t ws_bytes,
+                             const stl_launch* cfg, void* stream, stl_graph** out);
+stl_status stl_graph_launch(stl_graph* graph, void* stream);
+stl_status stl_graph_destroy(stl_graph* graph);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STLMI_H */

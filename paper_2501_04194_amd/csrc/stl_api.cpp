@@ -1,0 +1,853 @@
+// C ABI of the STL robustness library: plan compiler, validation, launch
+// configuration, persistent scheduling order, autotuner and HIP-graph
+// capture.  Kernels live in stl_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/stlmi.h"
+#include "stl_plan.h"
+
+namespace stlmi {
+size_t scratch_floats(int Lc, int nt, int max_until_b);
+hipError_t launch_exec(bool bwd, const DevPlan& plan, const struct Batch& bt, const struct KArgs& ka, int grid,
+                       int nt, size_t lds_bytes, hipStream_t s);
+hipError_t set_max_lds(size_t bytes);
+hipError_t launch_zero_counter(int* c, hipStream_t s);
+hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& plan, float* gp, hipStream_t s);
+
+// must match stl_kernels.hip
+struct Batch {
+    const float* x;
+    const int64_t* offsets;
+    const int32_t* order;
+    int64_t B;
+    int64_t T;
+    int32_t D;
+    int32_t Lcap;
+};
+struct KArgs {
+    const float* params;
+    float* root;
+    float* nodes;
+    int64_t n_total;
+    const float* G;
+    float* dx;
+    float* mask_part;
+    float* garena;
+    int64_t arena_floats;
+    int* counter;
+    int persistent;
+};
+}  // namespace stlmi
+
+using namespace stlmi;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+static stl_status fail(stl_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+extern "C" const char* stl_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ plan
+
+struct stl_plan {
+    DevPlan dev;          // liveness-optimised forward slot map
+    DevPlan dev_trace;    // forward map with one slot per instruction (node trace output)
+    int32_t n_nodes = 0;  // caller's nodes
+    int32_t n_params = 0;
+    int32_t D = 0;
+    int32_t max_until_b = 0;
+    int32_t has_until = 0;
+};
+
+namespace {
+
+struct Builder {
+    const stl_node* nodes;
+    int n_nodes;
+    const int32_t* child_idx;
+    int n_child_idx;
+    const stl_pred* preds;
+    int n_preds;
+    int D;
+    int n_params;
+    std::vector<Instr> ins;
+    std::vector<std::vector<int>> kids;   // instruction children (instruction indices)
+    std::vector<float> coef;
+    std::vector<int> pred_ins;
+    std::vector<int> mask_params;
+    int max_until_b = 0;
+    bool has_until = false;
+
+    int new_instr(Instr I, std::vector<int> ch)
+    {
+        ins.push_back(I);
+        kids.push_back(std::move(ch));
+        return (int)ins.size() - 1;
+    }
+};
+
+Instr blank()
+{
+    Instr I;
+    std::memset(&I, 0, sizeof I);
+    I.f_out = I.f_in0 = I.f_in1 = -1;
+    I.b_out = I.b_in0 = I.b_in1 = -1;
+    I.g_out = I.g_in0 = I.g_in1 = -1;
+    I.beta = I.mask = I.mslot = -1;
+    for (int k = 0; k < MAX_NCH; ++k) I.f_ch[k] = I.b_ch[k] = I.g_ch[k] = -1;
+    I.node = -1;
+    I.coef = 0;
+    I.b = -1;
+    return I;
+}
+
+// emit the instruction(s) of caller node `id` (post-order); returns instruction index
+stl_status emit(Builder& B, int id, int depth, int* out)
+{
+    if (depth > 256) return fail(STL_E_FORMULA, "formula too deep (cycle?) at node %d", id);
+    const stl_node& n = B.nodes[id];
+    Instr I = blank();
+    I.node = (int16_t)id;
+    std::vector<int> ch;
+    auto child = [&](int k) { return B.child_idx[n.child_off + k]; };
+    // children first
+    std::vector<int> kid_ins;
+    for (int k = 0; k < n.n_child; ++k) {
+        int ci;
+        stl_status s = emit(B, child(k), depth + 1, &ci);
+        if (s != STL_OK) return s;
+        kid_ins.push_back(ci);
+    }
+    const bool smooth = n.smooth != 0;
+    if (smooth) {
+        if (n.beta_param < 0 || n.beta_param >= B.n_params)
+            return fail(STL_E_ARG, "node %d: smooth node needs beta_param in [0, n_params)", id);
+        I.beta = (int8_t)n.beta_param;
+        I.flags |= F_SMOOTH;
+    }
+    switch (n.op) {
+    case STL_TRUE:
+        I.kind = K_TRUE;
+        break;
+    case STL_PRED_LINEAR:
+    case STL_PRED_NORM: {
+        if (n.pred < 0 || n.pred >= B.n_preds) return fail(STL_E_ARG, "node %d: pred index out of range", id);
+        const stl_pred& p = B.preds[n.pred];
+        if (p.kind != n.op) return fail(STL_E_FORMULA, "node %d: predicate kind does not match the node op", id);
+        I.kind = n.op == STL_PRED_LINEAR ? K_LIN : K_NORM;
+        I.coef = (int16_t)B.coef.size();
+        if (n.op == STL_PRED_LINEAR) {
+            B.coef.push_back(p.c);
+            for (int d = 0; d < B.D; ++d) B.coef.push_back(p.w[d]);
+        } else {
+            if (p.m < 1 || p.m > 4) return fail(STL_E_UNSUPPORTED, "node %d: norm predicate needs 1..4 rows", id);
+            B.coef.push_back((float)p.m);
+            B.coef.push_back(p.r);
+            B.coef.push_back(p.sign);
+            for (int i = 0; i < 4; ++i) B.coef.push_back(p.p[i]);
+            for (int i = 0; i < p.m * B.D; ++i) B.coef.push_back(p.A[i]);
+        }
+        if ((int)B.coef.size() > MAX_COEF) return fail(STL_E_UNSUPPORTED, "too many predicate coefficients");
+        if ((int)B.pred_ins.size() >= MAX_PRED) return fail(STL_E_UNSUPPORTED, "more than %d predicates", MAX_PRED);
+        break;
+    }
+    case STL_NOT:
+        I.kind = K_NOT;
+        break;
+    case STL_AND:
+    case STL_OR: {
+        I.kind = K_NARY;
+        if (n.op == STL_AND) I.flags |= F_MIN;
+        // more than MAX_NCH children: nest groups left to right (min/max and
+        // logsumexp are associative; left nesting keeps the lowest-child tie rule)
+        while ((int)kid_ins.size() > MAX_NCH) {
+            Instr J = I;
+            J.node = -1;
+            std::vector<int> grp(kid_ins.begin(), kid_ins.begin() + MAX_NCH);
+            J.nch = MAX_NCH;
+            int j = B.new_instr(J, grp);
+            kid_ins.erase(kid_ins.begin(), kid_ins.begin() + MAX_NCH);
+            kid_ins.insert(kid_ins.begin(), j);
+        }
+        I.nch = (int8_t)kid_ins.size();
+        break;
+    }
+    case STL_EVENTUALLY:
+    case STL_ALWAYS:
+        if (n.op == STL_ALWAYS) I.flags |= F_MIN;
+        if (n.mask_param >= 0) {
+            if (n.mask_param + 3 >= B.n_params) return fail(STL_E_ARG, "node %d: mask_param + 3 >= n_params", id);
+            if ((int)B.mask_params.size() >= MAX_MASKS) return fail(STL_E_UNSUPPORTED, "too many smooth masks");
+            I.kind = K_MASK;
+            I.mask = (int8_t)n.mask_param;
+            I.mslot = (int8_t)B.mask_params.size();
+            B.mask_params.push_back(n.mask_param);
+            if (n.mask_unbounded) I.flags |= F_MASK_UNB;
+        } else {
+            I.kind = K_WIN;
+            if (n.a < 0 || (n.b >= 0 && n.b < n.a) || n.b < -1)
+                return fail(STL_E_FORMULA, "node %d: bad interval [%d, %d]", id, n.a, n.b);
+            I.a = n.a;
+            I.b = n.b;
+            if (n.b < 0) I.flags |= F_UNB;
+            if (n.pad < 0 || n.pad > 2) return fail(STL_E_ARG, "node %d: bad pad policy", id);
+            I.pad = (int8_t)n.pad;
+            I.coef = (int16_t)B.coef.size();
+            B.coef.push_back(n.pad_value);
+        }
+        break;
+    case STL_UNTIL:
+        I.kind = K_UNTIL;
+        if (n.mask_param >= 0) return fail(STL_E_UNSUPPORTED, "node %d: smooth masks on Until are not supported", id);
+        if (n.a < 0 || (n.b >= 0 && n.b < n.a) || n.b < -1)
+            return fail(STL_E_FORMULA, "node %d: bad interval [%d, %d]", id, n.a, n.b);
+        I.a = n.a;
+        I.b = n.b;
+        if (n.b < 0) I.flags |= F_UNB;
+        B.has_until = true;
+        B.max_until_b = std::max(B.max_until_b, n.b < 0 ? (1 << 30) : n.b);
+        break;
+    default:
+        return fail(STL_E_FORMULA, "node %d: unknown op %d", id, n.op);
+    }
+    int k = B.new_instr(I, kid_ins);
+    if (n.op == STL_PRED_LINEAR || n.op == STL_PRED_NORM) B.pred_ins.push_back(k);
+    *out = k;
+    return STL_OK;
+}
+
+int expected_children(int op, int* lo, int* hi)
+{
+    switch (op) {
+    case STL_TRUE: case STL_PRED_LINEAR: case STL_PRED_NORM: *lo = *hi = 0; return 1;
+    case STL_NOT: case STL_EVENTUALLY: case STL_ALWAYS: *lo = *hi = 1; return 1;
+    case STL_UNTIL: *lo = *hi = 2; return 1;
+    case STL_AND: case STL_OR: *lo = 1; *hi = STL_MAX_CHILDREN; return 1;
+    default: return 0;
+    }
+}
+
+// greedy slot allocation over [def, last] intervals
+struct SlotAlloc {
+    std::vector<int> free_at;   // per slot: first step at which it is free again
+    int get(int def_step, int last_step)
+    {
+        for (size_t s = 0; s < free_at.size(); ++s)
+            if (free_at[s] <= def_step) { free_at[s] = last_step + 1; return (int)s; }
+        free_at.push_back(last_step + 1);
+        return (int)free_at.size() - 1;
+    }
+};
+
+}  // namespace
+
+extern "C" stl_status stl_compile(const stl_node* nodes, int32_t n_nodes, const int32_t* child_idx,
+                                  int32_t n_child_idx, int32_t root, const stl_pred* preds, int32_t n_preds,
+                                  int32_t D, int32_t n_params, float rho_max, float rho_pad, stl_plan** out)
+{
+    if (!out) return fail(STL_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!nodes || n_nodes <= 0) return fail(STL_E_ARG, "empty node array");
+    if (n_nodes > STL_MAX_NODES) return fail(STL_E_UNSUPPORTED, "more than %d nodes", STL_MAX_NODES);
+    if (root < 0 || root >= n_nodes) return fail(STL_E_ARG, "root %d out of range", root);
+    if (D < 1 || D > STL_MAX_D) return fail(STL_E_UNSUPPORTED, "D must be in [1, %d]", STL_MAX_D);
+    if (n_params < 0 || n_params > 127) return fail(STL_E_UNSUPPORTED, "n_params must be in [0, 127]");
+    if (n_child_idx < 0 || (n_child_idx > 0 && !child_idx)) return fail(STL_E_ARG, "bad child index array");
+    if (n_preds < 0 || (n_preds > 0 && !preds)) return fail(STL_E_ARG, "bad predicate array");
+    if (!(rho_max > 0) || !(rho_pad > 0)) return fail(STL_E_ARG, "rho_max and rho_pad must be > 0");
+    // structure: child counts and indices, every node reachable from the root at most once
+    std::vector<int> parents(n_nodes, 0);
+    for (int i = 0; i < n_nodes; ++i) {
+        int lo, hi;
+        if (!expected_children(nodes[i].op, &lo, &hi)) return fail(STL_E_FORMULA, "node %d: unknown op %d", i, nodes[i].op);
+        if (nodes[i].n_child < lo || nodes[i].n_child > hi)
+            return fail(STL_E_FORMULA, "node %d: op %d takes %d..%d children, got %d", i, nodes[i].op, lo, hi,
+                        nodes[i].n_child);
+        if (nodes[i].n_child > 0 &&
+            (nodes[i].child_off < 0 || nodes[i].child_off + nodes[i].n_child > n_child_idx))
+            return fail(STL_E_FORMULA, "node %d: children outside child_idx", i);
+    }
+    // reachability walk (iterative) with cycle / sharing detection
+    std::vector<int> stack{root};
+    std::vector<int> seen(n_nodes, 0);
+    seen[root] = 1;
+    while (!stack.empty()) {
+        int i = stack.back();
+        stack.pop_back();
+        for (int k = 0; k < nodes[i].n_child; ++k) {
+            int c = child_idx[nodes[i].child_off + k];
+            if (c < 0 || c >= n_nodes) return fail(STL_E_FORMULA, "node %d: dangling child %d", i, c);
+            if (c == root || seen[c]) return fail(STL_E_FORMULA, "node %d is shared or part of a cycle (formulas are trees)", c);
+            seen[c] = 1;
+            stack.push_back(c);
+        }
+    }
+    Builder B;
+    B.nodes = nodes;
+    B.n_nodes = n_nodes;
+    B.child_idx = child_idx;
+    B.n_child_idx = n_child_idx;
+    B.preds = preds;
+    B.n_preds = n_preds;
+    B.D = D;
+    B.n_params = n_params;
+    int rootk;
+    stl_status s = emit(B, root, 0, &rootk);
+    if (s != STL_OK) return s;
+    const int n = (int)B.ins.size();
+    if (n > MAX_INSTR) return fail(STL_E_UNSUPPORTED, "plan has %d instructions (max %d)", n, MAX_INSTR);
+
+    // consumers
+    std::vector<int> parent(n, -1);
+    for (int k = 0; k < n; ++k)
+        for (int c : B.kids[k]) parent[c] = k;
+
+    // forward slot map: value of k lives from k to its parent's step
+    SlotAlloc fa;
+    std::vector<int> fslot(n);
+    {
+        // intervals: def = k, last = parent step (root: n)
+        for (int k = 0; k < n; ++k) {
+            int last = parent[k] < 0 ? n : parent[k];
+            fslot[k] = fa.get(k, last);
+        }
+    }
+    // backward map: values get their own slots (kept through the adjoint sweep);
+    // adjoints are allocated over the reverse sweep.  Step numbering for the
+    // sweep: step of adjoint(k) = n - 1 - k; predicates' adjoints live to the
+    // final d/dx stage (step n).
+    SlotAlloc ga;
+    std::vector<int> gslot(n, -1);
+    for (int k = n - 1; k >= 0; --k) {
+        int def = parent[k] < 0 ? -1 : (n - 1 - parent[k]);
+        const bool pred = B.ins[k].kind == K_LIN || B.ins[k].kind == K_NORM;
+        int last = pred ? n : (n - 1 - k);
+        gslot[k] = ga.get(def, last);   // the parent's own slot stays busy through its step
+    }
+    // adjoints written by a parent must not share a slot with the parent's own
+    // adjoint: the allocation above already keeps the parent's slot busy
+    // through its own step (n-1-parent), and children are defined at def+1.
+    const int nval = n;
+    const int nadj = (int)ga.free_at.size();
+    for (int k = 0; k < n; ++k) {
+        Instr& I = B.ins[k];
+        const auto& ch = B.kids[k];
+        I.f_out = (int8_t)fslot[k];
+        I.b_out = (int8_t)k;
+        I.g_out = (int8_t)(nval + gslot[k]);
+        if (I.kind == K_NARY) {
+            for (int j = 0; j < (int)ch.size(); ++j) {
+                I.f_ch[j] = (int8_t)fslot[ch[j]];
+                I.b_ch[j] = (int8_t)ch[j];
+                I.g_ch[j] = (int8_t)(nval + gslot[ch[j]]);
+            }
+        } else {
+            if (ch.size() > 0) { I.f_in0 = (int8_t)fslot[ch[0]]; I.b_in0 = (int8_t)ch[0]; I.g_in0 = (int8_t)(nval + gslot[ch[0]]); }
+            if (ch.size() > 1) { I.f_in1 = (int8_t)fslot[ch[1]]; I.b_in1 = (int8_t)ch[1]; I.g_in1 = (int8_t)(nval + gslot[ch[1]]); }
+        }
+    }
+    stl_plan* p = new (std::nothrow) stl_plan();
+    if (!p) return fail(STL_E_ARG, "out of host memory");
+    DevPlan& dp = p->dev;
+    std::memset(&dp, 0, sizeof dp);
+    dp.n_ins = n;
+    dp.n_slots_fwd = (int)fa.free_at.size();
+    dp.n_slots_bwd = nval + nadj;
+    dp.D = D;
+    dp.n_masks = (int)B.mask_params.size();
+    dp.n_params = n_params;
+    dp.n_pred = (int)B.pred_ins.size();
+    dp.root = rootk;
+    dp.rho_max = rho_max;
+    dp.rho_pad = rho_pad;
+    for (int i = 0; i < dp.n_pred; ++i) dp.pred_ins[i] = (int16_t)B.pred_ins[i];
+    for (int i = 0; i < dp.n_masks; ++i) dp.mask_param[i] = (int8_t)B.mask_params[i];
+    for (int k = 0; k < n; ++k) dp.ins[k] = B.ins[k];
+    for (size_t i = 0; i < B.coef.size(); ++i) dp.coef[i] = B.coef[i];
+    // trace-output variant: slot k for instruction k
+    p->dev_trace = dp;
+    DevPlan& tp = p->dev_trace;
+    tp.n_slots_fwd = n;
+    for (int k = 0; k < n; ++k) {
+        Instr& I = tp.ins[k];
+        I.f_out = I.b_out;
+        I.f_in0 = I.b_in0;
+        I.f_in1 = I.b_in1;
+        for (int j = 0; j < MAX_NCH; ++j) I.f_ch[j] = I.b_ch[j];
+    }
+    p->n_nodes = n_nodes;
+    p->n_params = n_params;
+    p->D = D;
+    p->max_until_b = B.max_until_b;
+    p->has_until = B.has_until;
+    *out = p;
+    return STL_OK;
+}
+
+extern "C" stl_status stl_plan_destroy(stl_plan* plan)
+{
+    delete plan;
+    return STL_OK;
+}
+
+extern "C" stl_status stl_plan_info(const stl_plan* plan, int32_t* n_nodes, int32_t* n_params)
+{
+    if (!plan) return fail(STL_E_ARG, "plan is NULL");
+    if (n_nodes) *n_nodes = plan->n_nodes;
+    if (n_params) *n_params = plan->n_params;
+    return STL_OK;
+}
+
+extern "C" stl_status stl_lpt_order(const int64_t* host_offsets, int64_t B, int32_t* host_order)
+{
+    if (!host_offsets || !host_order || B < 0) return fail(STL_E_ARG, "bad arguments");
+    std::vector<int32_t> idx((size_t)B);
+    for (int64_t i = 0; i < B; ++i) {
+        if (host_offsets[i + 1] < host_offsets[i]) return fail(STL_E_ARG, "offsets must be non-decreasing");
+        idx[i] = (int32_t)i;
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+        return host_offsets[a + 1] - host_offsets[a] > host_offsets[b + 1] - host_offsets[b];
+    });
+    std::memcpy(host_order, idx.data(), sizeof(int32_t) * (size_t)B);
+    return STL_OK;
+}
+
+// ------------------------------------------------------------------ launch geometry
+
+namespace {
+
+struct DevInfo {
+    int cus = 256;
+    size_t lds_max = 65536;
+    bool lds_set = false;
+};
+
+std::mutex g_mu;
+std::map<int, DevInfo> g_dev;
+
+DevInfo& devinfo()
+{
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev.find(dev);
+    if (it != g_dev.end()) return it->second;
+    DevInfo di;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) di.cus = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+        di.lds_max = (size_t)v;
+    const size_t static_lds = 8192;   // Shared struct + headroom
+    di.lds_max = di.lds_max > static_lds ? di.lds_max - static_lds : 0;
+    if (set_max_lds(di.lds_max) == hipSuccess) di.lds_set = true;
+    (void)hipGetLastError();
+    return g_dev[dev] = di;
+}
+
+struct Geom {
+    int nt;
+    int grid;
+    int persistent;
+    int Lc;
+    bool global;
+    size_t arena_floats;
+    size_t lds_bytes;
+    size_t ws_bytes;        // total workspace
+    size_t off_part;        // mask partials (bytes)
+    size_t off_arena;       // global arenas (bytes)
+};
+
+stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch* cfg, bool bwd, bool trace,
+                    Geom* g)
+{
+    DevInfo& di = devinfo();
+    const DevPlan& dp = trace ? plan->dev_trace : plan->dev;
+    int nt = cfg && cfg->threads ? cfg->threads : 256;
+    if (nt != 64 && nt != 128 && nt != 256 && nt != 512) return fail(STL_E_ARG, "threads must be 64, 128, 256 or 512");
+    if (bt->T < 1 || bt->T > (1 << 24)) return fail(STL_E_SHAPE, "T must be in [1, 2^24]");
+    int Lc = (int)((bt->T + 3) / 4 * 4);
+    const int nslots = bwd ? dp.n_slots_bwd : dp.n_slots_fwd;
+    const int ub = plan->has_until ? (int)std::min<int64_t>(plan->max_until_b, bt->T) : 0;
+    size_t arena = (size_t)nslots * Lc + scratch_floats(Lc, nt, ub);
+    size_t lds = arena * sizeof(float);
+    bool global = (cfg && cfg->global_slots) || lds > di.lds_max;
+    int persistent = cfg ? (cfg->wg_per_cu > 0) : 0;
+    int grid;
+    if (global) {
+        int per_cu = cfg && cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 4;
+        persistent = 1;
+        grid = di.cus * per_cu;
+    } else if (persistent) {
+        grid = di.cus * cfg->wg_per_cu;
+    } else {
+        grid = (int)std::min<int64_t>(bt->B, 1 << 30);
+    }
+    if (persistent && grid > bt->B) grid = (int)std::max<int64_t>(1, bt->B);
+    g->nt = nt;
+    g->grid = std::max(grid, 1);
+    g->persistent = persistent;
+    g->Lc = Lc;
+    g->global = global;
+    g->arena_floats = arena;
+    g->lds_bytes = global ? 0 : lds;
+    size_t off = 256;   // counter
+    g->off_part = off;
+    if (bwd) off += (size_t)bt->B * std::max(dp.n_masks, 1) * 2 * sizeof(float);
+    off = (off + 255) / 256 * 256;
+    g->off_arena = off;
+    if (global) off += (size_t)g->grid * arena * sizeof(float);
+    g->ws_bytes = off;
+    return STL_OK;
+}
+
+stl_status check_batch(const stl_plan* plan, const stl_batch* bt)
+{
+    if (!plan) return fail(STL_E_ARG, "plan is NULL");
+    if (!bt) return fail(STL_E_ARG, "batch is NULL");
+    if (bt->B < 0) return fail(STL_E_SHAPE, "B < 0");
+    if (bt->B > 0 && !bt->x) return fail(STL_E_ARG, "x is NULL");
+    if (bt->D != plan->D) return fail(STL_E_SHAPE, "batch D=%d but the plan was compiled for D=%d", bt->D, plan->D);
+    if (bt->T < 1) return fail(STL_E_SHAPE, "T must be >= 1");
+    return STL_OK;
+}
+
+}  // namespace
+
+extern "C" stl_status stl_workspace_size(const stl_plan* plan, const stl_batch* batch, const stl_launch* cfg,
+                                         size_t* fwd_bytes, size_t* bwd_bytes)
+{
+    stl_status s = check_batch(plan, batch);
+    if (s != STL_OK) return s;
+    Geom gf, gb, gt;
+    if ((s = geometry(plan, batch, cfg, false, false, &gf)) != STL_OK) return s;
+    if ((s = geometry(plan, batch, cfg, false, true, &gt)) != STL_OK) return s;
+    if ((s = geometry(plan, batch, cfg, true, false, &gb)) != STL_OK) return s;
+    if (fwd_bytes) *fwd_bytes = std::max(gf.ws_bytes, gt.ws_bytes);
+    if (bwd_bytes) *bwd_bytes = gb.ws_bytes;
+    return STL_OK;
+}
+
+static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* params, bool bwd, float* root,
+                      float* nodes, const float* G, float* dx, float* gparams, void* ws, size_t ws_bytes,
+                      const stl_launch* cfg, void* stream)
+{
+    stl_status s = check_batch(plan, bt);
+    if (s != STL_OK) return s;
+    if (plan->n_params > 0 && !params) return fail(STL_E_ARG, "params is NULL");
+    if (!bwd && bt->B > 0 && !root) return fail(STL_E_ARG, "root output is NULL");
+    if (bwd && bt->B > 0 && (!G || !dx)) return fail(STL_E_ARG, "grad_root / grad_x is NULL");
+    const bool trace = !bwd && nodes != nullptr;
+    Geom g;
+    if ((s = geometry(plan, bt, cfg, bwd, trace, &g)) != STL_OK) return s;
+    if (!ws || ws_bytes < g.ws_bytes)
+        return fail(STL_E_WORKSPACE, "workspace too small: need %zu bytes, got %zu", g.ws_bytes, ws_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    const DevPlan& dp = trace ? plan->dev_trace : plan->dev;
+    if (bt->B == 0) {
+        if (bwd && gparams) {
+            if (launch_reduce_params(nullptr, 0, dp, gparams, st) != hipSuccess)
+                return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
+        }
+        return STL_OK;
+    }
+    Batch b;
+    b.x = bt->x;
+    b.offsets = bt->offsets;
+    b.order = bt->order;
+    b.B = bt->B;
+    b.T = bt->T;
+    b.D = bt->D;
+    b.Lcap = g.Lc;
+    KArgs ka;
+    std::memset(&ka, 0, sizeof ka);
+    char* wsb = (char*)ws;
+    ka.params = params;
+    ka.root = root;
+    ka.nodes = nodes;
+    ka.n_total = 0;
+    ka.G = G;
+    ka.dx = dx;
+    ka.mask_part = (float*)(wsb + g.off_part);
+    ka.garena = g.global ? (float*)(wsb + g.off_arena) : nullptr;
+    ka.arena_floats = (int64_t)g.arena_floats;
+    ka.counter = (int*)wsb;
+    ka.persistent = g.persistent;
+    if (nodes) {
+        if (bt->offsets) {
+            // N_total is needed for the [n_nodes][N_total] layout: read it once
+            int64_t nt = 0;
+            if (hipMemcpyAsync(&nt, bt->offsets + bt->B, sizeof nt, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return fail(STL_E_HIP, "reading offsets failed");
+            ka.n_total = nt;
+        } else {
+            ka.n_total = bt->B * bt->T;
+        }
+    }
+    if (g.persistent && launch_zero_counter(ka.counter, st) != hipSuccess)
+        return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
+    hipError_t e = launch_exec(bwd, dp, b, ka, g.grid, g.nt, g.lds_bytes, st);
+    if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    if (bwd && gparams) {
+        e = launch_reduce_params(ka.mask_part, bt->B, dp, gparams, st);
+        if (e != hipSuccess) return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(e));
+    }
+    return STL_OK;
+}
+
+extern "C" stl_status stl_forward(const stl_plan* plan, const stl_batch* batch, const float* d_params, float* d_root,
+                                  float* d_node_traces, void* d_ws, size_t ws_bytes, const stl_launch* cfg,
+                                  void* stream)
+{
+    return run(plan, batch, d_params, false, d_root, d_node_traces, nullptr, nullptr, nullptr, d_ws, ws_bytes, cfg,
+               stream);
+}
+
+extern "C" stl_status stl_backward(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                                   const float* d_grad_root, float* d_grad_x, float* d_grad_params, void* d_ws,
+                                   size_t ws_bytes, const stl_launch* cfg, void* stream)
+{
+    return run(plan, batch, d_params, true, nullptr, nullptr, d_grad_root, d_grad_x, d_grad_params, d_ws, ws_bytes,
+               cfg, stream);
+}
+
+// ------------------------------------------------------------------ autotuner
+
+namespace {
+
+struct TuneKey {
+    const stl_plan* plan;
+    int64_t B, T;
+    int D;
+    bool ragged;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(plan, B, T, D, ragged) < std::tie(o.plan, o.B, o.T, o.D, o.ragged);
+    }
+};
+std::map<TuneKey, std::pair<stl_launch, float>> g_tune;
+
+std::string plan_signature(const stl_plan* p, const stl_batch* bt)
+{
+    // stable text key for the on-disk cache: program shape plus batch shape
+    unsigned long long h = 1469598103934665603ull;
+    const unsigned char* c = (const unsigned char*)&p->dev;
+    for (size_t i = 0; i < sizeof(DevPlan); ++i) h = (h ^ c[i]) * 1099511628211ull;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%016llx_B%lld_T%lld_D%d_%s", h, (long long)bt->B, (long long)bt->T, bt->D,
+             bt->offsets ? "ragged" : "dense");
+    return buf;
+}
+
+bool cache_lookup(const std::string& key, stl_launch* out, float* ms)
+{
+    const char* path = std::getenv("STLMI_TUNE_CACHE");
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[200];
+        int a, b2, c;
+        float m;
+        // one JSON object per line: {"key": "...", "threads": a, "wg_per_cu": b, "global_slots": c, "ms": m}
+        if (std::sscanf(line, " {\"key\": \"%199[^\"]\", \"threads\": %d, \"wg_per_cu\": %d, \"global_slots\": %d, \"ms\": %f",
+                        k, &a, &b2, &c, &m) == 5 &&
+            key == k) {
+            out->threads = a;
+            out->wg_per_cu = b2;
+            out->global_slots = c;
+            out->reserved = 0;
+            *ms = m;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const std::string& key, const stl_launch& l, float ms)
+{
+    const char* path = std::getenv("STLMI_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"wg_per_cu\": %d, \"global_slots\": %d, \"ms\": %.6f}\n",
+                 key.c_str(), l.threads, l.wg_per_cu, l.global_slots, ms);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" stl_status stl_autotune(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                                   float* d_root, const float* d_grad_root, float* d_grad_x, float* d_grad_params,
+                                   void* d_ws, size_t ws_bytes, void* stream, stl_launch* best, float* best_ms)
+{
+    stl_status s = check_batch(plan, batch);
+    if (s != STL_OK) return s;
+    if (!best) return fail(STL_E_ARG, "best is NULL");
+    TuneKey key{plan, batch->B, batch->T, batch->D, batch->offsets != nullptr};
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *best = it->second.first;
+            if (best_ms) *best_ms = it->second.second;
+            return STL_OK;
+        }
+    }
+    const std::string sig = plan_signature(plan, batch);
+    float cms = 0;
+    if (cache_lookup(sig, best, &cms)) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tune[key] = {*best, cms};
+        if (best_ms) *best_ms = cms;
+        return STL_OK;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<stl_launch> cands;
+    for (int nt : {128, 256, 512})
+        for (int wpc : {0, 1, 2, 4, 8})
+            cands.push_back(stl_launch{nt, wpc, 0, 0});
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(STL_E_HIP, "hipEventCreate failed");
+    float bestt = 1e30f;
+    stl_launch bl{256, 0, 0, 0};
+    bool any = false;
+    for (const stl_launch& c : cands) {
+        size_t fw = 0, bw = 0;
+        if (stl_workspace_size(plan, batch, &c, &fw, &bw) != STL_OK) continue;
+        if (std::max(fw, bw) > ws_bytes) continue;
+        Geom g;
+        if (geometry(plan, batch, &c, true, false, &g) != STL_OK) continue;
+        if (g.global && !(c.global_slots)) {
+            // candidates that do not fit LDS all degrade to the same global layout
+        }
+        bool ok = true;
+        float tsum = 0;
+        for (int rep = 0; rep < 3 && ok; ++rep) {
+            hipEventRecord(e0, st);
+            ok = stl_forward(plan, batch, d_params, d_root, nullptr, d_ws, ws_bytes, &c, stream) == STL_OK &&
+                 stl_backward(plan, batch, d_params, d_grad_root, d_grad_x, d_grad_params, d_ws, ws_bytes, &c,
+                              stream) == STL_OK;
+            hipEventRecord(e1, st);
+            hipEventSynchronize(e1);
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) tsum += ms;   // first rep is a warm-up
+        }
+        if (!ok) continue;
+        any = true;
+        float t = tsum / 2;
+        if (t < bestt) { bestt = t; bl = c; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!any) return fail(STL_E_WORKSPACE, "no launch candidate fits the workspace");
+    *best = bl;
+    if (best_ms) *best_ms = bestt;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tune[key] = {bl, bestt};
+    }
+    cache_store(sig, bl, bestt);
+    return STL_OK;
+}
+
+// ------------------------------------------------------------------ graphs
+
+struct stl_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" stl_status stl_graph_capture(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                                        float* d_root, const float* d_grad_root, float* d_grad_x,
+                                        float* d_grad_params, void* d_ws, size_t ws_bytes, const stl_launch* cfg,
+                                        void* stream, stl_graph** out)
+{
+    if (!out) return fail(STL_E_ARG, "out is NULL");
+    *out = nullptr;
+    stl_status s = check_batch(plan, batch);
+    if (s != STL_OK) return s;
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(STL_E_HIP, "stream create failed");
+    // order the capture after the caller's pending work
+    hipEvent_t ev;
+    hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    hipEventRecord(ev, (hipStream_t)stream);
+    hipStreamWaitEvent(cs, ev, 0);
+    hipStreamSynchronize(cs);
+    hipEventDestroy(ev);
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        hipStreamDestroy(cs);
+        return fail(STL_E_HIP, "hipStreamBeginCapture failed");
+    }
+    stl_status s1 = stl_forward(plan, batch, d_params, d_root, nullptr, d_ws, ws_bytes, cfg, cs);
+    stl_status s2 = s1 == STL_OK ? stl_backward(plan, batch, d_params, d_grad_root, d_grad_x, d_grad_params, d_ws,
+                                                ws_bytes, cfg, cs)
+                                 : s1;
+    std::string err = g_err;
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(cs, &graph);
+    hipStreamDestroy(cs);
+    if (s2 != STL_OK) {
+        if (graph) hipGraphDestroy(graph);
+        g_err = err;
+        return s2;
+    }
+    if (ec != hipSuccess || !graph) return fail(STL_E_HIP, "hipStreamEndCapture failed");
+    stl_graph* gr = new (std::nothrow) stl_graph();
+    if (!gr) { hipGraphDestroy(graph); return fail(STL_E_ARG, "out of host memory"); }
+    gr->graph = graph;
+    if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(graph);
+        delete gr;
+        return fail(STL_E_HIP, "hipGraphInstantiate failed");
+    }
+    *out = gr;
+    return STL_OK;
+}
+
+extern "C" stl_status stl_graph_launch(stl_graph* graph, void* stream)
+{
+    if (!graph) return fail(STL_E_ARG, "graph is NULL");
+    hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(STL_E_HIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
+    return STL_OK;
+}
+
+extern "C" stl_status stl_graph_destroy(stl_graph* graph)
+{
+    if (!graph) return STL_OK;
+    if (graph->exec) hipGraphExecDestroy(graph->exec);
+    if (graph->graph) hipGraphDestroy(graph->graph);
+    delete graph;
+    return STL_OK;
+}

@@ -1,0 +1,1135 @@
+// HIP kernels for STL robustness traces on gfx950 (MI355X).
+//
+// One work-group owns one trajectory at a time (a persistent grid pulls
+// trajectory indices from a counter).  Every node trace of the formula lives
+// in an on-chip slot (LDS, or a per-work-group region of the workspace when
+// the trajectory is too long for LDS) and the plan's instructions run in
+// topological order, each one a work-group-cooperative parallel pass over the
+// timesteps.  Only x is read and only the root trace (forward) or dx and the
+// mask-bound partial sums (backward) are written to HBM.
+//
+// Operators (arXiv 2501.04194):
+//   windows over [a,b] (Sec. IV-B) are evaluated by van Herk / Gil-Werman
+//   block decomposition: blocks of K = b-a+1 positions, block-prefix and
+//   block-suffix reductions, and every window is suffix(start) (+) prefix(end)
+//   of two adjacent blocks.  The masked (T+K) x T array of the paper is never
+//   formed.  Unbounded windows are suffix scans.
+//   Smooth windows (Sec. III-C) use the same decomposition on "scaled pairs"
+//   (s, r) = s * 2^r, so sums of exp(beta u) never overflow whatever the
+//   signal range; beta is folded into base-2 exponents.
+//   The smooth time mask (Sec. VI) splits into a constant-weight core (a van
+//   Herk window) plus two sigmoid bands summed term by term.
+//   Until (Sec. IV-C) runs the running min over the inner index once per
+//   output (no 3-D array): hard with compare-selects, smooth with running
+//   scaled sums; its adjoint uses checkpointed recomputation.
+//   Hard min/max carry the element index so ties resolve to the lowest time
+//   index, matching the gradient routing rule.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+#include "stl_plan.h"
+
+namespace stlmi {
+
+#define DEV static __device__ __forceinline__
+
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr int MAX_NT = 512;
+constexpr int PAD_NEUTRAL = 0, PAD_LAST = 1, PAD_CONST = 2;
+
+// ------------------------------------------------------------------ types
+
+// scaled pair: value = s * 2^r
+struct SP {
+    float s;
+    int r;
+};
+constexpr int SP_NEG = -(1 << 29);
+
+DEV SP sp_zero() { return SP{0.f, SP_NEG}; }
+
+DEV SP sp_leaf(float z)  // 2^z
+{
+    float c = ceilf(fminf(fmaxf(z, -1e9f), 1e9f));
+    return SP{exp2f(z - c), (int)c};
+}
+
+DEV SP sp_add(SP a, SP b)
+{
+    int m = max(a.r, b.r);
+    return SP{ldexpf(a.s, a.r - m) + ldexpf(b.s, b.r - m), m};
+}
+
+DEV float sp_log2(SP a) { return (float)a.r + log2f(a.s); }
+
+DEV int clampe(long long e) { return (int)(e < -100000 ? -100000 : (e > 100000 ? 100000 : e)); }
+
+// value of a * 2^z as a float (exact exponent bookkeeping, no intermediate overflow)
+DEV float sp_times_exp2(SP a, float z)
+{
+    float c = ceilf(fminf(fmaxf(z, -1e9f), 1e9f));
+    return ldexpf(a.s * exp2f(z - c), clampe((long long)a.r + (long long)c));
+}
+
+// value with index: hard max with ties to the lowest index
+struct VI {
+    float v;
+    int i;
+};
+
+DEV VI vi_best(VI a, VI b)
+{
+    return (b.v > a.v || (b.v == a.v && b.i < a.i)) ? b : a;
+}
+
+struct OpSP {
+    __device__ __forceinline__ SP operator()(SP a, SP b) const { return sp_add(a, b); }
+};
+struct OpVI {
+    __device__ __forceinline__ VI operator()(VI a, VI b) const { return vi_best(a, b); }
+};
+struct OpD {
+    __device__ __forceinline__ double operator()(double a, double b) const { return a + b; }
+};
+struct OpF {
+    __device__ __forceinline__ float operator()(float a, float b) const { return a + b; }
+};
+
+// ------------------------------------------------------------------ scans
+
+struct Shared {
+    double scan[MAX_NT];
+    int flag[MAX_NT];
+    int ints[8];
+    float f[8];
+};
+
+// In-place inclusive scan of x[0..n) within segments.  Forward scans have
+// segment heads at positions p % K == 0; reverse scans at p % K == K-1 and
+// at n-1.  K <= 0 means one segment.  Each thread scans a contiguous chunk
+// sequentially; chunk aggregates are combined with a segmented
+// Hillis-Steele pass; the carry is then applied to each chunk's head part.
+// Must be called by every thread of the work-group.
+template <class T, class Op>
+DEV void seg_scan(T* x, int n, int K, bool rev, T ident, Op op, Shared& sh)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    T* shv = reinterpret_cast<T*>(sh.scan);
+    const int C = (n + nt - 1) / nt;
+    const int c0 = min(n, tid * C), c1 = min(n, c0 + C);
+    T acc = ident;
+    int head = 0;
+    if (c0 < c1) {
+        if (!rev) {
+            int rem = K > 0 ? c0 % K : c0;
+            for (int p = c0; p < c1; ++p) {
+                bool h = K > 0 ? (rem == 0) : (p == 0);
+                T v = x[p];
+                acc = h ? v : op(acc, v);
+                head |= h;
+                x[p] = acc;
+                if (K > 0 && ++rem == K) rem = 0;
+            }
+        } else {
+            int rem = K > 0 ? (c1 - 1) % K : 0;
+            for (int p = c1 - 1; p >= c0; --p) {
+                bool h = (p == n - 1) || (K > 0 && rem == K - 1);
+                T v = x[p];
+                acc = h ? v : op(v, acc);
+                head |= h;
+                x[p] = acc;
+                if (K > 0) rem = rem == 0 ? K - 1 : rem - 1;
+            }
+        }
+    }
+    shv[tid] = acc;
+    sh.flag[tid] = head;
+    __syncthreads();
+    for (int d = 1; d < nt; d <<= 1) {
+        T a = shv[tid];
+        int f = sh.flag[tid];
+        int src = rev ? tid + d : tid - d;
+        if (!f && (rev ? src < nt : src >= 0)) {
+            T b = shv[src];
+            a = rev ? op(a, b) : op(b, a);
+            f = sh.flag[src];
+        }
+        __syncthreads();
+        shv[tid] = a;
+        sh.flag[tid] = f;
+        __syncthreads();
+    }
+    const int nb = rev ? tid + 1 : tid - 1;
+    if (c0 < c1 && nb >= 0 && nb < nt) {
+        T carry = shv[nb];
+        if (!rev) {
+            int rem = K > 0 ? c0 % K : c0;
+            for (int p = c0; p < c1; ++p) {
+                bool h = K > 0 ? (rem == 0) : (p == 0);
+                if (h) break;
+                x[p] = op(carry, x[p]);
+                if (K > 0 && ++rem == K) rem = 0;
+            }
+        } else {
+            int rem = K > 0 ? (c1 - 1) % K : 0;
+            for (int p = c1 - 1; p >= c0; --p) {
+                bool h = (p == n - 1) || (K > 0 && rem == K - 1);
+                if (h) break;
+                x[p] = op(x[p], carry);
+                if (K > 0) rem = rem == 0 ? K - 1 : rem - 1;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// deterministic work-group sum of one float per thread
+DEV float wg_sum(float v, Shared& sh)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    float* f = reinterpret_cast<float*>(sh.scan);
+    f[tid] = v;
+    __syncthreads();
+    for (int s = nt >> 1; s > 0; s >>= 1) {
+        if (tid < s) f[tid] += f[tid + s];
+        __syncthreads();
+    }
+    float r = f[0];
+    __syncthreads();
+    return r;
+}
+
+DEV int lower_bound_i(const int* a, int n, int key)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ context
+
+struct Batch {
+    const float* x;
+    const int64_t* offsets;
+    const int32_t* order;
+    int64_t B;
+    int64_t T;
+    int32_t D;
+    int32_t Lcap;      // slot capacity (floats per slot)
+};
+
+struct Env {
+    const DevPlan* P;
+    const float* x;    // this trajectory, [L, D]
+    const float* params;
+    int L, Lc, D;
+    float* arena;      // slots
+    float* scr;        // op scratch (SCR_FLOATS(Lc) floats)
+    Shared* sh;
+};
+
+// scratch layout (floats): everything an operator needs, in units of Lc
+#define SCR_UNITS 16
+DEV float* S(const Env& e, int unit) { return e.scr + (size_t)unit * e.Lc; }
+
+DEV float* slot(const Env& e, int s) { return e.arena + (size_t)s * e.Lc; }
+
+DEV float pbeta(const Env& e, const Instr& I) { return I.beta >= 0 ? e.params[I.beta] : 1.f; }
+
+// ------------------------------------------------------------------ pointwise ops
+
+DEV void op_pred_fwd(const Env& e, const Instr& I, float* out)
+{
+    const float* cf = e.P->coef + I.coef;
+    const int D = e.D;
+    if (I.kind == K_LIN) {
+        const float c = cf[0];
+        for (int t = threadIdx.x; t < e.L; t += blockDim.x) {
+            const float* xr = e.x + (size_t)t * D;
+            float s = 0.f;
+            for (int d = 0; d < D; ++d) s = fmaf(cf[1 + d], xr[d], s);
+            out[t] = s - c;
+        }
+    } else {
+        const int m = (int)cf[0];
+        const float r = cf[1], sg = cf[2];
+        for (int t = threadIdx.x; t < e.L; t += blockDim.x) {
+            const float* xr = e.x + (size_t)t * D;
+            float q = 0.f;
+            for (int i = 0; i < m; ++i) {
+                float z = -cf[3 + i];
+                for (int d = 0; d < D; ++d) z = fmaf(cf[7 + i * D + d], xr[d], z);
+                q = fmaf(z, z, q);
+            }
+            out[t] = sg * (sqrtf(q) - r);
+        }
+    }
+}
+
+// d/dx of all predicates: dx[t, d] = sum_p dmu_p/dx_d * g_p[t]
+DEV void op_dx(const Env& e, float* dx)
+{
+    const DevPlan& P = *e.P;
+    const int D = e.D;
+    for (int t = threadIdx.x; t < e.L; t += blockDim.x) {
+        const float* xr = e.x + (size_t)t * D;
+        float acc[MAX_D];
+        for (int d = 0; d < D; ++d) acc[d] = 0.f;
+        for (int p = 0; p < P.n_pred; ++p) {
+            const Instr& I = P.ins[P.pred_ins[p]];
+            const float g = slot(e, I.g_out)[t];
+            const float* cf = P.coef + I.coef;
+            if (I.kind == K_LIN) {
+                for (int d = 0; d < D; ++d) acc[d] = fmaf(cf[1 + d], g, acc[d]);
+            } else {
+                const int m = (int)cf[0];
+                const float sg = cf[2];
+                float z[4];
+                float q = 0.f;
+                for (int i = 0; i < m; ++i) {
+                    z[i] = -cf[3 + i];
+                    for (int d = 0; d < D; ++d) z[i] = fmaf(cf[7 + i * D + d], xr[d], z[i]);
+                    q = fmaf(z[i], z[i], q);
+                }
+                if (q > 0.f) {
+                    const float k = sg * g / sqrtf(q);
+                    for (int d = 0; d < D; ++d) {
+                        float s = 0.f;
+                        for (int i = 0; i < m; ++i) s = fmaf(cf[7 + i * D + d], z[i], s);
+                        acc[d] = fmaf(k, s, acc[d]);
+                    }
+                }
+            }
+        }
+        for (int d = 0; d < D; ++d) dx[(size_t)t * D + d] = acc[d];
+    }
+}
+
+DEV void op_nary_fwd(const Env& e, const Instr& I, const int8_t* ch, float* out)
+{
+    const float sg = (I.flags & F_MIN) ? -1.f : 1.f;
+    const int n = I.nch;
+    const float* c[MAX_NCH];
+    for (int k = 0; k < MAX_NCH; ++k) c[k] = slot(e, ch[k < n ? k : 0]);
+    if (!(I.flags & F_SMOOTH)) {
+        for (int t = threadIdx.x; t < e.L; t += blockDim.x) {
+            float best = sg * c[0][t];
+            for (int k = 1; k < n; ++k) {
+                float v = sg * c[k][t];
+                if (v > best) best = v;
+            }
+            out[t] = sg * best;
+        }
+    } else {
+        const float bl = pbeta(e, I) * LOG2E;
+        for (int t = threadIdx.x; t < e.L; t += blockDim.x) {
+            float v[MAX_NCH];
+            float m = -INFINITY;
+            for (int k = 0; k < n; ++k) { v[k] = sg * c[k][t]; m = fmaxf(m, v[k]); }
+            float s = 0.f;
+            for (int k = 0; k < n; ++k) s += exp2f((v[k] - m) * bl);
+            out[t] = sg * (m + log2f(s) / bl);
+        }
+    }
+}
+
+DEV void op_nary_bwd(const Env& e, const Instr& I)
+{
+    const float sg = (I.flags & F_MIN) ? -1.f : 1.f;
+    const int n = I.nch;
+    const float* g = slot(e, I.g_out);
+    const float* out = slot(e, I.b_out);
+    const float* c[MAX_NCH];
+    float* gc[MAX_NCH];
+    for (int k = 0; k < MAX_NCH; ++k) {
+        c[k] = slot(e, I.b_ch[k < n ? k : 0]);
+        gc[k] = slot(e, I.g_ch[k < n ? k : 0]);
+    }
+    const bool smooth = I.flags & F_SMOOTH;
+    const float bl = pbeta(e, I) * LOG2E;
+    for (int t = threadIdx.x; t < e.L; t += blockDim.x) {
+        const float gt = g[t];
+        if (!smooth) {
+            int kb = 0;
+            float best = sg * c[0][t];
+            for (int k = 1; k < n; ++k) {
+                float v = sg * c[k][t];
+                if (v > best) { best = v; kb = k; }
+            }
+            for (int k = 0; k < n; ++k) gc[k][t] = (k == kb) ? gt : 0.f;
+        } else {
+            const float o = sg * out[t];
+            for (int k = 0; k < n; ++k) gc[k][t] = gt * exp2f((sg * c[k][t] - o) * bl);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ hard windows
+
+// Hard max (sg=+1) / min (sg=-1) of u over [t+klo, t+khi] (khi<0: to the end)
+// with the pad policy.  Writes out[t]; if jstar != NULL also the index of the
+// selected element (L when none / a constant pad).
+DEV void win_hard(const Env& e, const float* u, float* out, int* jstar, float sg, int klo, int khi,
+                  int pad, float padv, VI* Pre, VI* Suf)
+{
+    const int L = e.L;
+    const bool unb = khi < 0;
+    const int n = L - klo;
+    const int K = unb ? n : khi - klo + 1;
+    if (n > 0) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            VI v{sg * u[klo + i], klo + i};
+            Suf[i] = v;
+            if (!unb) Pre[i] = v;
+        }
+        __syncthreads();
+        const VI id{-INFINITY, 0x7fffffff};
+        seg_scan(Suf, n, unb ? 0 : K, true, id, OpVI(), *e.sh);
+        if (!unb) seg_scan(Pre, n, K, false, id, OpVI(), *e.sh);
+    }
+    const float rho_pad = e.P->rho_pad;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        VI r{-INFINITY, L};
+        bool any = false;
+        if (t < n) {
+            int e2 = min(t + K - 1, n - 1);
+            r = (unb || t / K == e2 / K) ? Suf[t] : vi_best(Suf[t], Pre[e2]);
+            any = true;
+        }
+        if (!unb && pad != PAD_NEUTRAL && t + khi > L - 1) {
+            if (pad == PAD_LAST) {
+                if (!any) r = VI{sg * u[L - 1], L - 1};
+            } else {
+                VI pv{sg * padv, L};
+                r = any ? vi_best(r, pv) : pv;
+            }
+            any = true;
+        }
+        out[t] = any ? sg * r.v : -sg * rho_pad;
+        if (jstar) jstar[t] = any ? r.i : L;
+    }
+    __syncthreads();
+}
+
+// adjoint of a hard window: gu[j] = sum of g[t] over the t whose selected
+// index is j.  The selected index is non-decreasing in t, so each j owns a
+// contiguous run of t, found by binary search; the run sum comes from an
+// fp64 prefix sum of g (exact to fp32 rounding, deterministic).
+DEV void win_hard_adj(const Env& e, const float* g, float* gu, const int* jstar, double* P)
+{
+    const int L = e.L;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) P[t + 1] = jstar[t] < L ? (double)g[t] : 0.0;
+    if (threadIdx.x == 0) P[0] = 0.0;
+    __syncthreads();
+    seg_scan(P + 1, L, 0, false, 0.0, OpD(), *e.sh);
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        int lo = lower_bound_i(jstar, L, j);
+        int hi = lower_bound_i(jstar, L, j + 1);
+        gu[j] = (float)(P[hi] - P[lo]);
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ smooth windows
+
+// Smooth max (sg=+1) / min of u over the integer window [t+klo, t+khi]
+// (khi<0: to the end), scaled by a constant weight 2^lw, as scaled pairs:
+// acc[t] = sum_j w 2^{z_j}, z = sg*beta*log2(e)*u.  Pads add their copies.
+// any[t] (byte flag) tells whether the window is non-empty.
+DEV void win_smooth_sum(const Env& e, const float* u, SP* acc, float sgz, int klo, int khi, int pad,
+                        float padv, SP* Pre, SP* Suf)
+{
+    const int L = e.L;
+    const bool unb = khi < 0;
+    const int n = L - klo;
+    const int K = unb ? n : khi - klo + 1;
+    if (n > 0) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            SP v = sp_leaf(sgz * u[klo + i]);
+            Suf[i] = v;
+            if (!unb) Pre[i] = v;
+        }
+        __syncthreads();
+        seg_scan(Suf, n, unb ? 0 : K, true, sp_zero(), OpSP(), *e.sh);
+        if (!unb) seg_scan(Pre, n, K, false, sp_zero(), OpSP(), *e.sh);
+    }
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        SP a = sp_zero();
+        if (t < n) {
+            int e2 = min(t + K - 1, n - 1);
+            a = (unb || t / K == e2 / K) ? Suf[t] : sp_add(Suf[t], Pre[e2]);
+        }
+        if (!unb && pad != PAD_NEUTRAL && t + khi > L - 1) {
+            int np = min(K, t + khi - (L - 1));
+            SP pv = sp_leaf(pad == PAD_LAST ? sgz * u[L - 1] : sgz * padv);
+            pv.s *= (float)np;
+            a = sp_add(a, pv);
+        }
+        acc[t] = a;
+    }
+    __syncthreads();
+}
+
+// Transposed window sum for adjoints: for each position j,
+// out[j] = sum over t in [j-khi, j-klo] (clipped to [0, nt_valid)) of h[t].
+// h (scaled pairs) is consumed (overwritten by the scans).
+DEV void win_smooth_adj_sum(const Env& e, SP* h, SP* hPre, SP* res, int klo, int khi, int n_valid)
+{
+    const int L = e.L;
+    const bool unb = khi < 0;
+    const int K = unb ? L : khi - klo + 1;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) hPre[t] = h[t];
+    __syncthreads();
+    seg_scan(hPre, L, unb ? 0 : K, false, sp_zero(), OpSP(), *e.sh);
+    if (!unb) seg_scan(h, L, K, true, sp_zero(), OpSP(), *e.sh);
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        SP a = sp_zero();
+        int en = min(j - klo, n_valid - 1);
+        int st = unb ? 0 : max(0, j - khi);
+        if (st <= en) {
+            if (unb) a = hPre[en];
+            else if (st / K == en / K) a = (st % K == 0) ? hPre[en] : h[st];
+            else a = sp_add(h[st], hPre[en]);
+        }
+        res[j] = a;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ masks
+
+struct MaskInfo {
+    int klo, khi;      // support {w > 0}; khi = L-1 .. for unbounded
+    int clo, chi;      // constant core (clo > chi: none)
+    float wc;          // core weight
+    bool any;
+};
+
+// weights w_k = max(sig(c(k-a)) - sig(c(k-b)) - eps, 0) for k in [0, L),
+// using sig(x) - sig(y) = sig(x) sig(-y) (1 - exp(-(x-y))) (no cancellation);
+// optionally d w/da and d w/db.  Finds the support and the core where both
+// sigmoid derivatives are below 2^-24 (|c(k-a)|, |c(k-b)| > 17), over which
+// w is constant to fp32 rounding.
+DEV MaskInfo mask_weights(const Env& e, const Instr& I, float* w, float* dwa, float* dwb)
+{
+    const float* pm = e.params + I.mask;
+    const float a = pm[0], b = pm[1], c = pm[2], eps = pm[3];
+    const bool unb = I.flags & F_MASK_UNB;
+    const int L = e.L;
+    const float gap = unb ? INFINITY : c * (b - a);
+    const float band = 1.f - expf(-gap);
+    int* si = e.sh->ints;
+    if (threadIdx.x == 0) { si[0] = L; si[1] = -1; }
+    __syncthreads();
+    int lo = L, hi = -1;
+    for (int k = threadIdx.x; k < L; k += blockDim.x) {
+        const float x1 = c * ((float)k - a);
+        const float s1 = 1.f / (1.f + expf(-x1));
+        float wk, s2 = 0.f;
+        if (unb) {
+            wk = s1 - eps;
+        } else {
+            const float y1 = c * ((float)k - b);
+            s2 = 1.f / (1.f + expf(-y1));
+            const float sny = 1.f / (1.f + expf(y1));
+            wk = s1 * sny * band - eps;
+        }
+        wk = wk > 0.f ? wk : 0.f;
+        w[k] = wk;
+        if (dwa) {
+            dwa[k] = wk > 0.f ? -c * s1 * (1.f - s1) : 0.f;
+            dwb[k] = (wk > 0.f && !unb) ? c * s2 * (1.f - s2) : 0.f;
+        }
+        if (wk > 0.f) { lo = min(lo, k); hi = max(hi, k); }
+    }
+    atomicMin(&si[0], lo);
+    atomicMax(&si[1], hi);
+    __syncthreads();
+    MaskInfo mi;
+    mi.klo = si[0];
+    mi.khi = si[1];
+    mi.any = mi.klo <= mi.khi;
+    if (c > 0.f && mi.any) {
+        mi.clo = max(mi.klo, (int)fminf(ceilf(a + 17.f / c), 2e9f));
+        mi.chi = unb ? mi.khi : min(mi.khi, (int)fmaxf(floorf(b - 17.f / c), -2e9f));
+    } else {
+        mi.clo = 1;
+        mi.chi = 0;
+    }
+    if (mi.clo > mi.chi) { mi.clo = 1; mi.chi = 0; mi.wc = 0.f; }
+    else mi.wc = w[(mi.clo + mi.chi) / 2];
+    __syncthreads();
+    return mi;
+}
+
+// ------------------------------------------------------------------ until
+
+// Hard Until, one thread per output t: running min of phi over [t, t+i],
+// max over i in [a, b] of min(running min, psi_{t+i}); phi wins ties.
+DEV void until_hard(const Env& e, const Instr& I, const float* phi, const float* psi, float* out,
+                    const float* g, float* gphi, float* gpsi)
+{
+    const int L = e.L, a = I.a, b = I.b;
+    const float rho_pad = e.P->rho_pad;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
+        if (a > imax) {
+            if (out) out[t] = -rho_pad;
+            continue;
+        }
+        float R = phi[t], best = -INFINITY;
+        int kR = t, tgt = -1;
+        bool tphi = false;
+        for (int i = 0; i <= imax; ++i) {
+            const float f = phi[t + i];
+            if (f < R) { R = f; kR = t + i; }
+            if (i >= a) {
+                const float p = psi[t + i];
+                const bool pw = R <= p;
+                const float v = pw ? R : p;
+                if (tgt < 0 || v > best) { best = v; tphi = pw; tgt = pw ? kR : t + i; }
+            }
+        }
+        if (out) out[t] = best;
+        if (g) {
+            const float gt = g[t];
+            if (gt != 0.f) atomicAdd(tphi ? &gphi[tgt] : &gpsi[tgt], gt);
+        }
+    }
+}
+
+// Smooth Until forward, one thread per output t:
+//   P_i = sum_{k<=i} 2^{-z_phi(t+k)}   (running scaled sum: smooth min of phi)
+//   Y_i = 1 / (P_i + 2^{-z_psi(t+i)})  (= exp(beta * smin(R_i, psi_{t+i})))
+//   out = log2(sum_{i in [a,b]} Y_i) / (beta log2 e)
+// Ephi / Epsi hold the leaves 2^{-z}.  Returns Z (scaled) through Zout when given.
+DEV void until_smooth_fwd(const Env& e, const Instr& I, const SP* Ephi, const SP* Epsi, float* out,
+                          float bl)
+{
+    const int L = e.L, a = I.a, b = I.b;
+    const float rho_pad = e.P->rho_pad;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
+        if (a > imax) { out[t] = -rho_pad; continue; }
+        SP P = sp_zero(), Z = sp_zero();
+        for (int i = 0; i <= imax; ++i) {
+            P = sp_add(P, Ephi[t + i]);
+            if (i >= a) {
+                SP Dn = sp_add(P, Epsi[t + i]);
+                Z = sp_add(Z, SP{1.f / Dn.s, -Dn.r});
+            }
+        }
+        out[t] = sp_log2(Z) / bl;
+    }
+}
+
+constexpr int UCK = 16;   // checkpoint spacing of the smooth Until adjoint
+
+// Smooth Until adjoint (checkpointed reverse sweep per output t):
+//   d out / d psi_{t+i} = Y_i^2 Q_i / Z,  Q_i = 2^{-z_psi(t+i)}
+//   d out / d phi_{t+k} = e_k / Z * sum_{i >= max(k,a)} Y_i^2,  e_k = 2^{-z_phi(t+k)}
+// Pass 1 recomputes Z and stores P every UCK steps; pass 2 walks the
+// checkpoint blocks backward, recomputing P inside each block, and adds the
+// contributions to the adjoint slots with LDS atomics.
+DEV void until_smooth_adj(const Env& e, const Instr& I, const SP* Ephi, const SP* Epsi, const float* g,
+                          float* gphi, float* gpsi, SP* ck, int ncks)
+{
+    const int L = e.L, a = I.a, b = I.b;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
+        const float gt = g[t];
+        if (a > imax || gt == 0.f) continue;
+        SP* myck = ck + (size_t)threadIdx.x * ncks;
+        SP P = sp_zero(), Z = sp_zero();
+        for (int i = 0; i <= imax; ++i) {
+            if (i % UCK == 0) myck[i / UCK] = P;
+            P = sp_add(P, Ephi[t + i]);
+            if (i >= a) {
+                SP Dn = sp_add(P, Epsi[t + i]);
+                Z = sp_add(Z, SP{1.f / Dn.s, -Dn.r});
+            }
+        }
+        const float gz = gt / Z.s;          // G / Z = gz * 2^{-Z.r}
+        SP A = sp_zero();                   // suffix sum of Y_i^2
+        for (int blk = imax / UCK; blk >= 0; --blk) {
+            const int i0 = blk * UCK, i1 = min(imax, i0 + UCK - 1);
+            SP Ps[UCK];
+            SP Pc = myck[blk];
+#pragma unroll
+            for (int q = 0; q < UCK; ++q) {
+                if (i0 + q <= i1) Pc = sp_add(Pc, Ephi[t + i0 + q]);
+                Ps[q] = Pc;
+            }
+#pragma unroll
+            for (int q = UCK - 1; q >= 0; --q) {
+                const int i = i0 + q;
+                if (i > i1) continue;
+                if (i >= a) {
+                    const SP Q = Epsi[t + i];
+                    const SP Dn = sp_add(Ps[q], Q);
+                    const float y = 1.f / Dn.s;       // Y = y * 2^{-Dn.r}
+                    const SP Y2{y * y, -2 * Dn.r};
+                    A = sp_add(A, Y2);
+                    // psi: gz * Y^2 * Q  (exponent -Z.r - 2 Dn.r + Q.r)
+                    atomicAdd(&gpsi[t + i], ldexpf(gz * Y2.s * Q.s, clampe((long long)Y2.r + Q.r - Z.r)));
+                }
+                const SP E = Ephi[t + i];
+                atomicAdd(&gphi[t + i], ldexpf(gz * A.s * E.s, clampe((long long)A.r + E.r - Z.r)));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ instructions
+
+DEV bool is_smooth(const Instr& I) { return I.flags & F_SMOOTH; }
+
+// Run one instruction forward with the given slot map (fwd or bwd).
+DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
+{
+    const int o = bwdmap ? I.b_out : I.f_out;
+    const int i0 = bwdmap ? I.b_in0 : I.f_in0;
+    const int i1 = bwdmap ? I.b_in1 : I.f_in1;
+    float* out = slot(e, o);
+    const int L = e.L;
+    const float sg = (I.flags & F_MIN) ? -1.f : 1.f;
+    switch (I.kind) {
+    case K_TRUE:
+        for (int t = threadIdx.x; t < L; t += blockDim.x) out[t] = e.P->rho_max;
+        break;
+    case K_LIN:
+    case K_NORM:
+        op_pred_fwd(e, I, out);
+        break;
+    case K_NOT: {
+        const float* u = slot(e, i0);
+        for (int t = threadIdx.x; t < L; t += blockDim.x) out[t] = -u[t];
+        break;
+    }
+    case K_NARY:
+        op_nary_fwd(e, I, bwdmap ? I.b_ch : I.f_ch, out);
+        break;
+    case K_WIN: {
+        const float* u = slot(e, i0);
+        const int khi = (I.flags & F_UNB) ? -1 : I.b;
+        const float padv = e.P->coef[I.coef];
+        if (!is_smooth(I)) {
+            win_hard(e, u, out, nullptr, sg, I.a, khi, I.pad, padv, (VI*)S(e, 0), (VI*)S(e, 2));
+        } else {
+            const float bl = pbeta(e, I) * LOG2E;
+            SP* acc = (SP*)S(e, 4);
+            win_smooth_sum(e, u, acc, sg * bl, I.a, khi, I.pad, padv, (SP*)S(e, 0), (SP*)S(e, 2));
+            const bool unb = khi < 0;
+            for (int t = threadIdx.x; t < L; t += blockDim.x) {
+                const bool any = (t + I.a <= L - 1) || (!unb && I.pad != PAD_NEUTRAL && t + khi > L - 1);
+                out[t] = any ? sg * sp_log2(acc[t]) / bl : -sg * e.P->rho_pad;
+            }
+        }
+        break;
+    }
+    case K_MASK: {
+        const float* u = slot(e, i0);
+        float* w = S(e, 6);
+        MaskInfo mi = mask_weights(e, I, w, nullptr, nullptr);
+        if (!is_smooth(I)) {
+            if (!mi.any) {
+                for (int t = threadIdx.x; t < L; t += blockDim.x) out[t] = -sg * e.P->rho_pad;
+            } else {
+                const int khi = ((I.flags & F_MASK_UNB) && mi.khi == L - 1) ? -1 : mi.khi;
+                win_hard(e, u, out, nullptr, sg, mi.klo, khi, PAD_NEUTRAL, 0.f, (VI*)S(e, 0), (VI*)S(e, 2));
+            }
+            break;
+        }
+        const float bl = pbeta(e, I) * LOG2E;
+        SP* acc = (SP*)S(e, 4);
+        SP* E = (SP*)S(e, 8);
+        const bool core = mi.clo <= mi.chi;
+        if (core) {
+            const int khi = ((I.flags & F_MASK_UNB) && mi.chi == L - 1) ? -1 : mi.chi;
+            win_smooth_sum(e, u, acc, sg * bl, mi.clo, khi, PAD_NEUTRAL, 0.f, (SP*)S(e, 0), (SP*)S(e, 2));
+        }
+        for (int j = threadIdx.x; j < L; j += blockDim.x) E[j] = sp_leaf(sg * bl * u[j]);
+        __syncthreads();
+        const float lwc = core ? log2f(mi.wc) : 0.f;
+        for (int t = threadIdx.x; t < L; t += blockDim.x) {
+            SP a = core ? acc[t] : sp_zero();
+            a.s *= core ? mi.wc : 0.f;
+            const int b0 = mi.klo, b1 = core ? mi.clo - 1 : mi.khi;
+            for (int k = b0; k <= b1 && t + k < L; ++k) a = sp_add(a, SP{w[k] * E[t + k].s, E[t + k].r});
+            if (core)
+                for (int k = mi.chi + 1; k <= mi.khi && t + k < L; ++k)
+                    a = sp_add(a, SP{w[k] * E[t + k].s, E[t + k].r});
+            const bool any = mi.any && t + mi.klo <= L - 1;
+            out[t] = any ? sg * sp_log2(a) / bl : -sg * e.P->rho_pad;
+        }
+        (void)lwc;
+        break;
+    }
+    case K_UNTIL: {
+        const float* phi = slot(e, i0);
+        const float* psi = slot(e, i1);
+        if (!is_smooth(I)) {
+            until_hard(e, I, phi, psi, out, nullptr, nullptr, nullptr);
+        } else {
+            const float bl = pbeta(e, I) * LOG2E;
+            SP* Ephi = (SP*)S(e, 0);
+            SP* Epsi = (SP*)S(e, 2);
+            for (int j = threadIdx.x; j < L; j += blockDim.x) {
+                Ephi[j] = sp_leaf(-bl * phi[j]);
+                Epsi[j] = sp_leaf(-bl * psi[j]);
+            }
+            __syncthreads();
+            until_smooth_fwd(e, I, Ephi, Epsi, out, bl);
+        }
+        break;
+    }
+    default:
+        break;
+    }
+    __syncthreads();
+}
+
+// Adjoint of one instruction (backward slot map).  Children adjoints are
+// written (not accumulated): every node has exactly one parent.
+DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
+{
+    const int L = e.L;
+    const float sg = (I.flags & F_MIN) ? -1.f : 1.f;
+    const float* g = slot(e, I.g_out);
+    switch (I.kind) {
+    case K_TRUE:
+    case K_LIN:
+    case K_NORM:
+        break;
+    case K_NOT: {
+        float* gu = slot(e, I.g_in0);
+        for (int t = threadIdx.x; t < L; t += blockDim.x) gu[t] = -g[t];
+        break;
+    }
+    case K_NARY:
+        op_nary_bwd(e, I);
+        break;
+    case K_WIN: {
+        const float* u = slot(e, I.b_in0);
+        float* gu = slot(e, I.g_in0);
+        const int khi = (I.flags & F_UNB) ? -1 : I.b;
+        const float padv = e.P->coef[I.coef];
+        if (!is_smooth(I)) {
+            int* js = (int*)S(e, 4);
+            win_hard(e, u, S(e, 5), js, sg, I.a, khi, I.pad, padv, (VI*)S(e, 0), (VI*)S(e, 2));
+            win_hard_adj(e, g, gu, js, (double*)S(e, 6));
+            break;
+        }
+        const float bl = pbeta(e, I) * LOG2E;
+        const float* out = slot(e, I.b_out);
+        const bool unb = khi < 0;
+        const int n = L - I.a;
+        SP* h = (SP*)S(e, 0);
+        float lastpad = 0.f;
+        for (int t = threadIdx.x; t < L; t += blockDim.x) {
+            const float O = sg * bl * out[t];
+            const bool real = t < n;
+            const bool padded = !unb && I.pad != PAD_NEUTRAL && t + khi > L - 1;
+            SP hv = sp_zero();
+            if (real || padded) {
+                SP q = sp_leaf(-O);
+                hv = SP{g[t] * q.s, q.r};
+            }
+            h[t] = real ? hv : sp_zero();
+            if (padded && I.pad == PAD_LAST) {
+                const int np = min(unb ? 0 : khi - I.a + 1, t + khi - (L - 1));
+                lastpad += (float)np * sp_times_exp2(hv, sg * bl * u[L - 1]);
+            }
+        }
+        lastpad = wg_sum(lastpad, *e.sh);
+        SP* res = (SP*)S(e, 4);
+        win_smooth_adj_sum(e, h, (SP*)S(e, 2), res, I.a, khi, n);
+        for (int j = threadIdx.x; j < L; j += blockDim.x) {
+            float v = sp_times_exp2(res[j], sg * bl * u[j]);
+            if (j == L - 1) v += lastpad;
+            gu[j] = v;
+        }
+        break;
+    }
+    case K_MASK: {
+        const float* u = slot(e, I.b_in0);
+        float* gu = slot(e, I.g_in0);
+        float* w = S(e, 6);
+        float* dwa = S(e, 7);
+        float* dwb = S(e, 8);
+        MaskInfo mi = mask_weights(e, I, w, dwa, dwb);
+        if (!is_smooth(I) || !mi.any) {
+            if (!mi.any) {
+                for (int j = threadIdx.x; j < L; j += blockDim.x) gu[j] = 0.f;
+            } else {
+                const int khi = ((I.flags & F_MASK_UNB) && mi.khi == L - 1) ? -1 : mi.khi;
+                int* js = (int*)S(e, 4);
+                win_hard(e, u, S(e, 5), js, sg, mi.klo, khi, PAD_NEUTRAL, 0.f, (VI*)S(e, 0), (VI*)S(e, 2));
+                win_hard_adj(e, g, gu, js, (double*)S(e, 10));
+            }
+            if (I.mslot >= 0 && threadIdx.x == 0) { mask_part[2 * I.mslot] = 0.f; mask_part[2 * I.mslot + 1] = 0.f; }
+            break;
+        }
+        const float bl = pbeta(e, I) * LOG2E;
+        const float* out = slot(e, I.b_out);
+        const bool core = mi.clo <= mi.chi;
+        SP* h = (SP*)S(e, 0);
+        SP* hb = (SP*)S(e, 9);      // band copy of h (the scans consume h)
+        SP* E = (SP*)S(e, 11);
+        const int nvalid = L - mi.klo;
+        float pa = 0.f, pb = 0.f;
+        for (int t = threadIdx.x; t < L; t += blockDim.x) {
+            E[t] = sp_leaf(sg * bl * u[t]);
+            SP hv = sp_zero();
+            if (t < nvalid) {
+                SP q = sp_leaf(-sg * bl * out[t]);
+                hv = SP{g[t] * q.s, q.r};
+            }
+            h[t] = hv;
+            hb[t] = hv;
+        }
+        __syncthreads();
+        // d/da, d/db: per t, sum over the support bands of dw_k 2^{z_{t+k} - O_t}
+        for (int t = threadIdx.x; t < nvalid; t += blockDim.x) {
+            SP aa = sp_zero(), ab = sp_zero();
+            const int b0 = mi.klo, b1 = core ? mi.clo - 1 : mi.khi;
+            for (int k = b0; k <= b1 && t + k < L; ++k) {
+                aa = sp_add(aa, SP{dwa[k] * E[t + k].s, E[t + k].r});
+                ab = sp_add(ab, SP{dwb[k] * E[t + k].s, E[t + k].r});
+            }
+            if (core)
+                for (int k = mi.chi + 1; k <= mi.khi && t + k < L; ++k) {
+                    aa = sp_add(aa, SP{dwa[k] * E[t + k].s, E[t + k].r});
+                    ab = sp_add(ab, SP{dwb[k] * E[t + k].s, E[t + k].r});
+                }
+            const float O = sg * bl * out[t];
+            const float ib = sg * g[t] / pbeta(e, I);
+            pa += ib * sp_times_exp2(aa, -O);
+            pb += ib * sp_times_exp2(ab, -O);
+        }
+        pa = wg_sum(pa, *e.sh);
+        pb = wg_sum(pb, *e.sh);
+        if (I.mslot >= 0 && threadIdx.x == 0) { mask_part[2 * I.mslot] = pa; mask_part[2 * I.mslot + 1] = pb; }
+        // dx: core via the transposed van Herk sum, bands term by term
+        SP* res = (SP*)S(e, 4);
+        if (core) {
+            const int khi = ((I.flags & F_MASK_UNB) && mi.chi == L - 1) ? -1 : mi.chi;
+            win_smooth_adj_sum(e, h, (SP*)S(e, 2), res, mi.clo, khi, nvalid);
+        }
+        for (int j = threadIdx.x; j < L; j += blockDim.x) {
+            SP a = core ? res[j] : sp_zero();
+            a.s *= core ? mi.wc : 0.f;
+            const int b0 = mi.klo, b1 = core ? mi.clo - 1 : mi.khi;
+            for (int k = b0; k <= b1 && j - k >= 0; ++k) a = sp_add(a, SP{w[k] * hb[j - k].s, hb[j - k].r});
+            if (core)
+                for (int k = mi.chi + 1; k <= mi.khi && j - k >= 0; ++k)
+                    a = sp_add(a, SP{w[k] * hb[j - k].s, hb[j - k].r});
+            gu[j] = sp_times_exp2(a, sg * bl * u[j]);
+        }
+        break;
+    }
+    case K_UNTIL: {
+        const float* phi = slot(e, I.b_in0);
+        const float* psi = slot(e, I.b_in1);
+        float* gphi = slot(e, I.g_in0);
+        float* gpsi = slot(e, I.g_in1);
+        for (int t = threadIdx.x; t < L; t += blockDim.x) { gphi[t] = 0.f; gpsi[t] = 0.f; }
+        __syncthreads();
+        if (!is_smooth(I)) {
+            until_hard(e, I, phi, psi, nullptr, g, gphi, gpsi);
+        } else {
+            const float bl = pbeta(e, I) * LOG2E;
+            SP* Ephi = (SP*)S(e, 0);
+            SP* Epsi = (SP*)S(e, 2);
+            for (int j = threadIdx.x; j < L; j += blockDim.x) {
+                Ephi[j] = sp_leaf(-bl * phi[j]);
+                Epsi[j] = sp_leaf(-bl * psi[j]);
+            }
+            __syncthreads();
+            const int bmax = I.b < 0 ? L - 1 : min(I.b, L - 1);
+            until_smooth_adj(e, I, Ephi, Epsi, g, gphi, gpsi, (SP*)S(e, 4), bmax / UCK + 1);
+        }
+        // d phi / d psi are sums of scaled terms: convert the scaled psi/phi sums in place
+        break;
+    }
+    default:
+        break;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ kernels
+
+struct KArgs {
+    const float* params;
+    float* root;           // forward: [N_total]
+    float* nodes;          // forward: [n_nodes][N_total] or NULL
+    int64_t n_total;
+    const float* G;        // backward: upstream gradient [N_total]
+    float* dx;             // backward: [N_total, D]
+    float* mask_part;      // backward: [B][n_masks][2]
+    float* garena;         // global slot arenas (NULL: LDS)
+    int64_t arena_floats;  // floats per arena (slots + scratch)
+    int* counter;          // persistent scheduler counter
+    int persistent;
+};
+
+DEV bool next_item(const KArgs& ka, Shared& sh, int64_t& item, bool first)
+{
+    if (!ka.persistent) {
+        item = blockIdx.x;
+        return first;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) sh.ints[7] = atomicAdd(ka.counter, 1);
+    __syncthreads();
+    item = sh.ints[7];
+    return true;
+}
+
+template <bool BWD>
+__global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt, KArgs ka)
+{
+    extern __shared__ float smem[];
+    __shared__ Shared sh;
+    const DevPlan* P = &plan;
+    float* arena = ka.garena ? ka.garena + (size_t)blockIdx.x * ka.arena_floats : smem;
+    const int nslots = BWD ? P->n_slots_bwd : P->n_slots_fwd;
+    const int Lc = bt.Lcap;
+    int64_t item = 0;
+    bool first = true;
+    while (next_item(ka, sh, item, first)) {
+        first = false;
+        if (item >= bt.B) break;
+        const int64_t b = bt.order ? (int64_t)bt.order[item] : item;
+        const int64_t off = bt.offsets ? bt.offsets[b] : b * bt.T;
+        const int64_t len = bt.offsets ? bt.offsets[b + 1] - off : bt.T;
+        if (len <= 0) continue;
+        if (len > Lc) {
+            // trajectory longer than the launch's capacity: report NaN
+            for (int64_t t = threadIdx.x; t < len; t += blockDim.x) {
+                if (!BWD) ka.root[off + t] = NAN;
+                else for (int d = 0; d < bt.D; ++d) ka.dx[(off + t) * bt.D + d] = NAN;
+            }
+            if (BWD && threadIdx.x == 0)
+                for (int m = 0; m < P->n_masks; ++m) {
+                    ka.mask_part[(b * P->n_masks + m) * 2] = NAN;
+                    ka.mask_part[(b * P->n_masks + m) * 2 + 1] = NAN;
+                }
+            continue;
+        }
+        Env e;
+        e.P = P;
+        e.x = bt.x + off * bt.D;
+        e.params = ka.params;
+        e.L = (int)len;
+        e.Lc = Lc;
+        e.D = bt.D;
+        e.arena = arena;
+        e.scr = arena + (size_t)nslots * Lc;
+        e.sh = &sh;
+        for (int k = 0; k < P->n_ins; ++k) exec_fwd(e, P->ins[k], BWD);
+        if (!BWD) {
+            const float* r = slot(e, P->ins[P->root].f_out);
+            for (int t = threadIdx.x; t < e.L; t += blockDim.x) ka.root[off + t] = r[t];
+            if (ka.nodes) {
+                // every node trace (debug): rerun with all slots kept is not
+                // needed because the forward map keeps node outputs until
+                // overwritten; the host gives every node its own slot when
+                // traces are requested.
+                for (int k = 0; k < P->n_ins; ++k) {
+                    const Instr& I = P->ins[k];
+                    if (I.node < 0) continue;
+                    const float* s = slot(e, I.f_out);
+                    for (int t = threadIdx.x; t < e.L; t += blockDim.x)
+                        ka.nodes[(int64_t)I.node * ka.n_total + off + t] = s[t];
+                }
+            }
+            __syncthreads();
+        } else {
+            float* gr = slot(e, P->ins[P->root].g_out);
+            for (int t = threadIdx.x; t < e.L; t += blockDim.x) gr[t] = ka.G[off + t];
+            __syncthreads();
+            float* mp = ka.mask_part + b * P->n_masks * 2;
+            for (int k = P->n_ins - 1; k >= 0; --k) exec_adj(e, P->ins[k], mp);
+            op_dx(e, ka.dx + off * bt.D);
+            __syncthreads();
+        }
+    }
+}
+
+// grad_params[mask_param + 0/1] = sum over trajectories (fixed order) of the
+// per-trajectory partials; every other parameter gradient is 0.
+__global__ void stl_reduce_params(const float* part, int64_t B, int n_masks, DevPlan plan, float* gp)
+{
+    __shared__ float red[256];
+    const int tid = threadIdx.x;
+    for (int p = tid; p < plan.n_params; p += blockDim.x) gp[p] = 0.f;
+    __syncthreads();
+    for (int q = 0; q < 2 * n_masks; ++q) {
+        float s = 0.f;
+        for (int64_t b = tid; b < B; b += blockDim.x) s += part[b * 2 * n_masks + q];
+        red[tid] = s;
+        __syncthreads();
+        for (int k = blockDim.x >> 1; k > 0; k >>= 1) {
+            if (tid < k) red[tid] += red[tid + k];
+            __syncthreads();
+        }
+        if (tid == 0) gp[plan.mask_param[q >> 1] + (q & 1)] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void stl_zero_counter(int* c) { if (threadIdx.x == 0) c[0] = 0; }
+
+}  // namespace stlmi
+
+// ------------------------------------------------------------------ launch helpers (host)
+
+namespace stlmi {
+
+size_t scratch_floats(int Lc, int nt, int max_until_b)
+{
+    size_t s = (size_t)SCR_UNITS * Lc + 64;
+    // smooth Until checkpoints: nt * (b/UCK + 1) scaled pairs, placed at unit 4
+    size_t ck = (size_t)nt * (size_t)(max_until_b / UCK + 1) * 2;
+    if ((size_t)4 * Lc + ck + 64 > s) s = (size_t)4 * Lc + ck + 64;
+    return s;
+}
+
+hipError_t launch_exec(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs& ka, int grid, int nt,
+                       size_t lds_bytes, hipStream_t s)
+{
+    if (bwd) {
+        hipLaunchKernelGGL(stl_exec_kernel<true>, dim3(grid), dim3(nt), lds_bytes, s, plan, bt, ka);
+    } else {
+        hipLaunchKernelGGL(stl_exec_kernel<false>, dim3(grid), dim3(nt), lds_bytes, s, plan, bt, ka);
+    }
+    return hipGetLastError();
+}
+
+hipError_t set_max_lds(size_t bytes)
+{
+    hipError_t e1 = hipFuncSetAttribute((const void*)stl_exec_kernel<false>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipError_t e2 = hipFuncSetAttribute((const void*)stl_exec_kernel<true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return e1 != hipSuccess ? e1 : e2;
+}
+
+hipError_t launch_zero_counter(int* c, hipStream_t s)
+{
+    hipLaunchKernelGGL(stl_zero_counter, dim3(1), dim3(64), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& plan, float* gp, hipStream_t s)
+{
+    hipLaunchKernelGGL(stl_reduce_params, dim3(1), dim3(256), 0, s, part, B, plan.n_masks, plan, gp);
+    return hipGetLastError();
+}
+
+}  // namespace stlmi

@@ -1,0 +1,79 @@
+// Internal execution-plan layout shared by the host plan compiler
+// (stl_api.cpp) and the device executor (stl_kernels.hip).  Not part of the
+// public ABI.
+//
+// A plan is a straight-line program over on-chip "slots" (one float per
+// timestep of the trajectory being processed): one instruction per formula
+// node, in topological order.  The forward kernel runs the instructions in
+// order with the forward slot map.  The backward kernel runs them in order
+// with the backward slot map (recomputing every trace the adjoints need),
+// then runs the adjoint of each instruction in reverse order and finally
+// writes d/dx from the predicate adjoints.  The whole program travels to
+// the GPU by value as a kernel argument, so a plan needs no device memory.
+#pragma once
+#include <stdint.h>
+
+namespace stlmi {
+
+enum Kind : int8_t {
+    K_TRUE = 0,
+    K_LIN = 1,     // linear predicate
+    K_NORM = 2,    // norm predicate
+    K_NOT = 3,
+    K_NARY = 4,    // and / or over up to 4 children
+    K_WIN = 5,     // eventually / always over an integer interval
+    K_MASK = 6,    // eventually / always with the smooth time mask
+    K_UNTIL = 7
+};
+
+enum Flag : int8_t {
+    F_SMOOTH = 1,
+    F_MIN = 2,        // min-type (and, always): evaluated as max on negated values
+    F_UNB = 4,        // unbounded integer interval
+    F_MASK_UNB = 8    // smooth mask with b = +inf
+};
+
+constexpr int MAX_INSTR = 48;
+constexpr int MAX_COEF = 160;
+constexpr int MAX_NCH = 4;
+constexpr int MAX_PRED = 16;
+constexpr int MAX_MASKS = 16;
+constexpr int MAX_D = 16;
+
+struct Instr {                  // 40 bytes
+    int8_t kind, flags, nch, pad;
+    int8_t f_out, f_in0, f_in1;             // forward slot map
+    int8_t b_out, b_in0, b_in1;             // backward slot map (values)
+    int8_t g_out, g_in0, g_in1;             // backward slot map (adjoints)
+    int8_t beta;                            // parameter index of beta (smooth), -1
+    int8_t mask;                            // parameter index of (a,b,c,eps), -1
+    int8_t mslot;                           // index of this mask in the d/da,d/db partials
+    int8_t f_ch[MAX_NCH], b_ch[MAX_NCH], g_ch[MAX_NCH];
+    int16_t node;                           // caller's node index (trace output), -1
+    int16_t coef;                           // predicate / pad-value offset into coef[]
+    int32_t a, b;                           // integer interval (b < 0: unbounded)
+};
+static_assert(sizeof(Instr) == 40, "Instr layout");
+
+struct DevPlan {
+    int32_t n_ins;
+    int32_t n_slots_fwd;
+    int32_t n_slots_bwd;
+    int32_t D;
+    int32_t n_masks;
+    int32_t n_params;
+    int32_t n_pred;
+    int32_t root;                           // instruction index of the root
+    float rho_max;
+    float rho_pad;
+    int16_t pred_ins[MAX_PRED];             // instruction index of each predicate
+    int8_t mask_param[MAX_MASKS];           // parameter index of each learnable mask
+    Instr ins[MAX_INSTR];
+    float coef[MAX_COEF];
+};
+
+// Predicate coefficient layout in coef[] at offset o:
+//   linear: [0] c, [1 .. 1+D) w
+//   norm:   [0] m, [1] r, [2] sign, [3..7) p, [7 .. 7+m*D) A (row-major)
+
+}  // namespace stlmi

@@ -1,0 +1,122 @@
+"""Host-side checks of libstlmi.so (no GPU needed): it loads, exports every
+entry point declared in include/stlmi.h, and its plan compiler validates
+formulas and reports errors through stl_last_error."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2501_04194_amd import stl, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "stlmi.h")).read()
+    # function declarations: a return type, the name, an opening parenthesis
+    return sorted(set(re.findall(r"^(?:stl_status|const char\*)\s+(stl_[a-z_]+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = stl.lib()
+    names = _declared()
+    assert "stl_compile" in names and "stl_forward" in names and "stl_backward" in names
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(names) == set(stl.EXPORTS)
+
+
+def _compile_raw(nodes, child, root, preds=(), D=2, n_params=0):
+    arr = (stl.Node * len(nodes))(*nodes)
+    ci = (ctypes.c_int32 * max(1, len(child)))(*child)
+    pr = (stl.Pred * max(1, len(preds)))(*preds)
+    h = ctypes.c_void_p()
+    st = stl.lib().stl_compile(arr, len(nodes), ci, len(child), root, pr, len(preds), D, n_params, 1e6, 1e6,
+                               ctypes.byref(h))
+    if st == 0:
+        stl.lib().stl_plan_destroy(h)
+    return st, stl.lib().stl_last_error().decode()
+
+
+def _node(op, n_child=0, child_off=0, a=0, b=-1, smooth=0, beta=-1, pred=-1, mask=-1, pad=0):
+    n = stl.Node()
+    n.op, n.n_child, n.child_off, n.a, n.b = op, n_child, child_off, a, b
+    n.smooth, n.beta_param, n.pred, n.mask_param, n.pad = smooth, beta, pred, mask, pad
+    return n
+
+
+def _lin():
+    p = stl.Pred()
+    p.kind = stl.STL_PRED_LINEAR
+    p.w[0] = 1.0
+    return p
+
+
+def test_compile_accepts_benchmark_formulas():
+    for spec, D, params in [(W.cfg0_formula(), 2, {}), (W.cfg1_formula(4), 4, {}), (W.cfg1_formula(3), 3, {}),
+                            (W.cfg2_formula(), 2, W.cfg2_params())]:
+        p = stl.Plan(spec, D, params)
+        n, npar = ctypes.c_int32(), ctypes.c_int32()
+        assert stl.lib().stl_plan_info(p.handle, ctypes.byref(n), ctypes.byref(npar)) == 0
+        assert n.value == p.n_nodes and npar.value == p.n_params
+
+
+def test_compile_error_paths():
+    E_ARG, E_FORMULA, E_UNSUP = -1, -2, -3
+    lin = _node(stl.STL_PRED_LINEAR, pred=0)
+    # bad interval b < a
+    st, msg = _compile_raw([lin, _node(stl.STL_EVENTUALLY, 1, 0, a=5, b=2)], [0], 1, [_lin()])
+    assert st == E_FORMULA and "interval" in msg
+    # dangling child
+    st, msg = _compile_raw([lin, _node(stl.STL_NOT, 1, 0)], [7], 1, [_lin()])
+    assert st == E_FORMULA and "dangling" in msg
+    # cycle: node 1 is its own child
+    st, msg = _compile_raw([lin, _node(stl.STL_NOT, 1, 0)], [1], 1, [_lin()])
+    assert st == E_FORMULA
+    # shared subformula (DAG) is rejected: formulas are trees
+    st, msg = _compile_raw([lin, _node(stl.STL_AND, 2, 0)], [0, 0], 1, [_lin()])
+    assert st == E_FORMULA and "shared" in msg
+    # wrong child count
+    st, msg = _compile_raw([lin, lin, _node(stl.STL_NOT, 2, 0)], [0, 1], 2, [_lin(), _lin()])
+    assert st == E_FORMULA
+    # smooth node without beta parameter
+    st, msg = _compile_raw([lin, _node(stl.STL_ALWAYS, 1, 0, a=0, b=3, smooth=1)], [0], 1, [_lin()])
+    assert st == E_ARG and "beta" in msg
+    # predicate index out of range
+    st, msg = _compile_raw([_node(stl.STL_PRED_LINEAR, pred=3)], [], 0, [_lin()])
+    assert st == E_ARG
+    # mask parameter block out of range
+    st, msg = _compile_raw([lin, _node(stl.STL_EVENTUALLY, 1, 0, mask=1)], [0], 1, [_lin()], n_params=3)
+    assert st == E_ARG
+    # D out of range, root out of range, unknown op
+    assert _compile_raw([lin], [], 0, [_lin()], D=0)[0] == E_UNSUP
+    assert _compile_raw([lin], [], 3, [_lin()])[0] == E_ARG
+    assert _compile_raw([_node(42)], [], 0)[0] == E_FORMULA
+    # Until with a smooth mask is outside the library's scope
+    st, msg = _compile_raw([lin, _node(stl.STL_PRED_LINEAR, pred=0), _node(stl.STL_UNTIL, 2, 0, mask=0)], [0, 1], 2,
+                           [_lin()], n_params=4)
+    assert st == E_UNSUP
+
+
+def test_nary_more_than_four_children_compiles():
+    spec = {"op": "or", "smooth": True, "beta": 5.0, "children": [W.lin([1, 0], c) for c in range(7)]}
+    p = stl.Plan(spec, 2)
+    assert p.n_nodes == 8
+
+
+def test_lpt_order():
+    off = np.array([0, 3, 10, 10, 15, 23], dtype=np.int64)   # lengths 3, 7, 0, 5, 8
+    assert stl.lpt_order(off).tolist() == [4, 1, 3, 0, 2]
+    with pytest.raises(stl.StlError):
+        stl.lpt_order(np.array([0, 5, 3], dtype=np.int64))
+
+
+def test_param_vector_layout():
+    p = stl.Plan(W.cfg2_formula(), 2, W.cfg2_params())
+    v = p.param_vector()
+    names = [nm for nm, _ in p.slots]
+    assert v[names.index("ev_a")] == 100.0 and v[names.index("al_b")] == 400.0
+    g = p.param_grads(np.arange(p.n_params, dtype=np.float32))
+    assert g["ev_a"] == names.index("ev_a")
