@@ -3,9 +3,12 @@
 Workload: B=4096 random-walk trajectories of T=2048 two-dimensional states,
 formula Eventually~[a,b](x0 > 0) and~ Always~[a,b](x1 < 0.5) with smooth
 sigmoid time masks (a=100, b=400, c=1, eps=1e-6, beta=10), gradients with
-respect to x and the four mask bounds.  One step = stl_forward + stl_backward
-over the whole batch; inputs are resident in HBM and rotate over several
-buffer sets so the 256 MB Infinity Cache cannot serve them.
+respect to x and the four mask bounds.  One step = stl_forward_saving +
+stl_backward_saved over the whole batch (the backward reuses the two
+mask-node traces the forward kept, as an autograd function does; pass
+--recompute for stl_forward + stl_backward); inputs are resident in HBM and
+rotate over several buffer sets so the 256 MB Infinity Cache cannot serve
+them.
 
 Prints one JSON line (metric, value, roofline of the dominant kernel, CPU
 oracle baseline).
@@ -53,6 +56,7 @@ def main():
     ap.add_argument("--rotate", type=int, default=4, help="input buffer sets cycled through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-traj", type=int, default=128)
+    ap.add_argument("--recompute", action="store_true", help="backward recomputes the node traces")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (trajectories shard with no "
@@ -73,12 +77,13 @@ def main():
     R = max(1, args.rotate)
     xs = [x0.clone() for _ in range(R)]
     Gs = [G0.clone() for _ in range(R)]
+    sv = [None if args.recompute else plan.saved_buffer(xs[i]) for i in range(R)]
     del x0, G0
 
     def step(k):
         i = k % R
-        plan.forward(xs[i], pv)
-        plan.backward(xs[i], Gs[i], pv)
+        plan.forward(xs[i], pv, saved=sv[i])
+        plan.backward(xs[i], Gs[i], pv, saved=sv[i])
 
     for k in range(args.warmup):
         step(k)
@@ -108,8 +113,8 @@ def main():
         return float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
     n_k = max(5, min(args.steps, 30))
-    fwd_ms = timed(lambda k: plan.forward(xs[k % R], pv), n_k)
-    bwd_ms = timed(lambda k: plan.backward(xs[k % R], Gs[k % R], pv, want_params=False), n_k)
+    fwd_ms = timed(lambda k: plan.forward(xs[k % R], pv, saved=sv[k % R]), n_k)
+    bwd_ms = timed(lambda k: plan.backward(xs[k % R], Gs[k % R], pv, want_params=False, saved=sv[k % R]), n_k)
     dom_is_bwd = bwd_ms >= fwd_ms
     dom_ms = bwd_ms if dom_is_bwd else fwd_ms
     dom_bytes = (BYTES_BWD if dom_is_bwd else BYTES_FWD) * steps_per_batch
@@ -137,11 +142,12 @@ def main():
         "config": {"workload": "smooth_mask_B4096_T2048_D2", "B": B, "T": T, "D": D,
                    "formula": "Eventually~[a,b](x0>0) and~ Always~[a,b](x1<0.5)",
                    "mask": {"a": 100.0, "b": 400.0, "c": 1.0, "eps": 1e-6}, "beta": 10.0,
-                   "grads": "x and the four mask bounds", "buffer_sets": R},
+                   "grads": "x and the four mask bounds", "buffer_sets": R,
+                   "saved_traces": not args.recompute},
         "hbm_frac_step": (BYTES_FWD + BYTES_BWD) * value / (HBM_PEAK_GBS * 1e9),
         "kernel_ms": {"forward": fwd_ms, "backward": bwd_ms},
         "wall_s": t_wall,
-        "roofline": {"bound": "hbm", "kernel": "stl_exec_kernel<bwd>" if dom_is_bwd else "stl_exec_kernel<fwd>",
+        "roofline": {"bound": "hbm", "kernel": "stl_fused_bwd" if dom_is_bwd else "stl_fused_fwd",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }

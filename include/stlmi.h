@@ -130,11 +130,11 @@ typedef struct {
 
 /* Launch configuration (NULL = library heuristic; see stl_autotune). */
 typedef struct {
-    int32_t threads;         /* work-group size: 64, 128, 256, 512 or 1024 */
+    int32_t threads;         /* work-group size of the generic executor: 64, 128, 256 or 512 */
     int32_t wg_per_cu;       /* persistent grid size per compute unit (0 = one work-group per
                                 trajectory) */
     int32_t global_slots;    /* 1: keep node traces in the workspace instead of LDS */
-    int32_t reserved;
+    int32_t flags;           /* bit 0: do not use the fused fast path (see stl_forward) */
 } stl_launch;
 
 typedef struct stl_plan stl_plan;
@@ -166,6 +166,15 @@ stl_status stl_workspace_size(const stl_plan* plan, const stl_batch* batch, cons
                               size_t* fwd_bytes, size_t* bwd_bytes);
 
 /*
+ * Fused fast path: when the formula is a smooth And/Or over up to 4
+ * smooth-mask Eventually/Always nodes on linear predicates (or one such
+ * node), the batch is dense and T <= 2048, stl_forward and stl_backward run
+ * one fused kernel per call (fp64 accumulation, one work-group per
+ * trajectory); trajectories it cannot take (signal range beyond fp64
+ * exponents, mask bands wider than 512 steps) are recomputed by the generic
+ * executor in the same call.  Results agree with the generic executor to
+ * float32 rounding.
+ *
  * Robustness traces: d_root receives the root trace ([B, T] dense or
  * [N_total] ragged, float32).  d_node_traces, if not NULL, receives every
  * node's trace as [n_nodes][N_total] in the caller's node numbering (debug and
@@ -186,6 +195,36 @@ stl_status stl_forward(const stl_plan* plan, const stl_batch* batch, const float
 stl_status stl_backward(const stl_plan* plan, const stl_batch* batch, const float* d_params,
                         const float* d_grad_root, float* d_grad_x, float* d_grad_params,
                         void* d_ws, size_t ws_bytes, const stl_launch* cfg, void* stream);
+
+/*
+ * Forward/backward with saved mask-node traces.  The backward of a smooth
+ * n-ary root needs every child's trace (Sec. III-C: the logsumexp adjoint
+ * weights each child by its softmax share); stl_backward recomputes them on
+ * chip, these variants keep them in HBM between the two calls instead
+ * (the usual saved-for-backward of an autograd function).
+ *
+ * stl_saved_size: bytes of the caller-owned device buffer `d_saved` for this
+ * batch: a header of B int32 validity flags (padded to 256 bytes) followed by
+ * [n_mask][B][T] float32 traces when the fused fast path applies (n_mask = the
+ * number of smooth-mask children of the root); only the header otherwise.
+ *
+ * stl_forward_saving: stl_forward that also fills d_saved (saved_bytes must
+ * be at least stl_saved_size).  Trajectories the fused kernel does not take
+ * are flagged 0 and recomputed by the backward.
+ *
+ * stl_backward_saved: stl_backward that reads d_saved written by
+ * stl_forward_saving with the same plan, batch contents and parameters (the
+ * caller guarantees this; the traces are not checked against x).  Results are
+ * those of stl_backward to float32 rounding.  Errors as stl_forward.
+ */
+stl_status stl_saved_size(const stl_plan* plan, const stl_batch* batch, size_t* saved_bytes);
+stl_status stl_forward_saving(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                              float* d_root, void* d_saved, size_t saved_bytes, void* d_ws,
+                              size_t ws_bytes, const stl_launch* cfg, void* stream);
+stl_status stl_backward_saved(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                              const void* d_saved, size_t saved_bytes, const float* d_grad_root,
+                              float* d_grad_x, float* d_grad_params, void* d_ws, size_t ws_bytes,
+                              const stl_launch* cfg, void* stream);
 
 /* Message describing the last non-OK status returned on this thread. */
 const char* stl_last_error(void);

@@ -24,31 +24,15 @@ hipError_t launch_exec(bool bwd, const DevPlan& plan, const struct Batch& bt, co
                        int nt, size_t lds_bytes, hipStream_t s);
 hipError_t set_max_lds(size_t bytes);
 hipError_t launch_zero_counter(int* c, hipStream_t s);
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
 hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& plan, float* gp, hipStream_t s);
+size_t fused_lds(int Lc, int n, int D, bool bwd);
+int fused_max_T();
+hipError_t launch_fused(bool bwd, const DevPlan& plan, const struct Batch& bt, const struct KArgs& ka, size_t lds,
+                        hipStream_t s);
+hipError_t set_max_lds_fused(size_t bytes);
+size_t mask_tab_bytes();
 
-// must match stl_kernels.hip
-struct Batch {
-    const float* x;
-    const int64_t* offsets;
-    const int32_t* order;
-    int64_t B;
-    int64_t T;
-    int32_t D;
-    int32_t Lcap;
-};
-struct KArgs {
-    const float* params;
-    float* root;
-    float* nodes;
-    int64_t n_total;
-    const float* G;
-    float* dx;
-    float* mask_part;
-    float* garena;
-    int64_t arena_floats;
-    int* counter;
-    int persistent;
-};
 }  // namespace stlmi
 
 using namespace stlmi;
@@ -69,6 +53,8 @@ static stl_status fail(stl_status s, const char* fmt, ...)
 }
 
 extern "C" const char* stl_last_error(void) { return g_err.c_str(); }
+
+void stlmi_set_error(const char* msg) { g_err = msg; }
 
 // ------------------------------------------------------------------ plan
 
@@ -387,8 +373,40 @@ extern "C" stl_status stl_compile(const stl_node* nodes, int32_t n_nodes, const 
     for (int i = 0; i < dp.n_masks; ++i) dp.mask_param[i] = (int8_t)B.mask_params[i];
     for (int k = 0; k < n; ++k) dp.ins[k] = B.ins[k];
     for (size_t i = 0; i < B.coef.size(); ++i) dp.coef[i] = B.coef[i];
-    // trace-output variant: slot k for instruction k
+    // fused fast path: root = smooth n-ary over <= 4 smooth-mask nodes on linear
+    // predicates, or a single such mask node
+    {
+        auto is_fmask = [&](int k) {
+            const Instr& I = B.ins[k];
+            return I.kind == K_MASK && (I.flags & F_SMOOTH) && B.kids[k].size() == 1 &&
+                   B.ins[B.kids[k][0]].kind == K_LIN;
+        };
+        FusedDesc& F = dp.fused;
+        std::memset(&F, 0, sizeof F);
+        const Instr& R = B.ins[rootk];
+        if (is_fmask(rootk)) {
+            F.n = 1;
+            F.root_nary = 0;
+            F.ins[0] = (int8_t)rootk;
+            F.pred[0] = (int8_t)B.kids[rootk][0];
+        } else if (R.kind == K_NARY && (R.flags & F_SMOOTH) && B.kids[rootk].size() <= 4) {
+            bool ok = true;
+            for (int c : B.kids[rootk]) ok = ok && is_fmask(c);
+            if (ok) {
+                F.n = (int8_t)B.kids[rootk].size();
+                F.root_nary = 1;
+                F.nary_min = (R.flags & F_MIN) ? 1 : 0;
+                F.nary_beta = R.beta;
+                for (int j = 0; j < F.n; ++j) {
+                    F.ins[j] = (int8_t)B.kids[rootk][j];
+                    F.pred[j] = (int8_t)B.kids[B.kids[rootk][j]][0];
+                }
+            }
+        }
+    }
+    // trace-output variant: slot k for instruction k (never fused)
     p->dev_trace = dp;
+    std::memset(&p->dev_trace.fused, 0, sizeof(FusedDesc));
     DevPlan& tp = p->dev_trace;
     tp.n_slots_fwd = n;
     for (int k = 0; k < n; ++k) {
@@ -464,6 +482,7 @@ DevInfo& devinfo()
     const size_t static_lds = 8192;   // Shared struct + headroom
     di.lds_max = di.lds_max > static_lds ? di.lds_max - static_lds : 0;
     if (set_max_lds(di.lds_max) == hipSuccess) di.lds_set = true;
+    (void)set_max_lds_fused(di.lds_max);
     (void)hipGetLastError();
     return g_dev[dev] = di;
 }
@@ -479,6 +498,10 @@ struct Geom {
     size_t ws_bytes;        // total workspace
     size_t off_part;        // mask partials (bytes)
     size_t off_arena;       // global arenas (bytes)
+    bool fused;             // fused fast path (dense batches of the fused formula shape)
+    size_t fused_lds;
+    size_t off_list;        // fused: fix-up list (bytes)
+    size_t off_tabs;        // fused: per-mask tables (bytes)
 };
 
 stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch* cfg, bool bwd, bool trace,
@@ -519,6 +542,33 @@ stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch*
     if (bwd) off += (size_t)bt->B * std::max(dp.n_masks, 1) * 2 * sizeof(float);
     off = (off + 255) / 256 * 256;
     g->off_arena = off;
+    g->fused = false;
+    g->fused_lds = 0;
+    g->off_list = 0;
+    g->off_tabs = 0;
+    const bool want_fused = dp.fused.n > 0 && !trace && bt->offsets == nullptr && bt->T <= fused_max_T() &&
+                            !(cfg && (cfg->flags & 1));
+    if (want_fused) {
+        const size_t fl = fused_lds((int)((bt->T + 3) / 4 * 4), dp.fused.n, bt->D, bwd);
+        if (fl <= di.lds_max) {
+            g->fused = true;
+            g->fused_lds = fl;
+            // the generic executor handles the fix-up list with a small persistent grid
+            if (!global) {
+                g->persistent = 1;
+                g->grid = (int)std::max<int64_t>(1, std::min<int64_t>(bt->B, di.cus / 4));
+            } else {
+                g->grid = (int)std::max<int64_t>(1, std::min<int64_t>(bt->B, di.cus / 4));
+            }
+            g->off_list = off;
+            off += (size_t)bt->B * sizeof(int);
+            off = (off + 255) / 256 * 256;
+            g->off_tabs = off;
+            off += (size_t)dp.fused.n * mask_tab_bytes();
+            off = (off + 255) / 256 * 256;
+            g->off_arena = off;
+        }
+    }
     if (global) off += (size_t)g->grid * arena * sizeof(float);
     g->ws_bytes = off;
     return STL_OK;
@@ -551,12 +601,29 @@ extern "C" stl_status stl_workspace_size(const stl_plan* plan, const stl_batch* 
     return STL_OK;
 }
 
+static size_t saved_header(int64_t B) { return ((size_t)B * sizeof(int32_t) + 255) / 256 * 256; }
+
+static size_t saved_bytes_needed(const stl_plan* plan, const stl_batch* bt)
+{
+    const int n = plan->dev.fused.n;
+    const bool fusable = n > 0 && bt->offsets == nullptr && bt->T <= fused_max_T();
+    return saved_header(bt->B) + (fusable ? (size_t)n * bt->B * bt->T * sizeof(float) : 0);
+}
+
+// saved: 0 none, 1 forward writes d_saved, 2 backward reads it
 static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* params, bool bwd, float* root,
                       float* nodes, const float* G, float* dx, float* gparams, void* ws, size_t ws_bytes,
-                      const stl_launch* cfg, void* stream)
+                      const stl_launch* cfg, void* stream, int saved = 0, void* d_saved = nullptr,
+                      size_t saved_bytes = 0)
 {
     stl_status s = check_batch(plan, bt);
     if (s != STL_OK) return s;
+    if (saved && bt->B > 0) {
+        if (!d_saved) return fail(STL_E_ARG, "saved buffer is NULL");
+        const size_t need = saved_bytes_needed(plan, bt);
+        if (saved_bytes < need)
+            return fail(STL_E_ARG, "saved buffer too small: need %zu bytes, got %zu", need, saved_bytes);
+    }
     if (plan->n_params > 0 && !params) return fail(STL_E_ARG, "params is NULL");
     if (!bwd && bt->B > 0 && !root) return fail(STL_E_ARG, "root output is NULL");
     if (bwd && bt->B > 0 && (!G || !dx)) return fail(STL_E_ARG, "grad_root / grad_x is NULL");
@@ -608,9 +675,35 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
             ka.n_total = bt->B * bt->T;
         }
     }
-    if (g.persistent && launch_zero_counter(ka.counter, st) != hipSuccess)
+    ka.list_count = (int*)wsb + 1;
+    ka.list = g.fused ? (int*)(wsb + g.off_list) : nullptr;
+    ka.tabs = g.fused ? (const MaskTab*)(wsb + g.off_tabs) : nullptr;
+    ka.list_mode = 0;
+    if (saved) {
+        int* flags = (int*)d_saved;
+        float* traces = (float*)((char*)d_saved + saved_header(bt->B));
+        ka.saved_flag = flags;
+        if (saved == 1 && g.fused) ka.saved = traces;
+        if (saved == 2 && g.fused) ka.saved_in = traces;
+        // a forward that does not take the fused path leaves nothing to reuse
+        if (saved == 1 && !g.fused && launch_fill_int(flags, bt->B, 0, st) != hipSuccess)
+            return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    if ((g.persistent || g.fused) && launch_zero_counter(ka.counter, st) != hipSuccess)
         return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
-    hipError_t e = launch_exec(bwd, dp, b, ka, g.grid, g.nt, g.lds_bytes, st);
+    hipError_t e;
+    if (g.fused) {
+        e = launch_fused(bwd, dp, b, ka, g.fused_lds, st);
+        if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+        // trajectories the fused kernel could not take (signal range beyond
+        // fp64 exponents, very wide mask bands) go through the generic executor
+        KArgs kf = ka;
+        kf.list_mode = 1;
+        kf.persistent = 1;
+        e = launch_exec(bwd, dp, b, kf, g.grid, g.nt, g.lds_bytes, st);
+    } else {
+        e = launch_exec(bwd, dp, b, ka, g.grid, g.nt, g.lds_bytes, st);
+    }
     if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     if (bwd && gparams) {
         e = launch_reduce_params(ka.mask_part, bt->B, dp, gparams, st);
@@ -633,6 +726,32 @@ extern "C" stl_status stl_backward(const stl_plan* plan, const stl_batch* batch,
 {
     return run(plan, batch, d_params, true, nullptr, nullptr, d_grad_root, d_grad_x, d_grad_params, d_ws, ws_bytes,
                cfg, stream);
+}
+
+extern "C" stl_status stl_saved_size(const stl_plan* plan, const stl_batch* batch, size_t* saved_bytes)
+{
+    stl_status s = check_batch(plan, batch);
+    if (s != STL_OK) return s;
+    if (!saved_bytes) return fail(STL_E_ARG, "saved_bytes is NULL");
+    *saved_bytes = saved_bytes_needed(plan, batch);
+    return STL_OK;
+}
+
+extern "C" stl_status stl_forward_saving(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                                         float* d_root, void* d_saved, size_t saved_bytes, void* d_ws,
+                                         size_t ws_bytes, const stl_launch* cfg, void* stream)
+{
+    return run(plan, batch, d_params, false, d_root, nullptr, nullptr, nullptr, nullptr, d_ws, ws_bytes, cfg, stream,
+               1, d_saved, saved_bytes);
+}
+
+extern "C" stl_status stl_backward_saved(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                                         const void* d_saved, size_t saved_bytes, const float* d_grad_root,
+                                         float* d_grad_x, float* d_grad_params, void* d_ws, size_t ws_bytes,
+                                         const stl_launch* cfg, void* stream)
+{
+    return run(plan, batch, d_params, true, nullptr, nullptr, d_grad_root, d_grad_x, d_grad_params, d_ws, ws_bytes,
+               cfg, stream, 2, const_cast<void*>(d_saved), saved_bytes);
 }
 
 // ------------------------------------------------------------------ autotuner
@@ -682,7 +801,7 @@ bool cache_lookup(const std::string& key, stl_launch* out, float* ms)
             out->threads = a;
             out->wg_per_cu = b2;
             out->global_slots = c;
-            out->reserved = 0;
+            out->flags = 0;
             *ms = m;
             found = true;
         }

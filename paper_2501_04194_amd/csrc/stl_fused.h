@@ -1,0 +1,766 @@
+// Fused fast path for formulas of the shape
+//     root = smooth And/Or over up to 4 smooth-mask Eventually/Always nodes,
+//            each over a linear predicate (or a single such mask node),
+// e.g. Eventually~[a,b](x0 > 0) and~ Always~[a,b](x1 < 0.5) with the smooth
+// time mask of arXiv 2501.04194 Sec. VI.  Included by stl_kernels.hip.
+//
+// One work-group (FNT threads) computes the whole formula for one trajectory
+// of length L <= FNT * FNO; thread i owns timesteps [FNO*i, FNO*i + FNO) and
+// keeps their mask traces in registers.  For each mask node the terms
+// 2^{z_j}, z = sign * beta * log2(e) * u, are held in fp64 relative to one
+// per-trajectory reference exponent (fp64's exponent range makes per-window
+// rescaling unnecessary; fp64 FMA runs at the non-packed fp32 FMA rate on
+// CDNA4).  The constant-weight core of the mask is a van Herk window: block
+// prefix and block suffix sums (segmented scans done in registers and wave
+// shuffles), every window is suffix(start) + prefix(end), no subtraction.
+// The two sigmoid bands are register-blocked FMA loops over LDS with fp64
+// weights read as scalars from a per-call table.  Two LDS arrays suffice:
+// the terms (later the adjoint terms, later the block prefixes) and the
+// block suffixes, so four work-groups fit in one compute unit.  LDS arrays
+// hold one pad element per 8 so that lanes owning 8 consecutive elements hit
+// distinct banks.
+//
+// Trajectories whose signal range exceeds fp64's exponent range, and masks
+// whose bands are wider than FMAXB, are handed to the generic executor.
+#pragma once
+
+namespace stlmi {
+
+constexpr int FNT = 256;          // threads per work-group
+constexpr int FNO = 8;            // consecutive timesteps per thread
+constexpr int FNW = FNT / 64;     // waves per work-group
+constexpr int FMAXB = 512;        // max padded width of one band weight array
+constexpr int FHOFF = 32;         // low-side zero padding of the adjoint array (elements)
+constexpr int FTAIL = 32;         // high-side zero padding (elements)
+constexpr int FMAXN = 4;          // mask nodes under the root
+
+// Per-mask tables, computed once per call by stl_mask_tables.
+struct MaskTab {
+    int ok;                     // 0: bands too wide for the fused path
+    int any;                    // support {w > 0} is non-empty
+    int klo, khi, clo, chi;     // support and constant core (clo > chi: no core)
+    int core, K, off;           // van Herk block length and head offset (core only)
+    int kl0, nWl, kr0, nWr;     // bands: padded start offsets and widths (multiples of 8)
+    int nz_al, nz_bl;           // left band: d/da, d/db weights not all zero
+    int nz_ar, nz_br;           // right band: same
+    float wc;                   // core weight
+    double Wl[FMAXB], Wr[FMAXB];                          // band weights
+    double Dal[FMAXB], Dar[FMAXB], Dbl[FMAXB], Dbr[FMAXB];  // d w / d a, d w / d b
+    double Wlr[FMAXB + 8], Wrr[FMAXB + 8];                // reversed, for transposed sums
+};
+
+struct FShared {
+    double wv[FNW];
+    int wf[FNW];
+    int wi[FNW];
+    int ints[8];
+    int fragile;
+};
+
+DEV int PX(int j) { return j + (j >> 3); }
+__host__ __device__ constexpr int px_len(int n) { return n + (n >> 3) + 16; }
+DEV int floor8(int v) { return v & ~7; }
+DEV int round8(int v) { return (v + 7) & ~7; }
+
+DEV int wg_max_i(int v, FShared& sh)
+{
+    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d));
+    if ((threadIdx.x & 63) == 0) sh.wi[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int r = sh.wi[0];
+    for (int w = 1; w < FNW; ++w) r = max(r, sh.wi[w]);
+    __syncthreads();
+    return r;
+}
+
+// deterministic work-group sum (fixed shuffle tree, waves in order)
+DEV double wg_sum_d(double v, FShared& sh)
+{
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+    if ((threadIdx.x & 63) == 0) sh.wv[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh.wv[0];
+    for (int w = 1; w < FNW; ++w) r += sh.wv[w];
+    __syncthreads();
+    return r;
+}
+
+DEV float log2d(double s)
+{
+    int e;
+    double m = frexp(s, &e);
+    return (float)e + log2f((float)m);
+}
+
+// 2^d as a double for d <= 0 (log2 units): exact exponent split
+DEV double exp2d_neg(float d)
+{
+    float fl = floorf(d);
+    int ip = (int)fmaxf(fl, -1100.f);
+    return ldexp((double)exp2f(d - fl), ip);
+}
+
+// Segmented inclusive scan of the FNO values vin[] owned by this thread
+// (timesteps 8*tid .. 8*tid+7), written to the padded LDS array out[0..n).
+// Forward: heads where (p + off) % K == 0; reverse: where (p + off) % K ==
+// K-1 and at n-1.  Values past n must be 0.  Ends with a barrier.
+template <bool REV>
+DEV void fscan(const double* vin, double* out, int n, int K, int off, FShared& sh, int tid)
+{
+    const int lane = tid & 63, w = tid >> 6;
+    const int c0 = FNO * tid;
+    double v[FNO];
+    int hm = 0;
+    int rem = (c0 + off) % K;
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) {
+        const int p = c0 + i;
+        v[i] = vin[i];
+        const bool h = REV ? (p == n - 1 || rem == K - 1) : (rem == 0);
+        hm |= (h && p < n) ? (1 << i) : 0;
+        rem = rem + 1 == K ? 0 : rem + 1;
+    }
+    double acc = 0.0;
+    if (!REV) {
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) { acc = ((hm >> i) & 1) ? v[i] : acc + v[i]; v[i] = acc; }
+    } else {
+#pragma unroll
+        for (int i = FNO - 1; i >= 0; --i) { acc = ((hm >> i) & 1) ? v[i] : v[i] + acc; v[i] = acc; }
+    }
+    double a = acc;
+    int f = hm != 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double ao = REV ? __shfl_down(a, d) : __shfl_up(a, d);
+        const int fo = REV ? __shfl_down(f, d) : __shfl_up(f, d);
+        const bool valid = REV ? (lane + d < 64) : (lane >= d);
+        if (valid) {
+            if (!f) a = ao + a;
+            f |= fo;
+        }
+    }
+    double ex = REV ? __shfl_down(a, 1) : __shfl_up(a, 1);
+    int exf = REV ? __shfl_down(f, 1) : __shfl_up(f, 1);
+    if (REV ? lane == 63 : lane == 0) { ex = 0.0; exf = 0; }
+    if (REV ? lane == 0 : lane == 63) { sh.wv[w] = a; sh.wf[w] = f; }
+    __syncthreads();
+    double c = 0.0;
+    if (!REV) {
+        for (int w2 = 0; w2 < w; ++w2) c = sh.wf[w2] ? sh.wv[w2] : c + sh.wv[w2];
+    } else {
+        for (int w2 = FNW - 1; w2 > w; --w2) c = sh.wf[w2] ? sh.wv[w2] : c + sh.wv[w2];
+    }
+    const double carry = exf ? ex : c + ex;
+    if (!REV) {
+        bool go = true;
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) { go = go && !((hm >> i) & 1); if (go) v[i] += carry; }
+    } else {
+        bool go = true;
+#pragma unroll
+        for (int i = FNO - 1; i >= 0; --i) { go = go && !((hm >> i) & 1); if (go) v[i] += carry; }
+    }
+#pragma unroll
+    for (int i = 0; i < FNO; ++i)
+        if (c0 + i < n) out[PX(c0 + i)] = v[i];
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ band sums
+
+// S[i] += sum_{dk<8} W[dk] * window[i + dk], window = (a[0..7], b[0..7])
+DEV void fma_block(double* S, const double* __restrict__ W, const double* a, const double* b)
+{
+#pragma unroll
+    for (int dk = 0; dk < 8; ++dk) {
+        const double w = W[dk];
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) {
+            const int p = i + dk;
+            S[i] = fma(w, p < 8 ? a[p] : b[p - 8], S[i]);
+        }
+    }
+}
+
+DEV void load8(double* r, const double* A)
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) r[c] = A[c];
+}
+
+// S[i] += sum_{s=s0}^{nW-1} W[s] * A[PX(base + i + s)], i in [0, FNO).  base + s0
+// must be a multiple of 8; A is padded storage holding zeros wherever the
+// loop reads outside the valid range (it reads up to base + nW + 7).  W is a
+// uniform (scalar-loadable) pointer; nW and s0 are multiples of 8.  The two
+// 8-element halves of the window alternate roles, so nothing is moved.
+DEV void band_acc(const double* A, int base, const double* __restrict__ W, int s0, int nW, double* S)
+{
+    if (s0 >= nW) return;
+    int q = PX(base + s0);
+    double x[8], y[8];
+    load8(x, A + q);
+    load8(y, A + q + 9);
+    int s = s0;
+    for (;;) {
+        fma_block(S, W + s, x, y);
+        s += 8;
+        if (s >= nW) break;
+        q += 9;
+        load8(x, A + q + 9);
+        fma_block(S, W + s, y, x);
+        s += 8;
+        if (s >= nW) break;
+        q += 9;
+        load8(y, A + q + 9);
+    }
+}
+
+// ------------------------------------------------------------------ tables
+
+struct TabShared {
+    int ints[8];
+};
+
+// One work-group per mask node: support, core and band weight tables.
+__global__ void __launch_bounds__(256) stl_mask_tables(DevPlan plan, const float* params, int L, MaskTab* tabs)
+{
+    __shared__ TabShared sh;
+    const DevPlan& P = plan;
+    const int m = blockIdx.x;
+    const Instr& I = P.ins[P.fused.ins[m]];
+    MaskTab& T = tabs[m];
+    const MaskInfo mi = mask_info(params, I, L, sh, nullptr, nullptr, nullptr);
+    const bool core = mi.any && mi.clo <= mi.chi;
+    const int le = core ? mi.clo : mi.khi + 1;
+    const int kl0 = mi.any ? floor8(mi.klo) : 0;
+    const int nWl = mi.any ? round8(le - kl0) : 0;
+    const int rs = mi.chi + 1, re = mi.khi + 1;
+    const int kr0 = core ? floor8(rs) : 0;
+    const int nWr = core ? round8(re - kr0) : 0;
+    const bool ok = nWl <= FMAXB && nWr <= FMAXB;
+    if (threadIdx.x == 0) {
+        T.ok = ok;
+        T.any = mi.any;
+        T.klo = mi.klo;
+        T.khi = mi.khi;
+        T.clo = mi.clo;
+        T.chi = mi.chi;
+        T.core = core;
+        T.K = core ? mi.chi - mi.clo + 1 : 1;
+        T.off = core ? (T.K - mi.clo % T.K) % T.K : 0;
+        T.kl0 = kl0;
+        T.nWl = nWl;
+        T.kr0 = kr0;
+        T.nWr = nWr;
+        T.wc = core ? mi.wc : 0.f;
+        sh.ints[4] = 0;
+    }
+    __syncthreads();
+    if (!ok) return;
+    const MaskP mp = mask_params(params + I.mask, I.flags & F_MASK_UNB);
+    for (int s = threadIdx.x; s < FMAXB + 8; s += blockDim.x) {
+        float wl = 0.f, dal = 0.f, dbl = 0.f, wr = 0.f, dar = 0.f, dbr = 0.f;
+        if (s < nWl) {
+            const int k = kl0 + s;
+            if (k >= mi.klo && k < le) wl = mask_wk(mp, k, &dal, &dbl);
+        }
+        if (s < nWr) {
+            const int k = kr0 + s;
+            if (k >= rs && k < re) wr = mask_wk(mp, k, &dar, &dbr);
+        }
+        if (s < FMAXB) {
+            T.Wl[s] = wl;
+            T.Dal[s] = dal;
+            T.Dbl[s] = dbl;
+            T.Wr[s] = wr;
+            T.Dar[s] = dar;
+            T.Dbr[s] = dbr;
+        }
+        // reversed: Wlr[s] = Wl[nWl - s] for 1 <= s <= nWl
+        float wlr = 0.f, wrr = 0.f;
+        if (s >= 1 && s <= nWl) {
+            const int k = kl0 + nWl - s;
+            if (k >= mi.klo && k < le) wlr = mask_wk(mp, k);
+        }
+        if (s >= 1 && s <= nWr) {
+            const int k = kr0 + nWr - s;
+            if (k >= rs && k < re) wrr = mask_wk(mp, k);
+        }
+        T.Wlr[s] = wlr;
+        T.Wrr[s] = wrr;
+        if (dal != 0.f) atomicOr(&sh.ints[4], 1);
+        if (dbl != 0.f) atomicOr(&sh.ints[4], 2);
+        if (dar != 0.f) atomicOr(&sh.ints[4], 4);
+        if (dbr != 0.f) atomicOr(&sh.ints[4], 8);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T.nz_al = (sh.ints[4] & 1) != 0;
+        T.nz_bl = (sh.ints[4] & 2) != 0;
+        T.nz_ar = (sh.ints[4] & 4) != 0;
+        T.nz_br = (sh.ints[4] & 8) != 0;
+    }
+}
+
+// ------------------------------------------------------------------ forward pieces
+
+struct FOp {
+    float sg, bl, beta;
+    const float* cf;     // predicate: [0] c, [1..] w
+    int R;               // reference exponent
+};
+
+DEV void fop_init(const DevPlan& P, int m, const float* params, FOp& op)
+{
+    const FusedDesc& F = P.fused;
+    const Instr& I = P.ins[F.ins[m]];
+    op.cf = P.coef + P.ins[F.pred[m]].coef;
+    op.sg = (I.flags & F_MIN) ? -1.f : 1.f;
+    op.beta = params[I.beta];
+    op.bl = op.beta * LOG2E;
+    op.R = 0;
+}
+
+// E[j] = 2^{z_j - R} for this thread's timesteps: registers e[] and the
+// padded LDS array E with a zero tail.  Sets op.R.  The barriers of the
+// work-group maximum come before the first write to E, so earlier reads of
+// E by other threads are complete.
+DEV void fused_terms(FOp& op, const float* x, int L, int D, double* e, double* E, FShared& sh, float* z, int tid)
+{
+    const int c0 = FNO * tid;
+    float zmax = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) {
+        const int j = c0 + i;
+        float s = 0.f;
+        if (j < L) {
+            const float* xr = x + (size_t)j * D;
+            for (int d = 0; d < D; ++d) s = fmaf(op.cf[1 + d], xr[d], s);
+            z[i] = op.sg * op.bl * (s - op.cf[0]);
+            zmax = fmaxf(zmax, z[i]);
+        } else {
+            z[i] = -INFINITY;
+        }
+    }
+    const int R = wg_max_i((int)ceilf(fminf(fmaxf(zmax, -1e9f), 1e9f)), sh);
+    op.R = R;
+    bool frag = false;
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) {
+        const int j = c0 + i;
+        if (j < L) {
+            const float d = z[i] - (float)R;
+            frag |= d < -1000.f;
+            e[i] = exp2d_neg(d);
+            E[PX(j)] = e[i];
+        } else {
+            e[i] = 0.0;
+            if (j < L + FTAIL) E[PX(j)] = 0.0;
+        }
+    }
+    for (int j = max(L, FNO * FNT) + tid; j < L + FTAIL; j += FNT) E[PX(j)] = 0.0;
+    if (frag) sh.fragile = 1;
+    __syncthreads();
+}
+
+// Forward trace of one mask node for this thread's timesteps (out[0..FNO)).
+// Uses A (terms, then block prefixes) and Bs (block suffixes).
+DEV void mask_trace(const DevPlan& P, const MaskTab& T, FOp& op, const float* x, int L, int D, double* A,
+                    double* Bs, float* out, FShared& sh, int tid)
+{
+    const int c0 = FNO * tid;
+    double e[FNO];
+    float z[FNO];
+    fused_terms(op, x, L, D, e, A, sh, z, tid);
+    if (!T.any) {
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) out[i] = -op.sg * P.rho_pad;
+        return;
+    }
+    double S[FNO];
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) S[i] = 0.0;
+    const int lim = L - c0;
+    if (c0 < L) {
+        band_acc(A, c0 + T.kl0, T.Wl, 0, min(T.nWl, max(0, round8(lim - T.kl0))), S);
+        if (T.core) band_acc(A, c0 + T.kr0, T.Wr, 0, min(T.nWr, max(0, round8(lim - T.kr0))), S);
+    }
+    if (T.core) {
+        __syncthreads();                              // band reads of the terms are done
+        fscan<false>(e, A, L, T.K, T.off, sh, tid);   // block prefixes over the terms
+        fscan<true>(e, Bs, L, T.K, T.off, sh, tid);   // block suffixes
+        if (c0 < L) {
+            const int K = T.K, s0 = c0 + T.clo;
+            const int qL = (L - 1 + T.off) / K;
+            int q = (s0 + T.off) / K, rem = (s0 + T.off) % K;
+            const double wc = (double)T.wc;
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) {
+                const int s = s0 + i;
+                if (s <= L - 1) {
+                    const bool clipped = s + K - 1 > L - 1;
+                    const int en = clipped ? L - 1 : s + K - 1;
+                    const bool same = rem == 0 || (clipped && qL == q);
+                    S[i] = fma(wc, same ? Bs[PX(s)] : Bs[PX(s)] + A[PX(en)], S[i]);
+                }
+                if (++rem == K) { rem = 0; ++q; }
+            }
+        }
+    }
+    const float ibl = 1.f / op.bl;
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) {
+        const int t = c0 + i;
+        out[i] = -op.sg * P.rho_pad;
+        if (t < L && t + T.klo <= L - 1) {
+            if (!(S[i] > 0.0)) sh.fragile = 1;
+            out[i] = op.sg * ((float)op.R + log2d(S[i])) * ibl;
+        }
+    }
+}
+
+// Opaque copy of the thread index: the per-mask loops take their index
+// arithmetic from it, so the compiler does not hoist one copy per mask out of
+// the loop and keep them all live.
+DEV int opaque_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// every mask trace for this thread's timesteps (tr[m][i]); ends with a barrier
+template <int N>
+DEV void mask_traces(const DevPlan& P, const KArgs& ka, const float* x, int L, int D, double* A, double* Bs,
+                     float (&tr)[N][FNO], FShared& sh)
+{
+#pragma unroll 1
+    for (int m = 0; m < N; ++m) {
+        FOp op;
+        fop_init(P, m, ka.params, op);
+        float out[FNO];
+        mask_trace(P, ka.tabs[m], op, x, L, D, A, Bs, out, sh, opaque_tid());
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) tr[k][i] = k == m ? out[i] : tr[k][i];
+    }
+    __syncthreads();
+}
+
+// root = smooth n-ary over the mask traces v[0..N) at one timestep (same
+// formula as the generic op); wts receives d root / d v_k
+template <int N>
+DEV float fused_root(const DevPlan& P, const float* params, const float* v, float* wts)
+{
+    const FusedDesc& F = P.fused;
+    if (N == 1 && !F.root_nary) {
+        if (wts) wts[0] = 1.f;
+        return v[0];
+    }
+    const float sg = F.nary_min ? -1.f : 1.f;
+    const float bl = params[F.nary_beta] * LOG2E;
+    float m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < N; ++k) m = fmaxf(m, sg * v[k]);
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) s += exp2f((sg * v[k] - m) * bl);
+    const float r = sg * (m + log2f(s) / bl);
+    if (wts) {
+        const float o = sg * r;
+#pragma unroll
+        for (int k = 0; k < N; ++k) wts[k] = exp2f((sg * v[k] - o) * bl);
+    }
+    return r;
+}
+
+// LDS: two padded fp64 arrays
+__host__ __device__ inline size_t fused_lds_bytes(int Lc)
+{
+    return (size_t)2 * px_len(Lc + FHOFF + FTAIL) * sizeof(double);
+}
+
+DEV bool fused_enter(const DevPlan& P, const KArgs& ka, FShared& sh)
+{
+    bool ok = true;
+    for (int m = 0; m < P.fused.n; ++m) ok = ok && ka.tabs[m].ok;
+    if (threadIdx.x == 0) sh.fragile = 0;
+    __syncthreads();
+    return ok;
+}
+
+DEV void fused_handoff(const KArgs& ka, int64_t b)
+{
+    if (threadIdx.x == 0) ka.list[atomicAdd(ka.list_count, 1)] = (int)b;
+}
+
+// 8 consecutive floats at p[c0 ..] (positions < L only)
+DEV void store8(float* p, int c0, int L, const float* v)
+{
+    if (c0 + FNO <= L && (((uintptr_t)(p + c0)) & 15) == 0) {
+        float4* q = (float4*)(p + c0);
+        q[0] = make_float4(v[0], v[1], v[2], v[3]);
+        q[1] = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < FNO; ++i)
+            if (c0 + i < L) p[c0 + i] = v[i];
+    }
+}
+
+DEV void load8f(const float* p, int c0, int L, float* v)
+{
+    if (c0 + FNO <= L && (((uintptr_t)(p + c0)) & 15) == 0) {
+        const float4* q = (const float4*)(p + c0);
+        const float4 a = q[0], b = q[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) v[i] = c0 + i < L ? p[c0 + i] : 0.f;
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(FNT) stl_fused_fwd(DevPlan plan, Batch bt, KArgs ka)
+{
+    extern __shared__ double fsm[];
+    __shared__ FShared sh;
+    const DevPlan& P = plan;
+    const int L = (int)bt.T, Lc = bt.Lcap, D = bt.D;
+    const int64_t b = blockIdx.x;
+    const int pl = px_len(Lc + FHOFF + FTAIL);
+    double* A = fsm;
+    double* Bs = A + pl;
+    if (!fused_enter(P, ka, sh)) {
+        if (ka.saved_flag && threadIdx.x == 0) ka.saved_flag[b] = 0;
+        fused_handoff(ka, b);
+        return;
+    }
+    const float* x = bt.x + b * (int64_t)L * D;
+    const int c0 = FNO * threadIdx.x;
+    float tr[N][FNO];
+    mask_traces<N>(P, ka, x, L, D, A, Bs, tr, sh);
+    if (sh.fragile) {
+        if (ka.saved_flag && threadIdx.x == 0) ka.saved_flag[b] = 0;
+        fused_handoff(ka, b);
+        return;
+    }
+    float r[FNO];
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) {
+        float v[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = tr[m][i];
+        r[i] = fused_root<N>(P, ka.params, v, nullptr);
+    }
+    store8(ka.root + b * (int64_t)L, c0, L, r);
+    if (ka.saved) {
+        // mask-node traces for the backward: [n][B][T], valid when the flag is 1
+#pragma unroll
+        for (int m = 0; m < N; ++m) store8(ka.saved + ((int64_t)m * bt.B + b) * L, c0, L, tr[m]);
+        if (threadIdx.x == 0) ka.saved_flag[b] = 1;
+    }
+}
+
+// d/da, d/db contributions of one band: p += sum_i k_i * sum_s dW[s] E[t_i + s]
+// (one weight set at a time: a derivative that is zero over the whole band
+// is skipped, e.g. d/db over the band around a)
+DEV void deriv_band(const double* A, int base, const double* W, int nz, int nW, const double* h, int sc, double k0,
+                    double& p)
+{
+    if (nW <= 0 || !nz) return;
+    double S[FNO];
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) S[i] = 0.0;
+    band_acc(A, base, W, 0, nW, S);
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) p = fma(ldexp(h[i], sc) * k0, S[i], p);     // sg G_m 2^{R - O_t} / beta
+}
+
+template <int N>
+__global__ void __launch_bounds__(FNT) stl_fused_bwd(DevPlan plan, Batch bt, KArgs ka)
+{
+    extern __shared__ double fsm[];
+    __shared__ FShared sh;
+    const DevPlan& P = plan;
+    const FusedDesc& F = P.fused;
+    const int L = (int)bt.T, Lc = bt.Lcap, D = bt.D;
+    const int64_t b = blockIdx.x;
+    const int pl = px_len(Lc + FHOFF + FTAIL);
+    double* A = fsm;             // terms E, then adjoint terms H (offset FHOFF), then block prefixes
+    double* Bs = A + pl;         // block suffixes
+    if (!fused_enter(P, ka, sh)) { fused_handoff(ka, b); return; }
+    const float* x = bt.x + b * (int64_t)L * D;
+    const int c0 = FNO * threadIdx.x;
+    float tr[N][FNO];
+    if (ka.saved_in && ka.saved_flag[b] == 1) {
+        // mask-node traces kept by the forward
+#pragma unroll
+        for (int m = 0; m < N; ++m) load8f(ka.saved_in + ((int64_t)m * bt.B + b) * L, c0, L, tr[m]);
+    } else {
+        // forward recompute of every mask trace (the n-ary adjoint needs all of them)
+        mask_traces<N>(P, ka, x, L, D, A, Bs, tr, sh);
+        if (sh.fragile) { fused_handoff(ka, b); return; }
+    }
+    // adjoint of each mask trace, G_m = G * d root / d trace_m (gm), and its
+    // exponent O_t = sg beta log2(e) trace_m (in place of the trace)
+    float gm[N][FNO];
+    {
+        float G8[FNO];
+        load8f(ka.G + b * (int64_t)L, c0, L, G8);
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) {
+            float v[N], wts[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = tr[k][i];
+            fused_root<N>(P, ka.params, v, wts);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const Instr& I = P.ins[F.ins[k]];
+                const float sg = (I.flags & F_MIN) ? -1.f : 1.f;
+                gm[k][i] = c0 + i < L ? G8[i] * wts[k] : 0.f;
+                tr[k][i] = sg * ka.params[I.beta] * LOG2E * v[k];
+            }
+        }
+    }
+    float* mp = ka.mask_part + b * P.n_masks * 2;
+    float* dx = ka.dx + b * (int64_t)L * D;
+#pragma unroll 1
+    for (int m = 0; m < N; ++m) {
+        const int tid = opaque_tid();
+        const int c0 = FNO * tid;
+        const MaskTab& T = ka.tabs[m];
+        const Instr& I = P.ins[F.ins[m]];
+        FOp op;
+        fop_init(P, m, ka.params, op);
+        float g[FNO], om[FNO];        // this mask's G_m and O_t
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) {
+            g[i] = gm[0][i];
+            om[i] = tr[0][i];
+#pragma unroll
+            for (int k = 1; k < N; ++k) {
+                g[i] = k == m ? gm[k][i] : g[i];
+                om[i] = k == m ? tr[k][i] : om[i];
+            }
+        }
+        float gv[FNO];
+        if (!T.any) {
+            if (I.mslot >= 0 && tid == 0) { mp[2 * I.mslot] = 0.f; mp[2 * I.mslot + 1] = 0.f; }
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) gv[i] = 0.f;
+        } else {
+            float z[FNO];
+            {
+                double e[FNO];
+                fused_terms(op, x, L, D, e, A, sh, z, tid);
+            }
+            // H_t = G_m[t] 2^{-O_t - Q}, Q the per-trajectory exponent of max |G_m 2^{-O}|
+            int qloc = INT_MIN;
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) {
+                const int t = c0 + i;
+                if (t < L && t + T.klo <= L - 1 && g[i] != 0.f) {
+                    int eg;
+                    frexpf(g[i], &eg);
+                    qloc = max(qloc, eg - (int)floorf(om[i]));
+                }
+            }
+            const int qm = wg_max_i(qloc, sh);
+            const int Q = qm == INT_MIN ? 0 : qm;
+            double h[FNO];
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) {
+                const int t = c0 + i;
+                h[i] = 0.0;
+                if (t < L && t + T.klo <= L - 1) {
+                    const float fl = floorf(om[i]);
+                    h[i] = ldexp((double)(g[i] * exp2f(fl - om[i])), -(int)fl - Q);
+                }
+            }
+            // d/da, d/db: sum_t sg G_m[t]/beta * sum_k dw_k 2^{z_{t+k} - O_t}, over the bands
+            double pa = 0.0, pb = 0.0;
+            if (c0 < L) {
+                const double k0 = (double)(op.sg / op.beta);
+                const int lim = L - c0, sc = op.R + Q;
+                const int nl = min(T.nWl, max(0, round8(lim - T.kl0)));
+                deriv_band(A, c0 + T.kl0, T.Dal, T.nz_al, nl, h, sc, k0, pa);
+                deriv_band(A, c0 + T.kl0, T.Dbl, T.nz_bl, nl, h, sc, k0, pb);
+                if (T.core) {
+                    const int nr = min(T.nWr, max(0, round8(lim - T.kr0)));
+                    deriv_band(A, c0 + T.kr0, T.Dar, T.nz_ar, nr, h, sc, k0, pa);
+                    deriv_band(A, c0 + T.kr0, T.Dbr, T.nz_br, nr, h, sc, k0, pb);
+                }
+            }
+            pa = wg_sum_d(pa, sh);     // (contains barriers: every E read above is done)
+            pb = wg_sum_d(pb, sh);
+            if (I.mslot >= 0 && tid == 0) { mp[2 * I.mslot] = (float)pa; mp[2 * I.mslot + 1] = (float)pb; }
+            // A now holds H (zero padded both sides)
+            for (int j = tid - FHOFF; j < 0; j += FNT) A[PX(j + FHOFF)] = 0.0;
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) {
+                const int j = c0 + i;
+                if (j < L + FTAIL) A[PX(j + FHOFF)] = (j < L) ? h[i] : 0.0;
+            }
+            for (int j = max(L, FNO * FNT) + tid; j < L + FTAIL; j += FNT) A[PX(j + FHOFF)] = 0.0;
+            __syncthreads();
+            // dx bands: transposed band sums over t of H
+            double Bd[FNO];
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) Bd[i] = 0.0;
+            if (c0 < L) {
+                {
+                    const int base = c0 - T.kl0 - T.nWl;
+                    band_acc(A, base + FHOFF, T.Wlr, max(0, round8(-base - FHOFF)), T.nWl + 8, Bd);
+                }
+                if (T.core) {
+                    const int base = c0 - T.kr0 - T.nWr;
+                    band_acc(A, base + FHOFF, T.Wrr, max(0, round8(-base - FHOFF)), T.nWr + 8, Bd);
+                }
+            }
+            // dx core: van Herk over t of H, windows [j - chi, j - clo] (heads at t % K == 0)
+            if (T.core) {
+                __syncthreads();                         // H reads done: A receives the block prefixes
+                fscan<false>(h, A, L, T.K, 0, sh, tid);
+                fscan<true>(h, Bs, L, T.K, 0, sh, tid);
+                const double wc = (double)T.wc;
+                const int K = T.K;
+                // window of j over t: [j - chi, j - clo]; j - clo <= L - 1 always, so
+                // only the start can be clipped (at t = 0, a block start)
+                const int stu = c0 - T.chi;
+                int rem = stu > 0 ? stu % K : 0;      // (max(0, j - chi)) % K
+#pragma unroll
+                for (int i = 0; i < FNO; ++i) {
+                    const int j = c0 + i;
+                    if (j < L) {
+                        const int st = max(0, stu + i), en = j - T.clo;
+                        if (st <= en) {
+                            const bool same = (stu + i < 0) ? en < K : rem == 0;
+                            const double c = same ? (rem == 0 ? A[PX(en)] : Bs[PX(st)]) : Bs[PX(st)] + A[PX(en)];
+                            Bd[i] = fma(wc, c, Bd[i]);
+                        }
+                    }
+                    if (stu + i >= 0 && ++rem == K) rem = 0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) {
+                // the term 2^{z_j - R} again, from the exponent kept in registers
+                gv[i] = c0 + i < L ? (float)ldexp(Bd[i] * exp2d_neg(z[i] - (float)op.R), op.R + Q) : 0.f;
+            }
+        }
+        // dx += w_m gv on this thread's rows (the first mask initialises them;
+        // each row is read and written by its owning thread only)
+        const float* cf = op.cf;
+        const int n8 = min(FNO, L - c0);
+        for (int i = 0; i < n8; ++i) {
+            float* row = dx + (int64_t)(c0 + i) * D;
+            for (int d = 0; d < D; ++d) row[d] = (m == 0 ? 0.f : row[d]) + cf[1 + d] * gv[i];
+        }
+    }
+}
+
+}  // namespace stlmi

@@ -71,6 +71,26 @@ DEV float sp_times_exp2(SP a, float z)
     return ldexpf(a.s * exp2f(z - c), clampe((long long)a.r + (long long)c));
 }
 
+// scaled pair with a double mantissa: signed sums of many terms (adjoints)
+struct SPD {
+    double s;
+    int r;
+};
+
+DEV SPD spd_add(SPD a, SP b)
+{
+    int m = max(a.r, b.r);
+    return SPD{ldexp(a.s, a.r - m) + ldexp((double)b.s, b.r - m), m};
+}
+
+// renormalised float scaled pair of a double-mantissa pair
+DEV SP spd_to_sp(SPD a)
+{
+    int e;
+    const double mant = frexp(a.s, &e);
+    return SP{(float)mant, clampe((long long)a.r + e)};
+}
+
 // value with index: hard max with ties to the lowest index
 struct VI {
     float v;
@@ -104,14 +124,23 @@ struct Shared {
     float f[8];
 };
 
+// storage index maps for scanned arrays: identity, or one pad element after
+// every 8 (conflict-free LDS access when each lane owns 8 consecutive elements)
+struct IdxId {
+    __device__ __forceinline__ int operator()(int p) const { return p; }
+};
+struct IdxPad {
+    __device__ __forceinline__ int operator()(int p) const { return p + (p >> 3); }
+};
+
 // In-place inclusive scan of x[0..n) within segments.  Forward scans have
-// segment heads at positions p % K == 0; reverse scans at p % K == K-1 and
-// at n-1.  K <= 0 means one segment.  Each thread scans a contiguous chunk
-// sequentially; chunk aggregates are combined with a segmented
-// Hillis-Steele pass; the carry is then applied to each chunk's head part.
-// Must be called by every thread of the work-group.
-template <class T, class Op>
-DEV void seg_scan(T* x, int n, int K, bool rev, T ident, Op op, Shared& sh)
+// segment heads at positions with (p + off) % K == 0; reverse scans at
+// (p + off) % K == K-1 and at n-1.  K <= 0 means one segment.  Each thread
+// scans a contiguous chunk sequentially; chunk aggregates are combined with a
+// segmented Hillis-Steele pass; the carry is then applied to each chunk's
+// head part.  Must be called by every thread of the work-group.
+template <class T, class Op, class SH, class IX = IdxId>
+DEV void seg_scan(T* x, int n, int K, bool rev, T ident, Op op, SH& sh, int off = 0, IX ix = IX())
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     T* shv = reinterpret_cast<T*>(sh.scan);
@@ -121,23 +150,23 @@ DEV void seg_scan(T* x, int n, int K, bool rev, T ident, Op op, Shared& sh)
     int head = 0;
     if (c0 < c1) {
         if (!rev) {
-            int rem = K > 0 ? c0 % K : c0;
+            int rem = K > 0 ? (c0 + off) % K : c0;
             for (int p = c0; p < c1; ++p) {
                 bool h = K > 0 ? (rem == 0) : (p == 0);
-                T v = x[p];
+                T v = x[ix(p)];
                 acc = h ? v : op(acc, v);
                 head |= h;
-                x[p] = acc;
+                x[ix(p)] = acc;
                 if (K > 0 && ++rem == K) rem = 0;
             }
         } else {
-            int rem = K > 0 ? (c1 - 1) % K : 0;
+            int rem = K > 0 ? (c1 - 1 + off) % K : 0;
             for (int p = c1 - 1; p >= c0; --p) {
                 bool h = (p == n - 1) || (K > 0 && rem == K - 1);
-                T v = x[p];
+                T v = x[ix(p)];
                 acc = h ? v : op(v, acc);
                 head |= h;
-                x[p] = acc;
+                x[ix(p)] = acc;
                 if (K > 0) rem = rem == 0 ? K - 1 : rem - 1;
             }
         }
@@ -163,19 +192,19 @@ DEV void seg_scan(T* x, int n, int K, bool rev, T ident, Op op, Shared& sh)
     if (c0 < c1 && nb >= 0 && nb < nt) {
         T carry = shv[nb];
         if (!rev) {
-            int rem = K > 0 ? c0 % K : c0;
+            int rem = K > 0 ? (c0 + off) % K : c0;
             for (int p = c0; p < c1; ++p) {
                 bool h = K > 0 ? (rem == 0) : (p == 0);
                 if (h) break;
-                x[p] = op(carry, x[p]);
+                x[ix(p)] = op(carry, x[ix(p)]);
                 if (K > 0 && ++rem == K) rem = 0;
             }
         } else {
-            int rem = K > 0 ? (c1 - 1) % K : 0;
+            int rem = K > 0 ? (c1 - 1 + off) % K : 0;
             for (int p = c1 - 1; p >= c0; --p) {
                 bool h = (p == n - 1) || (K > 0 && rem == K - 1);
                 if (h) break;
-                x[p] = op(x[p], carry);
+                x[ix(p)] = op(x[ix(p)], carry);
                 if (K > 0) rem = rem == 0 ? K - 1 : rem - 1;
             }
         }
@@ -211,15 +240,6 @@ DEV int lower_bound_i(const int* a, int n, int key)
 
 // ------------------------------------------------------------------ context
 
-struct Batch {
-    const float* x;
-    const int64_t* offsets;
-    const int32_t* order;
-    int64_t B;
-    int64_t T;
-    int32_t D;
-    int32_t Lcap;      // slot capacity (floats per slot)
-};
 
 struct Env {
     const DevPlan* P;
@@ -508,41 +528,66 @@ struct MaskInfo {
     bool any;
 };
 
-// weights w_k = max(sig(c(k-a)) - sig(c(k-b)) - eps, 0) for k in [0, L),
-// using sig(x) - sig(y) = sig(x) sig(-y) (1 - exp(-(x-y))) (no cancellation);
-// optionally d w/da and d w/db.  Finds the support and the core where both
-// sigmoid derivatives are below 2^-24 (|c(k-a)|, |c(k-b)| > 17), over which
-// w is constant to fp32 rounding.
-DEV MaskInfo mask_weights(const Env& e, const Instr& I, float* w, float* dwa, float* dwb)
+// Smooth-mask weight of offset k (Sec. VI):
+//   w_k = max(sig(c(k-a)) - sig(c(k-b)) - eps, 0)
+// using sig(x) - sig(y) = sig(x) sig(-y) (1 - exp(-(x-y))), which has no
+// cancellation, and its derivatives d w/da = -c sig'(c(k-a)),
+// d w/db = c sig'(c(k-b)) (zero where the clamp is active).
+struct MaskP {
+    float a, b, c, eps, band;
+    bool unb;
+};
+
+DEV MaskP mask_params(const float* pm, bool unb)
 {
-    const float* pm = e.params + I.mask;
-    const float a = pm[0], b = pm[1], c = pm[2], eps = pm[3];
-    const bool unb = I.flags & F_MASK_UNB;
-    const int L = e.L;
-    const float gap = unb ? INFINITY : c * (b - a);
-    const float band = 1.f - expf(-gap);
-    int* si = e.sh->ints;
+    MaskP m;
+    m.a = pm[0];
+    m.b = pm[1];
+    m.c = pm[2];
+    m.eps = pm[3];
+    m.unb = unb;
+    m.band = unb ? 1.f : 1.f - expf(-m.c * (m.b - m.a));
+    return m;
+}
+
+DEV float mask_wk(const MaskP& m, int k, float* dwa = nullptr, float* dwb = nullptr)
+{
+    const float x1 = m.c * ((float)k - m.a);
+    const float s1 = 1.f / (1.f + expf(-x1));
+    float wk, s2 = 0.f;
+    if (m.unb) {
+        wk = s1 - m.eps;
+    } else {
+        const float y1 = m.c * ((float)k - m.b);
+        s2 = 1.f / (1.f + expf(-y1));
+        const float sny = 1.f / (1.f + expf(y1));
+        wk = s1 * sny * m.band - m.eps;
+    }
+    wk = wk > 0.f ? wk : 0.f;
+    if (dwa) {
+        *dwa = wk > 0.f ? -m.c * s1 * (1.f - s1) : 0.f;
+        *dwb = (wk > 0.f && !m.unb) ? m.c * s2 * (1.f - s2) : 0.f;
+    }
+    return wk;
+}
+
+// Weights for k in [0, L) (stored when w != NULL), the support {w > 0} and
+// the core where both sigmoid derivatives are below 2^-24 (|c(k-a)|,
+// |c(k-b)| > 17), over which w is constant to fp32 rounding.
+template <class SH>
+DEV MaskInfo mask_info(const float* params, const Instr& I, int L, SH& sh, float* w, float* dwa, float* dwb)
+{
+    const MaskP mp = mask_params(params + I.mask, I.flags & F_MASK_UNB);
+    const bool unb = mp.unb;
+    int* si = sh.ints;
     if (threadIdx.x == 0) { si[0] = L; si[1] = -1; }
     __syncthreads();
     int lo = L, hi = -1;
     for (int k = threadIdx.x; k < L; k += blockDim.x) {
-        const float x1 = c * ((float)k - a);
-        const float s1 = 1.f / (1.f + expf(-x1));
-        float wk, s2 = 0.f;
-        if (unb) {
-            wk = s1 - eps;
-        } else {
-            const float y1 = c * ((float)k - b);
-            s2 = 1.f / (1.f + expf(-y1));
-            const float sny = 1.f / (1.f + expf(y1));
-            wk = s1 * sny * band - eps;
-        }
-        wk = wk > 0.f ? wk : 0.f;
-        w[k] = wk;
-        if (dwa) {
-            dwa[k] = wk > 0.f ? -c * s1 * (1.f - s1) : 0.f;
-            dwb[k] = (wk > 0.f && !unb) ? c * s2 * (1.f - s2) : 0.f;
-        }
+        float da, db;
+        const float wk = mask_wk(mp, k, dwa ? &da : nullptr, &db);
+        if (w) w[k] = wk;
+        if (dwa) { dwa[k] = da; dwb[k] = db; }
         if (wk > 0.f) { lo = min(lo, k); hi = max(hi, k); }
     }
     atomicMin(&si[0], lo);
@@ -552,6 +597,7 @@ DEV MaskInfo mask_weights(const Env& e, const Instr& I, float* w, float* dwa, fl
     mi.klo = si[0];
     mi.khi = si[1];
     mi.any = mi.klo <= mi.khi;
+    const float a = mp.a, b = mp.b, c = mp.c;
     if (c > 0.f && mi.any) {
         mi.clo = max(mi.klo, (int)fminf(ceilf(a + 17.f / c), 2e9f));
         mi.chi = unb ? mi.khi : min(mi.khi, (int)fmaxf(floorf(b - 17.f / c), -2e9f));
@@ -560,9 +606,14 @@ DEV MaskInfo mask_weights(const Env& e, const Instr& I, float* w, float* dwa, fl
         mi.chi = 0;
     }
     if (mi.clo > mi.chi) { mi.clo = 1; mi.chi = 0; mi.wc = 0.f; }
-    else mi.wc = w[(mi.clo + mi.chi) / 2];
+    else mi.wc = mask_wk(mp, (mi.clo + mi.chi) / 2);
     __syncthreads();
     return mi;
+}
+
+DEV MaskInfo mask_weights(const Env& e, const Instr& I, float* w, float* dwa, float* dwb)
+{
+    return mask_info(e.params, I, e.L, *e.sh, w, dwa, dwb);
 }
 
 // ------------------------------------------------------------------ until
@@ -755,15 +806,17 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
         __syncthreads();
         const float lwc = core ? log2f(mi.wc) : 0.f;
         for (int t = threadIdx.x; t < L; t += blockDim.x) {
-            SP a = core ? acc[t] : sp_zero();
-            a.s *= core ? mi.wc : 0.f;
+            // band terms are summed one by one (up to a few hundred of them):
+            // accumulate with a double mantissa so the error does not grow with the count
+            SPD a{0.0, SP_NEG};
+            if (core) a = spd_add(a, SP{acc[t].s * mi.wc, acc[t].r});
             const int b0 = mi.klo, b1 = core ? mi.clo - 1 : mi.khi;
-            for (int k = b0; k <= b1 && t + k < L; ++k) a = sp_add(a, SP{w[k] * E[t + k].s, E[t + k].r});
+            for (int k = b0; k <= b1 && t + k < L; ++k) a = spd_add(a, SP{w[k] * E[t + k].s, E[t + k].r});
             if (core)
                 for (int k = mi.chi + 1; k <= mi.khi && t + k < L; ++k)
-                    a = sp_add(a, SP{w[k] * E[t + k].s, E[t + k].r});
+                    a = spd_add(a, SP{w[k] * E[t + k].s, E[t + k].r});
             const bool any = mi.any && t + mi.klo <= L - 1;
-            out[t] = any ? sg * sp_log2(a) / bl : -sg * e.P->rho_pad;
+            out[t] = any ? sg * sp_log2(spd_to_sp(a)) / bl : -sg * e.P->rho_pad;
         }
         (void)lwc;
         break;
@@ -894,21 +947,21 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
         __syncthreads();
         // d/da, d/db: per t, sum over the support bands of dw_k 2^{z_{t+k} - O_t}
         for (int t = threadIdx.x; t < nvalid; t += blockDim.x) {
-            SP aa = sp_zero(), ab = sp_zero();
+            SPD aa{0.0, SP_NEG}, ab{0.0, SP_NEG};
             const int b0 = mi.klo, b1 = core ? mi.clo - 1 : mi.khi;
             for (int k = b0; k <= b1 && t + k < L; ++k) {
-                aa = sp_add(aa, SP{dwa[k] * E[t + k].s, E[t + k].r});
-                ab = sp_add(ab, SP{dwb[k] * E[t + k].s, E[t + k].r});
+                aa = spd_add(aa, SP{dwa[k] * E[t + k].s, E[t + k].r});
+                ab = spd_add(ab, SP{dwb[k] * E[t + k].s, E[t + k].r});
             }
             if (core)
                 for (int k = mi.chi + 1; k <= mi.khi && t + k < L; ++k) {
-                    aa = sp_add(aa, SP{dwa[k] * E[t + k].s, E[t + k].r});
-                    ab = sp_add(ab, SP{dwb[k] * E[t + k].s, E[t + k].r});
+                    aa = spd_add(aa, SP{dwa[k] * E[t + k].s, E[t + k].r});
+                    ab = spd_add(ab, SP{dwb[k] * E[t + k].s, E[t + k].r});
                 }
             const float O = sg * bl * out[t];
             const float ib = sg * g[t] / pbeta(e, I);
-            pa += ib * sp_times_exp2(aa, -O);
-            pb += ib * sp_times_exp2(ab, -O);
+            pa += ib * sp_times_exp2(spd_to_sp(aa), -O);
+            pb += ib * sp_times_exp2(spd_to_sp(ab), -O);
         }
         pa = wg_sum(pa, *e.sh);
         pb = wg_sum(pb, *e.sh);
@@ -920,14 +973,15 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
             win_smooth_adj_sum(e, h, (SP*)S(e, 2), res, mi.clo, khi, nvalid);
         }
         for (int j = threadIdx.x; j < L; j += blockDim.x) {
-            SP a = core ? res[j] : sp_zero();
-            a.s *= core ? mi.wc : 0.f;
+            // signed adjoint terms: accumulate with a double mantissa
+            SPD a{0.0, SP_NEG};
+            if (core) a = spd_add(a, SP{res[j].s * mi.wc, res[j].r});
             const int b0 = mi.klo, b1 = core ? mi.clo - 1 : mi.khi;
-            for (int k = b0; k <= b1 && j - k >= 0; ++k) a = sp_add(a, SP{w[k] * hb[j - k].s, hb[j - k].r});
+            for (int k = b0; k <= b1 && j - k >= 0; ++k) a = spd_add(a, SP{w[k] * hb[j - k].s, hb[j - k].r});
             if (core)
                 for (int k = mi.chi + 1; k <= mi.khi && j - k >= 0; ++k)
-                    a = sp_add(a, SP{w[k] * hb[j - k].s, hb[j - k].r});
-            gu[j] = sp_times_exp2(a, sg * bl * u[j]);
+                    a = spd_add(a, SP{w[k] * hb[j - k].s, hb[j - k].r});
+            gu[j] = sp_times_exp2(spd_to_sp(a), sg * bl * u[j]);
         }
         break;
     }
@@ -963,19 +1017,8 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
 
 // ------------------------------------------------------------------ kernels
 
-struct KArgs {
-    const float* params;
-    float* root;           // forward: [N_total]
-    float* nodes;          // forward: [n_nodes][N_total] or NULL
-    int64_t n_total;
-    const float* G;        // backward: upstream gradient [N_total]
-    float* dx;             // backward: [N_total, D]
-    float* mask_part;      // backward: [B][n_masks][2]
-    float* garena;         // global slot arenas (NULL: LDS)
-    int64_t arena_floats;  // floats per arena (slots + scratch)
-    int* counter;          // persistent scheduler counter
-    int persistent;
-};
+struct MaskTab;
+
 
 DEV bool next_item(const KArgs& ka, Shared& sh, int64_t& item, bool first)
 {
@@ -1003,8 +1046,9 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
     bool first = true;
     while (next_item(ka, sh, item, first)) {
         first = false;
-        if (item >= bt.B) break;
-        const int64_t b = bt.order ? (int64_t)bt.order[item] : item;
+        const int64_t nitems = ka.list_mode ? (int64_t)*ka.list_count : bt.B;
+        if (item >= nitems) break;
+        const int64_t b = ka.list_mode ? (int64_t)ka.list[item] : (bt.order ? (int64_t)bt.order[item] : item);
         const int64_t off = bt.offsets ? bt.offsets[b] : b * bt.T;
         const int64_t len = bt.offsets ? bt.offsets[b + 1] - off : bt.T;
         if (len <= 0) continue;
@@ -1083,7 +1127,19 @@ __global__ void stl_reduce_params(const float* part, int64_t B, int n_masks, Dev
     }
 }
 
-__global__ void stl_zero_counter(int* c) { if (threadIdx.x == 0) c[0] = 0; }
+__global__ void stl_zero_counter(int* c) { if (threadIdx.x < 2) c[threadIdx.x] = 0; }
+
+__global__ void stl_fill_int(int* p, int64_t n, int v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace stlmi
+
+#include "stl_fused.h"
+
+namespace stlmi {
 
 }  // namespace stlmi
 
@@ -1120,9 +1176,67 @@ hipError_t set_max_lds(size_t bytes)
     return e1 != hipSuccess ? e1 : e2;
 }
 
+size_t fused_lds(int Lc, int n, int D, bool bwd)
+{
+    (void)n;
+    (void)D;
+    (void)bwd;
+    return fused_lds_bytes(Lc);
+}
+
+int fused_max_T() { return FNT * FNO; }
+
+size_t mask_tab_bytes() { return sizeof(MaskTab); }
+
+hipError_t launch_fused(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs& ka, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(stl_mask_tables, dim3(plan.fused.n), dim3(256), 0, s, plan, ka.params, (int)bt.T,
+                       (MaskTab*)ka.tabs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)bt.B), block(FNT);
+#define STLMI_FUSED_CASE(NN)                                                              \
+    case NN:                                                                              \
+        if (bwd)                                                                          \
+            hipLaunchKernelGGL(stl_fused_bwd<NN>, grid, block, lds, s, plan, bt, ka);     \
+        else                                                                              \
+            hipLaunchKernelGGL(stl_fused_fwd<NN>, grid, block, lds, s, plan, bt, ka);     \
+        break;
+    switch (plan.fused.n) {
+        STLMI_FUSED_CASE(1)
+        STLMI_FUSED_CASE(2)
+        STLMI_FUSED_CASE(3)
+        STLMI_FUSED_CASE(4)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef STLMI_FUSED_CASE
+    return hipGetLastError();
+}
+
+hipError_t set_max_lds_fused(size_t bytes)
+{
+    const void* fns[] = {(const void*)stl_fused_fwd<1>, (const void*)stl_fused_fwd<2>, (const void*)stl_fused_fwd<3>,
+                         (const void*)stl_fused_fwd<4>, (const void*)stl_fused_bwd<1>, (const void*)stl_fused_bwd<2>,
+                         (const void*)stl_fused_bwd<3>, (const void*)stl_fused_bwd<4>};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_zero_counter(int* c, hipStream_t s)
 {
     hipLaunchKernelGGL(stl_zero_counter, dim3(1), dim3(64), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(stl_fill_int, dim3(grid), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -55,6 +55,19 @@ struct Instr {                  // 40 bytes
 };
 static_assert(sizeof(Instr) == 40, "Instr layout");
 
+// Fused fast path (set by the plan compiler when the formula has the shape
+// root = smooth And/Or over up to 4 smooth-mask Eventually/Always nodes, each
+// over a linear predicate, or a single such mask node): one kernel computes
+// the whole formula per trajectory with fp64 accumulation.
+struct FusedDesc {
+    int8_t n;                               // number of mask nodes (0: no fused path)
+    int8_t root_nary;                       // 1: root is the n-ary node, 0: root is the mask node
+    int8_t nary_min;                        // the n-ary node is an And
+    int8_t nary_beta;                       // its beta parameter index
+    int8_t ins[4];                          // instruction index of each mask node
+    int8_t pred[4];                         // instruction index of its linear predicate
+};
+
 struct DevPlan {
     int32_t n_ins;
     int32_t n_slots_fwd;
@@ -68,6 +81,7 @@ struct DevPlan {
     float rho_pad;
     int16_t pred_ins[MAX_PRED];             // instruction index of each predicate
     int8_t mask_param[MAX_MASKS];           // parameter index of each learnable mask
+    FusedDesc fused;
     Instr ins[MAX_INSTR];
     float coef[MAX_COEF];
 };
@@ -75,5 +89,39 @@ struct DevPlan {
 // Predicate coefficient layout in coef[] at offset o:
 //   linear: [0] c, [1 .. 1+D) w
 //   norm:   [0] m, [1] r, [2] sign, [3..7) p, [7 .. 7+m*D) A (row-major)
+
+// Launch arguments shared by the host launchers and the kernels.
+struct MaskTab;
+
+struct Batch {
+    const float* x;
+    const int64_t* offsets;
+    const int32_t* order;
+    int64_t B;
+    int64_t T;
+    int32_t D;
+    int32_t Lcap;      // slot capacity (floats per slot)
+};
+
+struct KArgs {
+    const float* params;
+    float* root;           // forward: [N_total]
+    float* nodes;          // forward: [n_nodes][N_total] or NULL
+    int64_t n_total;
+    const float* G;        // backward: upstream gradient [N_total]
+    float* dx;             // backward: [N_total, D]
+    float* mask_part;      // backward: [B][n_masks][2]
+    float* garena;         // global slot arenas (NULL: LDS)
+    int64_t arena_floats;  // floats per arena (slots + scratch)
+    int* counter;          // persistent scheduler counter
+    int persistent;
+    int* list_count;       // fused path: number of trajectories sent to the generic executor
+    int* list;             // fused path: their indices
+    int list_mode;         // generic executor processes list[0 .. *list_count)
+    const MaskTab* tabs;   // fused path: per-mask tables (workspace)
+    float* saved;          // fused forward: mask-node traces out ([n][B][T]) or NULL
+    const float* saved_in; // fused backward: mask-node traces in, or NULL (recompute)
+    int* saved_flag;       // [B]: 1 where the saved traces of a trajectory are valid
+};
 
 }  // namespace stlmi

@@ -47,13 +47,13 @@ class Batch(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("global_slots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
 
 
 _lib = None
 EXPORTS = ["stl_compile", "stl_plan_destroy", "stl_plan_info", "stl_workspace_size", "stl_forward",
-           "stl_backward", "stl_last_error", "stl_lpt_order", "stl_autotune", "stl_graph_capture",
-           "stl_graph_launch", "stl_graph_destroy"]
+           "stl_backward", "stl_saved_size", "stl_forward_saving", "stl_backward_saved", "stl_last_error",
+           "stl_lpt_order", "stl_autotune", "stl_graph_capture", "stl_graph_launch", "stl_graph_destroy"]
 
 
 def lib():
@@ -73,6 +73,10 @@ def lib():
                                      ctypes.POINTER(sz)]
     L.stl_forward.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, sz, ctypes.POINTER(Launch), vp]
     L.stl_backward.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, sz, ctypes.POINTER(Launch), vp]
+    L.stl_saved_size.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(sz)]
+    L.stl_forward_saving.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, sz, vp, sz, ctypes.POINTER(Launch), vp]
+    L.stl_backward_saved.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, sz, vp, vp, vp, vp, sz,
+                                     ctypes.POINTER(Launch), vp]
     L.stl_last_error.restype = ctypes.c_char_p
     L.stl_lpt_order.argtypes = [ctypes.POINTER(i64), i64, ctypes.POINTER(i32)]
     L.stl_autotune.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(Launch),
@@ -81,10 +85,9 @@ def lib():
                                     vp, ctypes.POINTER(vp)]
     L.stl_graph_launch.argtypes = [vp, vp]
     L.stl_graph_destroy.argtypes = [vp]
-    for f in ["stl_compile", "stl_plan_destroy", "stl_plan_info", "stl_workspace_size", "stl_forward",
-              "stl_backward", "stl_lpt_order", "stl_autotune", "stl_graph_capture", "stl_graph_launch",
-              "stl_graph_destroy"]:
-        getattr(L, f).restype = ctypes.c_int
+    for f in EXPORTS:
+        if f != "stl_last_error":
+            getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
 
@@ -271,8 +274,19 @@ class Plan:
             self._ws[key] = ws
         return ws
 
-    def forward(self, x, pvec, offsets=None, order=None, T=None, node_traces=False, launch=None):
-        """Root robustness trace (float32) and optionally every node trace."""
+    def saved_buffer(self, x, offsets=None, T=None):
+        """Device buffer for the mask-node traces kept between forward and backward (``stl_saved_size``)."""
+        import torch
+        bt = self._batch(x, offsets, None, T)
+        n = ctypes.c_size_t()
+        _check(lib().stl_saved_size(self._h, ctypes.byref(bt), ctypes.byref(n)))
+        return torch.empty(max(256, n.value), dtype=torch.uint8, device=x.device)
+
+    def forward(self, x, pvec, offsets=None, order=None, T=None, node_traces=False, launch=None, saved=None):
+        """Root robustness trace (float32) and optionally every node trace.
+
+        ``saved`` (from ``saved_buffer``): also keep the mask-node traces for
+        ``backward(..., saved=...)`` (``stl_forward_saving``)."""
         import torch
         _require_gpu(torch, x)
         x = x.contiguous()
@@ -281,17 +295,26 @@ class Plan:
         root = torch.empty(N, dtype=torch.float32, device=x.device)
         nodes = torch.empty((self.n_nodes, N), dtype=torch.float32, device=x.device) if node_traces else None
         ws = self.workspace(torch, bt, launch, x.device)
-        _check(lib().stl_forward(self._h, ctypes.byref(bt), _ptr(pvec), _ptr(root), _ptr(nodes), _ptr(ws),
-                                 ws.numel(), None if launch is None else ctypes.byref(launch),
-                                 _stream(torch, x.device)))
+        lp = None if launch is None else ctypes.byref(launch)
+        if saved is not None:
+            if node_traces:
+                raise ValueError("node_traces and saved cannot be combined")
+            _check(lib().stl_forward_saving(self._h, ctypes.byref(bt), _ptr(pvec), _ptr(root), _ptr(saved),
+                                            saved.numel(), _ptr(ws), ws.numel(), lp, _stream(torch, x.device)))
+        else:
+            _check(lib().stl_forward(self._h, ctypes.byref(bt), _ptr(pvec), _ptr(root), _ptr(nodes), _ptr(ws),
+                                     ws.numel(), lp, _stream(torch, x.device)))
         if offsets is None:
             root = root.view(x.shape[0], x.shape[1])
             if nodes is not None:
                 nodes = nodes.view(self.n_nodes, x.shape[0], x.shape[1])
         return (root, nodes) if node_traces else root
 
-    def backward(self, x, G, pvec, offsets=None, order=None, T=None, launch=None, want_params=True):
-        """(dx, dparams-vector) for the upstream gradient G of the root trace."""
+    def backward(self, x, G, pvec, offsets=None, order=None, T=None, launch=None, want_params=True, saved=None):
+        """(dx, dparams-vector) for the upstream gradient G of the root trace.
+
+        ``saved``: the buffer filled by ``forward(..., saved=...)`` on the
+        same x and parameters (``stl_backward_saved``)."""
         import torch
         _require_gpu(torch, x)
         x = x.contiguous()
@@ -300,9 +323,14 @@ class Plan:
         dx = torch.empty_like(x)
         gp = torch.empty(max(1, self.n_params), dtype=torch.float32, device=x.device) if want_params else None
         ws = self.workspace(torch, bt, launch, x.device)
-        _check(lib().stl_backward(self._h, ctypes.byref(bt), _ptr(pvec), _ptr(G), _ptr(dx), _ptr(gp), _ptr(ws),
-                                  ws.numel(), None if launch is None else ctypes.byref(launch),
-                                  _stream(torch, x.device)))
+        lp = None if launch is None else ctypes.byref(launch)
+        if saved is not None:
+            _check(lib().stl_backward_saved(self._h, ctypes.byref(bt), _ptr(pvec), _ptr(saved), saved.numel(),
+                                            _ptr(G), _ptr(dx), _ptr(gp), _ptr(ws), ws.numel(), lp,
+                                            _stream(torch, x.device)))
+        else:
+            _check(lib().stl_backward(self._h, ctypes.byref(bt), _ptr(pvec), _ptr(G), _ptr(dx), _ptr(gp), _ptr(ws),
+                                      ws.numel(), lp, _stream(torch, x.device)))
         return dx, gp
 
 
@@ -390,22 +418,25 @@ def make_autograd():
     import torch
 
     class StlRobustness(torch.autograd.Function):
-        """Robustness trace with a hand-written backward (``stl_backward``).
+        """Robustness trace with a hand-written backward.
 
-        Saves only x and the parameter vector: the node traces are recomputed
-        on chip in the backward kernel.
+        Saves x, the parameter vector and the mask-node traces of the fused
+        path (``stl_forward_saving`` / ``stl_backward_saved``); anything else
+        is recomputed on chip in the backward kernel.
         """
 
         @staticmethod
         def forward(ctx, plan, x, pvec):
             ctx.plan = plan
-            ctx.save_for_backward(x, pvec)
-            return plan.forward(x, pvec)
+            x = x.contiguous()
+            saved = plan.saved_buffer(x)
+            ctx.save_for_backward(x, pvec, saved)
+            return plan.forward(x, pvec, saved=saved)
 
         @staticmethod
         def backward(ctx, G):
-            x, pvec = ctx.saved_tensors
-            dx, gp = ctx.plan.backward(x, G, pvec)
+            x, pvec, saved = ctx.saved_tensors
+            dx, gp = ctx.plan.backward(x, G, pvec, saved=saved)
             return None, dx, gp[: pvec.numel()]
 
     return StlRobustness

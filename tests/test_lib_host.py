@@ -13,10 +13,10 @@ from paper_2501_04194_amd import stl, workloads as W
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    txt = open(os.path.join(ROOT, "include", "stlmi.h")).read()
+def _declared(header="stlmi.h"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     # function declarations: a return type, the name, an opening parenthesis
-    return sorted(set(re.findall(r"^(?:stl_status|const char\*)\s+(stl_[a-z_]+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^(?:stl_status|const char\*)\s+(stl_[a-z_0-9]+)\s*\(", txt, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -26,6 +26,20 @@ def test_library_exports_every_declared_symbol():
     for nm in names:
         assert hasattr(L, nm), nm
     assert set(names) == set(stl.EXPORTS)
+    mlp_names = _declared("stlmi_mlp.h")
+    assert len(mlp_names) == 7
+    for nm in mlp_names:
+        assert hasattr(L, nm), nm
+
+
+def test_mlp_entry_points_validate_arguments():
+    from paper_2501_04194_amd import mlp as M
+    L = M._lib()
+    assert L.stl_bf16_gemm(None, 1, 1, None, 1, 1, -1, 2, 2, None, 0, None, 0, 0, None, 0, None) == -1
+    assert L.stl_cast_bf16(None, None, 5, None) == -1
+    assert L.stl_adam_step(None, None, None, None, None, 4, 0.1, 0.9, 0.99, 1e-8, 0, None) == -1
+    assert "stl_adam_step" in stl.lib().stl_last_error().decode()
+    assert L.stl_cast_bf16(None, None, 0, None) == 0          # empty is fine
 
 
 def _compile_raw(nodes, child, root, preds=(), D=2, n_params=0):
