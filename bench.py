@@ -48,6 +48,94 @@ def cpu_baseline(n_traj=128):
                       % (n_traj, dt)}
 
 
+def bench_graph(args):
+    """Secondary workloads through the hipGraph-captured forward + backward.
+
+    smooth_until: B=1024, T=1000, D=4, Always[0,inf)(Eventually~[0,50](x0 > 0.2))
+    and~ (x1 < 0.5 Until~[20,200] x2 + x3 > 0.1), beta=10, gradient w.r.t. x
+    (56 B/step: x 16 + root 4, x 16 + G 4 + dx 16).
+    ragged: 10,000 trajectories of lengths U{64..8192}, D=3, the same formula,
+    packed with int64 offsets, LPT order and the autotuned launch (44 B/step).
+    """
+    import torch
+    from paper_2501_04194_amd import stl, workloads as W
+    import oracle
+
+    dev = torch.device("cuda:0")
+    if args.workload == "smooth_until":
+        spec, params, x = W.workload(1)
+        B, T, D = x.shape
+        offsets = None
+        n_steps = B * T
+        bpstep = (4 * D + 4) + (4 * D + 4 + 4 * D)     # fwd (x + root) + bwd (x + G + dx)
+        cfg = {"workload": W.CONFIGS[1]["name"], "B": B, "T": T, "D": D, "beta": 10.0}
+    else:
+        spec, params, x, offsets = W.ragged_workload()
+        B = len(offsets) - 1
+        D = x.shape[1]
+        T = int(np.max(np.diff(offsets)))
+        n_steps = int(offsets[-1])
+        bpstep = (4 * D + 4) + (4 * D + 4 + 4 * D)
+        cfg = {"workload": W.CONFIGS[3]["name"], "trajectories": B, "total_steps": n_steps, "D": D,
+               "max_len": T, "beta": 10.0}
+    plan = stl.Plan(spec, D, params)
+    pv = torch.from_numpy(plan.param_vector()).to(dev)
+    xd = torch.from_numpy(x).to(dev)
+    Gh = W.upstream_grad(101 if offsets is None else 103, (n_steps,) if offsets is not None else (B, T))
+    Gd = torch.from_numpy(Gh).to(dev)
+    od = order = None
+    if offsets is not None:
+        od = torch.from_numpy(offsets).to(dev)
+        order = torch.from_numpy(stl.lpt_order(offsets)).to(dev)
+    launch, tune_ms = stl.autotune(plan, xd, pv, Gd, offsets=od, order=order, T=T)
+    g = stl.Graph(plan, xd, pv, Gd, offsets=od, order=order, T=T, launch=launch)
+    for _ in range(args.warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        g.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1) / args.steps
+    value = n_steps / (ms * 1e-3)
+    achieved = bpstep * n_steps / (ms * 1e-3) / 1e9
+    cfg.update({"launch": {"threads": launch.threads, "wg_per_cu": launch.wg_per_cu,
+                           "global_slots": launch.global_slots}, "graph": True})
+    out = {"metric": "fwd+bwd signal-steps/s (%s)" % cfg["workload"], "value": value, "unit": "signal-steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": cfg,
+           "wall_s": t_wall,
+           "roofline": {"bound": "hbm", "kernel": "stl_exec_kernel (forward + backward graph)",
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
+    if not args.no_cpu_baseline:
+        oracle.build()
+        if offsets is None:
+            n = B                       # the whole batch (a few seconds of CPU work)
+            xs, Gs, offs = x[:n], Gh[:n], None
+            sample = "%d of the %d trajectories (T=%d)" % (n, B, T)
+            steps = n * T
+        else:
+            n = 400                     # about ten seconds of CPU work
+            offs = offsets[: n + 1]
+            xs, Gs = x[: offs[-1]], Gh[: offs[-1]]
+            sample = "the first %d of the %d trajectories (%d steps)" % (n, B, int(offs[-1]))
+            steps = int(offs[-1])
+        t0 = time.perf_counter()
+        oracle.forward(spec, xs, params={}, offsets=offs)
+        oracle.backward(spec, xs, Gs, params={}, offsets=offs)
+        dt = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": steps / dt, "unit": "signal-steps/s", "cores": cores, "kind": "oracle",
+                               "sample": sample + ", forward + backward, FP64 C oracle with OpenMP, %.2f s" % dt}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,11 +145,25 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-traj", type=int, default=128)
     ap.add_argument("--recompute", action="store_true", help="backward recomputes the node traces")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy a 256 MiB buffer three times (the reference kernel for HBM counters)")
+    ap.add_argument("--workload", default="smooth_mask", choices=["smooth_mask", "smooth_until", "ragged"],
+                    help="smooth_mask: the headline workload; the others are secondary measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (trajectories shard with no "
               "communication; see the design notes).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(64 * 1024 * 1024, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload != "smooth_mask":
+        return bench_graph(args)
 
     import torch
     from paper_2501_04194_amd import stl, workloads as W

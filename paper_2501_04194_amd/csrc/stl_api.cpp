@@ -689,7 +689,8 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
         if (saved == 1 && !g.fused && launch_fill_int(flags, bt->B, 0, st) != hipSuccess)
             return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
-    if ((g.persistent || g.fused) && launch_zero_counter(ka.counter, st) != hipSuccess)
+    // (the fused path's table kernel resets the counters itself)
+    if (g.persistent && !g.fused && launch_zero_counter(ka.counter, st) != hipSuccess)
         return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
     hipError_t e;
     if (g.fused) {

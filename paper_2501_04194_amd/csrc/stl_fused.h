@@ -30,9 +30,13 @@ constexpr int FNT = 256;          // threads per work-group
 constexpr int FNO = 8;            // consecutive timesteps per thread
 constexpr int FNW = FNT / 64;     // waves per work-group
 constexpr int FMAXB = 512;        // max padded width of one band weight array
-constexpr int FHOFF = 32;         // low-side zero padding of the adjoint array (elements)
-constexpr int FTAIL = 32;         // high-side zero padding (elements)
+constexpr int FHOFF = 32;         // room for the shift of the term / adjoint copies (elements)
+constexpr int FTAIL = 16;         // high-side zero padding (elements)
 constexpr int FMAXN = 4;          // mask nodes under the root
+// waves per SIMD the kernels are compiled for (VGPR budget 512 / waves); LDS
+// allows four work-groups (of one wave per SIMD) per compute unit
+constexpr int FWAVES_FWD = 4;
+constexpr int FWAVES_BWD = 3;
 
 // Per-mask tables, computed once per call by stl_mask_tables.
 struct MaskTab {
@@ -40,13 +44,13 @@ struct MaskTab {
     int any;                    // support {w > 0} is non-empty
     int klo, khi, clo, chi;     // support and constant core (clo > chi: no core)
     int core, K, off;           // van Herk block length and head offset (core only)
-    int kl0, nWl, kr0, nWr;     // bands: padded start offsets and widths (multiples of 8)
+    int kl0, nWl, kr0, nWr;     // bands: first offset and width (a multiple of 8; zero weights pad it)
     int nz_al, nz_bl;           // left band: d/da, d/db weights not all zero
     int nz_ar, nz_br;           // right band: same
     float wc;                   // core weight
     double Wl[FMAXB], Wr[FMAXB];                          // band weights
     double Dal[FMAXB], Dar[FMAXB], Dbl[FMAXB], Dbr[FMAXB];  // d w / d a, d w / d b
-    double Wlr[FMAXB + 8], Wrr[FMAXB + 8];                // reversed, for transposed sums
+    double Wlr[FMAXB + 8], Wrr[FMAXB + 8];                // reversed (W[nW-1-s]), for transposed sums
 };
 
 struct FShared {
@@ -59,7 +63,6 @@ struct FShared {
 
 DEV int PX(int j) { return j + (j >> 3); }
 __host__ __device__ constexpr int px_len(int n) { return n + (n >> 3) + 16; }
-DEV int floor8(int v) { return v & ~7; }
 DEV int round8(int v) { return (v + 7) & ~7; }
 
 DEV int wg_max_i(int v, FShared& sh)
@@ -169,12 +172,18 @@ DEV void fscan(const double* vin, double* out, int n, int K, int off, FShared& s
 
 // ------------------------------------------------------------------ band sums
 
+// The weight tables are written by an earlier launch and only read here:
+// reading them through the constant address space lets uniform reads become
+// scalar loads (weights as scalar FMA operands, no vector memory traffic).
+typedef const __attribute__((address_space(4))) double* cdptr;
+
 // S[i] += sum_{dk<8} W[dk] * window[i + dk], window = (a[0..7], b[0..7])
 DEV void fma_block(double* S, const double* __restrict__ W, const double* a, const double* b)
 {
+    const cdptr Wc = (cdptr)W;
 #pragma unroll
     for (int dk = 0; dk < 8; ++dk) {
-        const double w = W[dk];
+        const double w = Wc[dk];
 #pragma unroll
         for (int i = 0; i < FNO; ++i) {
             const int p = i + dk;
@@ -183,38 +192,53 @@ DEV void fma_block(double* S, const double* __restrict__ W, const double* a, con
     }
 }
 
-DEV void load8(double* r, const double* A)
+// element index of the zero block (8 zeros) at the end of each LDS array
+__host__ __device__ constexpr int fused_zero_at(int Lc) { return (Lc + FHOFF + FTAIL + 7) & ~7; }
+// padded length of each LDS array (doubles)
+__host__ __device__ constexpr int fused_arr_len(int Lc) { return px_len(fused_zero_at(Lc) + 8); }
+
+// The 8 elements starting at element p (a multiple of 8) of the padded array
+// A, or the zero block at element zp when [p, p+8) is not inside the written
+// range [0, hi).
+DEV void load8z(double* r, const double* A, int p, int hi, int zp)
 {
+    const int pp = (p >= 0 && p + 8 <= hi) ? p : zp;
+    const double* a = A + (pp >> 3) * 9;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) r[c] = A[c];
+    for (int c = 0; c < 8; ++c) r[c] = a[c];
 }
 
-// S[i] += sum_{s=s0}^{nW-1} W[s] * A[PX(base + i + s)], i in [0, FNO).  base + s0
-// must be a multiple of 8; A is padded storage holding zeros wherever the
-// loop reads outside the valid range (it reads up to base + nW + 7).  W is a
-// uniform (scalar-loadable) pointer; nW and s0 are multiples of 8.  The two
-// 8-element halves of the window alternate roles, so nothing is moved.
-DEV void band_acc(const double* A, int base, const double* __restrict__ W, int s0, int nW, double* S)
+// S[i] += sum_{s=s0}^{nW-1} W[s] * A[PX(base + i + s)], i in [0, FNO).  base is
+// this lane's window start (a multiple of 8); s0 and nW are the same for the
+// whole wave (multiples of 8), so the loop is uniform and W (a uniform
+// pointer) is read with scalar loads.  Blocks outside the written range [0, hi)
+// of A read as the zero block at zp: windows of lanes near either end of the
+// trajectory need no lane-dependent trip count.  The two 8-element halves of
+// the window alternate roles, so nothing is moved.
+DEV void band_acc(const double* A, int base, const double* __restrict__ W, int s0, int nW, int hi, int zp, double* S)
 {
     if (s0 >= nW) return;
-    int q = PX(base + s0);
+    int p = base + s0;
     double x[8], y[8];
-    load8(x, A + q);
-    load8(y, A + q + 9);
+    load8z(x, A, p, hi, zp);
+    load8z(y, A, p + 8, hi, zp);
     int s = s0;
     for (;;) {
         fma_block(S, W + s, x, y);
         s += 8;
         if (s >= nW) break;
-        q += 9;
-        load8(x, A + q + 9);
+        p += 8;
+        load8z(x, A, p + 8, hi, zp);
         fma_block(S, W + s, y, x);
         s += 8;
         if (s >= nW) break;
-        q += 9;
-        load8(y, A + q + 9);
+        p += 8;
+        load8z(y, A, p + 8, hi, zp);
     }
 }
+
+// timestep of the first lane of this thread's wave (uniform)
+DEV int wave_c0(int tid) { return __builtin_amdgcn_readfirstlane(FNO * tid); }
 
 // ------------------------------------------------------------------ tables
 
@@ -222,10 +246,14 @@ struct TabShared {
     int ints[8];
 };
 
-// One work-group per mask node: support, core and band weight tables.
-__global__ void __launch_bounds__(256) stl_mask_tables(DevPlan plan, const float* params, int L, MaskTab* tabs)
+// One work-group per mask node: support, core and band weight tables.  Work-group
+// 0 also resets the two counters of the fused launch (the generic executor's work
+// counter and the hand-off list length).
+__global__ void __launch_bounds__(256) stl_mask_tables(DevPlan plan, const float* params, int L, MaskTab* tabs,
+                                                       int* counters)
 {
     __shared__ TabShared sh;
+    if (blockIdx.x == 0 && threadIdx.x < 2) counters[threadIdx.x] = 0;
     const DevPlan& P = plan;
     const int m = blockIdx.x;
     const Instr& I = P.ins[P.fused.ins[m]];
@@ -233,10 +261,10 @@ __global__ void __launch_bounds__(256) stl_mask_tables(DevPlan plan, const float
     const MaskInfo mi = mask_info(params, I, L, sh, nullptr, nullptr, nullptr);
     const bool core = mi.any && mi.clo <= mi.chi;
     const int le = core ? mi.clo : mi.khi + 1;
-    const int kl0 = mi.any ? floor8(mi.klo) : 0;
+    const int kl0 = mi.any ? mi.klo : 0;
     const int nWl = mi.any ? round8(le - kl0) : 0;
     const int rs = mi.chi + 1, re = mi.khi + 1;
-    const int kr0 = core ? floor8(rs) : 0;
+    const int kr0 = core ? rs : 0;
     const int nWr = core ? round8(re - kr0) : 0;
     const bool ok = nWl <= FMAXB && nWr <= FMAXB;
     if (threadIdx.x == 0) {
@@ -277,14 +305,14 @@ __global__ void __launch_bounds__(256) stl_mask_tables(DevPlan plan, const float
             T.Dar[s] = dar;
             T.Dbr[s] = dbr;
         }
-        // reversed: Wlr[s] = Wl[nWl - s] for 1 <= s <= nWl
+        // reversed: Wlr[s] = Wl[nWl - 1 - s] for 0 <= s < nWl
         float wlr = 0.f, wrr = 0.f;
-        if (s >= 1 && s <= nWl) {
-            const int k = kl0 + nWl - s;
+        if (s < nWl) {
+            const int k = kl0 + nWl - 1 - s;
             if (k >= mi.klo && k < le) wlr = mask_wk(mp, k);
         }
-        if (s >= 1 && s <= nWr) {
-            const int k = kr0 + nWr - s;
+        if (s < nWr) {
+            const int k = kr0 + nWr - 1 - s;
             if (k >= rs && k < re) wrr = mask_wk(mp, k);
         }
         T.Wlr[s] = wlr;
@@ -322,11 +350,18 @@ DEV void fop_init(const DevPlan& P, int m, const float* params, FOp& op)
     op.R = 0;
 }
 
-// E[j] = 2^{z_j - R} for this thread's timesteps: registers e[] and the
-// padded LDS array E with a zero tail.  Sets op.R.  The barriers of the
-// work-group maximum come before the first write to E, so earlier reads of
-// E by other threads are complete.
-DEV void fused_terms(FOp& op, const float* x, int L, int D, double* e, double* E, FShared& sh, float* z, int tid)
+// Shift of the copy of the terms read by a band starting at offset k0:
+// term j sits at padded position PX(j + band_shift(k0)), so that every
+// thread's band window starts on a multiple of 8 whatever k0 is.
+DEV int band_shift(int k0) { return 8 - (k0 & 7); }
+
+// E[j] = 2^{z_j - R} for this thread's timesteps: registers e[] and two
+// padded LDS copies, A shifted by shA and B shifted by shB (one per band),
+// with a zero tail.  Sets op.R.  The barriers of the work-group maximum come
+// before the first write, so earlier reads of A and B by other threads are
+// complete.
+DEV void fused_terms(FOp& op, const float* x, int L, int D, double* e, double* A, double* B, int shA, int shB,
+                     FShared& sh, float* z, int tid)
 {
     const int c0 = FNO * tid;
     float zmax = -INFINITY;
@@ -353,26 +388,34 @@ DEV void fused_terms(FOp& op, const float* x, int L, int D, double* e, double* E
             const float d = z[i] - (float)R;
             frag |= d < -1000.f;
             e[i] = exp2d_neg(d);
-            E[PX(j)] = e[i];
+            A[PX(j + shA)] = e[i];
+            B[PX(j + shB)] = e[i];
         } else {
             e[i] = 0.0;
-            if (j < L + FTAIL) E[PX(j)] = 0.0;
+            if (j < L + FTAIL) {
+                A[PX(j + shA)] = 0.0;
+                B[PX(j + shB)] = 0.0;
+            }
         }
     }
-    for (int j = max(L, FNO * FNT) + tid; j < L + FTAIL; j += FNT) E[PX(j)] = 0.0;
+    for (int j = max(L, FNO * FNT) + tid; j < L + FTAIL; j += FNT) {
+        A[PX(j + shA)] = 0.0;
+        B[PX(j + shB)] = 0.0;
+    }
     if (frag) sh.fragile = 1;
     __syncthreads();
 }
 
 // Forward trace of one mask node for this thread's timesteps (out[0..FNO)).
 // Uses A (terms, then block prefixes) and Bs (block suffixes).
-DEV void mask_trace(const DevPlan& P, const MaskTab& T, FOp& op, const float* x, int L, int D, double* A,
+DEV void mask_trace(const DevPlan& P, const MaskTab& T, FOp& op, const float* x, int L, int Lc, int D, double* A,
                     double* Bs, float* out, FShared& sh, int tid)
 {
     const int c0 = FNO * tid;
     double e[FNO];
     float z[FNO];
-    fused_terms(op, x, L, D, e, A, sh, z, tid);
+    const int shA = band_shift(T.kl0), shB = band_shift(T.kr0);
+    fused_terms(op, x, L, D, e, A, Bs, shA, shB, sh, z, tid);
     if (!T.any) {
 #pragma unroll
         for (int i = 0; i < FNO; ++i) out[i] = -op.sg * P.rho_pad;
@@ -381,13 +424,15 @@ DEV void mask_trace(const DevPlan& P, const MaskTab& T, FOp& op, const float* x,
     double S[FNO];
 #pragma unroll
     for (int i = 0; i < FNO; ++i) S[i] = 0.0;
-    const int lim = L - c0;
-    if (c0 < L) {
-        band_acc(A, c0 + T.kl0, T.Wl, 0, min(T.nWl, max(0, round8(lim - T.kl0))), S);
-        if (T.core) band_acc(A, c0 + T.kr0, T.Wr, 0, min(T.nWr, max(0, round8(lim - T.kr0))), S);
+    {
+        // the wave's first lane has the longest valid window: its limit serves the wave
+        const int lim = L - wave_c0(tid), zp = fused_zero_at(Lc);
+        band_acc(A, c0 + T.kl0 + shA, T.Wl, 0, min(T.nWl, max(0, round8(lim - T.kl0))), L + FTAIL + shA, zp, S);
+        if (T.core)
+            band_acc(Bs, c0 + T.kr0 + shB, T.Wr, 0, min(T.nWr, max(0, round8(lim - T.kr0))), L + FTAIL + shB, zp, S);
     }
     if (T.core) {
-        __syncthreads();                              // band reads of the terms are done
+        __syncthreads();                              // band reads of the term copies are done
         fscan<false>(e, A, L, T.K, T.off, sh, tid);   // block prefixes over the terms
         fscan<true>(e, Bs, L, T.K, T.off, sh, tid);   // block suffixes
         if (c0 < L) {
@@ -432,7 +477,7 @@ DEV int opaque_tid()
 
 // every mask trace for this thread's timesteps (tr[m][i]); ends with a barrier
 template <int N>
-DEV void mask_traces(const DevPlan& P, const KArgs& ka, const float* x, int L, int D, double* A, double* Bs,
+DEV void mask_traces(const DevPlan& P, const KArgs& ka, const float* x, int L, int Lc, int D, double* A, double* Bs,
                      float (&tr)[N][FNO], FShared& sh)
 {
 #pragma unroll 1
@@ -440,7 +485,7 @@ DEV void mask_traces(const DevPlan& P, const KArgs& ka, const float* x, int L, i
         FOp op;
         fop_init(P, m, ka.params, op);
         float out[FNO];
-        mask_trace(P, ka.tabs[m], op, x, L, D, A, Bs, out, sh, opaque_tid());
+        mask_trace(P, ka.tabs[m], op, x, L, Lc, D, A, Bs, out, sh, opaque_tid());
 #pragma unroll
         for (int k = 0; k < N; ++k)
 #pragma unroll
@@ -479,11 +524,12 @@ DEV float fused_root(const DevPlan& P, const float* params, const float* v, floa
 // LDS: two padded fp64 arrays
 __host__ __device__ inline size_t fused_lds_bytes(int Lc)
 {
-    return (size_t)2 * px_len(Lc + FHOFF + FTAIL) * sizeof(double);
+    return (size_t)2 * fused_arr_len(Lc) * sizeof(double);
 }
 
-DEV bool fused_enter(const DevPlan& P, const KArgs& ka, FShared& sh)
+DEV bool fused_enter(const DevPlan& P, const KArgs& ka, FShared& sh, double* A, double* Bs, int Lc)
 {
+    if (threadIdx.x < 16) (threadIdx.x < 8 ? A : Bs)[(fused_zero_at(Lc) >> 3) * 9 + (threadIdx.x & 7)] = 0.0;
     bool ok = true;
     for (int m = 0; m < P.fused.n; ++m) ok = ok && ka.tabs[m].ok;
     if (threadIdx.x == 0) sh.fragile = 0;
@@ -524,17 +570,17 @@ DEV void load8f(const float* p, int c0, int L, float* v)
 }
 
 template <int N>
-__global__ void __launch_bounds__(FNT) stl_fused_fwd(DevPlan plan, Batch bt, KArgs ka)
+__global__ void __launch_bounds__(FNT, FWAVES_FWD) stl_fused_fwd(DevPlan plan, Batch bt, KArgs ka)
 {
     extern __shared__ double fsm[];
     __shared__ FShared sh;
     const DevPlan& P = plan;
     const int L = (int)bt.T, Lc = bt.Lcap, D = bt.D;
     const int64_t b = blockIdx.x;
-    const int pl = px_len(Lc + FHOFF + FTAIL);
+    const int pl = fused_arr_len(Lc);
     double* A = fsm;
     double* Bs = A + pl;
-    if (!fused_enter(P, ka, sh)) {
+    if (!fused_enter(P, ka, sh, A, Bs, Lc)) {
         if (ka.saved_flag && threadIdx.x == 0) ka.saved_flag[b] = 0;
         fused_handoff(ka, b);
         return;
@@ -542,7 +588,7 @@ __global__ void __launch_bounds__(FNT) stl_fused_fwd(DevPlan plan, Batch bt, KAr
     const float* x = bt.x + b * (int64_t)L * D;
     const int c0 = FNO * threadIdx.x;
     float tr[N][FNO];
-    mask_traces<N>(P, ka, x, L, D, A, Bs, tr, sh);
+    mask_traces<N>(P, ka, x, L, Lc, D, A, Bs, tr, sh);
     if (sh.fragile) {
         if (ka.saved_flag && threadIdx.x == 0) ka.saved_flag[b] = 0;
         fused_handoff(ka, b);
@@ -568,20 +614,20 @@ __global__ void __launch_bounds__(FNT) stl_fused_fwd(DevPlan plan, Batch bt, KAr
 // d/da, d/db contributions of one band: p += sum_i k_i * sum_s dW[s] E[t_i + s]
 // (one weight set at a time: a derivative that is zero over the whole band
 // is skipped, e.g. d/db over the band around a)
-DEV void deriv_band(const double* A, int base, const double* W, int nz, int nW, const double* h, int sc, double k0,
-                    double& p)
+DEV void deriv_band(const double* A, int base, const double* W, int nz, int nW, int hi, int zp, const double* h,
+                    int sc, double k0, double& p)
 {
     if (nW <= 0 || !nz) return;
     double S[FNO];
 #pragma unroll
     for (int i = 0; i < FNO; ++i) S[i] = 0.0;
-    band_acc(A, base, W, 0, nW, S);
+    band_acc(A, base, W, 0, nW, hi, zp, S);
 #pragma unroll
     for (int i = 0; i < FNO; ++i) p = fma(ldexp(h[i], sc) * k0, S[i], p);     // sg G_m 2^{R - O_t} / beta
 }
 
 template <int N>
-__global__ void __launch_bounds__(FNT) stl_fused_bwd(DevPlan plan, Batch bt, KArgs ka)
+__global__ void __launch_bounds__(FNT, FWAVES_BWD) stl_fused_bwd(DevPlan plan, Batch bt, KArgs ka)
 {
     extern __shared__ double fsm[];
     __shared__ FShared sh;
@@ -589,10 +635,10 @@ __global__ void __launch_bounds__(FNT) stl_fused_bwd(DevPlan plan, Batch bt, KAr
     const FusedDesc& F = P.fused;
     const int L = (int)bt.T, Lc = bt.Lcap, D = bt.D;
     const int64_t b = blockIdx.x;
-    const int pl = px_len(Lc + FHOFF + FTAIL);
-    double* A = fsm;             // terms E, then adjoint terms H (offset FHOFF), then block prefixes
-    double* Bs = A + pl;         // block suffixes
-    if (!fused_enter(P, ka, sh)) { fused_handoff(ka, b); return; }
+    const int pl = fused_arr_len(Lc);
+    double* A = fsm;             // terms E, then adjoint terms H, then block prefixes (shifted copies
+    double* Bs = A + pl;         // for the left band in A, the right band in Bs), then block suffixes
+    if (!fused_enter(P, ka, sh, A, Bs, Lc)) { fused_handoff(ka, b); return; }
     const float* x = bt.x + b * (int64_t)L * D;
     const int c0 = FNO * threadIdx.x;
     float tr[N][FNO];
@@ -602,7 +648,7 @@ __global__ void __launch_bounds__(FNT) stl_fused_bwd(DevPlan plan, Batch bt, KAr
         for (int m = 0; m < N; ++m) load8f(ka.saved_in + ((int64_t)m * bt.B + b) * L, c0, L, tr[m]);
     } else {
         // forward recompute of every mask trace (the n-ary adjoint needs all of them)
-        mask_traces<N>(P, ka, x, L, D, A, Bs, tr, sh);
+        mask_traces<N>(P, ka, x, L, Lc, D, A, Bs, tr, sh);
         if (sh.fragile) { fused_handoff(ka, b); return; }
     }
     // adjoint of each mask trace, G_m = G * d root / d trace_m (gm), and its
@@ -654,9 +700,10 @@ __global__ void __launch_bounds__(FNT) stl_fused_bwd(DevPlan plan, Batch bt, KAr
             for (int i = 0; i < FNO; ++i) gv[i] = 0.f;
         } else {
             float z[FNO];
+            const int shA = band_shift(T.kl0), shB = band_shift(T.kr0);
             {
                 double e[FNO];
-                fused_terms(op, x, L, D, e, A, sh, z, tid);
+                fused_terms(op, x, L, D, e, A, Bs, shA, shB, sh, z, tid);
             }
             // H_t = G_m[t] 2^{-O_t - Q}, Q the per-trajectory exponent of max |G_m 2^{-O}|
             int qloc = INT_MIN;
@@ -683,47 +730,65 @@ __global__ void __launch_bounds__(FNT) stl_fused_bwd(DevPlan plan, Batch bt, KAr
             }
             // d/da, d/db: sum_t sg G_m[t]/beta * sum_k dw_k 2^{z_{t+k} - O_t}, over the bands
             double pa = 0.0, pb = 0.0;
-            if (c0 < L) {
+            const int zp = fused_zero_at(Lc);
+            {
                 const double k0 = (double)(op.sg / op.beta);
-                const int lim = L - c0, sc = op.R + Q;
+                const int lim = L - wave_c0(tid), sc = op.R + Q;
                 const int nl = min(T.nWl, max(0, round8(lim - T.kl0)));
-                deriv_band(A, c0 + T.kl0, T.Dal, T.nz_al, nl, h, sc, k0, pa);
-                deriv_band(A, c0 + T.kl0, T.Dbl, T.nz_bl, nl, h, sc, k0, pb);
+                const int hl = L + FTAIL + shA, hr = L + FTAIL + shB;
+                deriv_band(A, c0 + T.kl0 + shA, T.Dal, T.nz_al, nl, hl, zp, h, sc, k0, pa);
+                deriv_band(A, c0 + T.kl0 + shA, T.Dbl, T.nz_bl, nl, hl, zp, h, sc, k0, pb);
                 if (T.core) {
                     const int nr = min(T.nWr, max(0, round8(lim - T.kr0)));
-                    deriv_band(A, c0 + T.kr0, T.Dar, T.nz_ar, nr, h, sc, k0, pa);
-                    deriv_band(A, c0 + T.kr0, T.Dbr, T.nz_br, nr, h, sc, k0, pb);
+                    deriv_band(Bs, c0 + T.kr0 + shB, T.Dar, T.nz_ar, nr, hr, zp, h, sc, k0, pa);
+                    deriv_band(Bs, c0 + T.kr0 + shB, T.Dbr, T.nz_br, nr, hr, zp, h, sc, k0, pb);
                 }
             }
             pa = wg_sum_d(pa, sh);     // (contains barriers: every E read above is done)
             pb = wg_sum_d(pb, sh);
             if (I.mslot >= 0 && tid == 0) { mp[2 * I.mslot] = (float)pa; mp[2 * I.mslot + 1] = (float)pb; }
-            // A now holds H (zero padded both sides)
-            for (int j = tid - FHOFF; j < 0; j += FNT) A[PX(j + FHOFF)] = 0.0;
+            // adjoint terms H, two shifted copies (A for the left band, Bs for
+            // the right) zero padded on both sides: H_t sits at PX(t + hA)
+            // with hA = kl0 - 1 (mod 8), so that the transposed window of
+            // output j, starting at t = j - kl0 - nWl + 1, starts on a multiple of 8
+            const int hA = 24 + ((T.kl0 - 1) & 7), hB = 24 + ((T.kr0 - 1) & 7);
+            for (int p = tid; p < 32; p += FNT) {
+                if (p < hA) A[PX(p)] = 0.0;
+                if (p < hB) Bs[PX(p)] = 0.0;
+            }
 #pragma unroll
             for (int i = 0; i < FNO; ++i) {
                 const int j = c0 + i;
-                if (j < L + FTAIL) A[PX(j + FHOFF)] = (j < L) ? h[i] : 0.0;
+                if (j < L + FTAIL) {
+                    const double hv = (j < L) ? h[i] : 0.0;
+                    A[PX(j + hA)] = hv;
+                    Bs[PX(j + hB)] = hv;
+                }
             }
-            for (int j = max(L, FNO * FNT) + tid; j < L + FTAIL; j += FNT) A[PX(j + FHOFF)] = 0.0;
+            for (int j = max(L, FNO * FNT) + tid; j < L + FTAIL; j += FNT) {
+                A[PX(j + hA)] = 0.0;
+                Bs[PX(j + hB)] = 0.0;
+            }
             __syncthreads();
-            // dx bands: transposed band sums over t of H
+            // dx bands: dx_j += sum_k w_k H_{j-k} = sum_s Wrev[s] H_{j - k0 - nW + 1 + s}
             double Bd[FNO];
 #pragma unroll
             for (int i = 0; i < FNO; ++i) Bd[i] = 0.0;
-            if (c0 < L) {
-                {
-                    const int base = c0 - T.kl0 - T.nWl;
-                    band_acc(A, base + FHOFF, T.Wlr, max(0, round8(-base - FHOFF)), T.nWl + 8, Bd);
-                }
+            {
+                // blocks before t = 0 read as zeros; the wave's last lane (base + 8*63)
+                // fixes the first block any lane of the wave needs
+                const int w0 = wave_c0(tid) + FNO * 63;
+                const int base = c0 - T.kl0 - T.nWl + 1 + hA;      // a multiple of 8
+                band_acc(A, base, T.Wlr, max(0, -(w0 - T.kl0 - T.nWl + 1 + hA)), T.nWl, L + FTAIL + hA, zp, Bd);
                 if (T.core) {
-                    const int base = c0 - T.kr0 - T.nWr;
-                    band_acc(A, base + FHOFF, T.Wrr, max(0, round8(-base - FHOFF)), T.nWr + 8, Bd);
+                    const int base2 = c0 - T.kr0 - T.nWr + 1 + hB;
+                    band_acc(Bs, base2, T.Wrr, max(0, -(w0 - T.kr0 - T.nWr + 1 + hB)), T.nWr, L + FTAIL + hB, zp,
+                             Bd);
                 }
             }
             // dx core: van Herk over t of H, windows [j - chi, j - clo] (heads at t % K == 0)
             if (T.core) {
-                __syncthreads();                         // H reads done: A receives the block prefixes
+                __syncthreads();                         // H reads done: A, Bs receive the block sums
                 fscan<false>(h, A, L, T.K, 0, sh, tid);
                 fscan<true>(h, Bs, L, T.K, 0, sh, tid);
                 const double wc = (double)T.wc;

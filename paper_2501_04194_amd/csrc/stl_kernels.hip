@@ -1106,25 +1106,30 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
 }
 
 // grad_params[mask_param + 0/1] = sum over trajectories (fixed order) of the
-// per-trajectory partials; every other parameter gradient is 0.
+// per-trajectory partials; every other parameter gradient is 0.  One
+// work-group per (mask, bound): block q sums column q.
 __global__ void stl_reduce_params(const float* part, int64_t B, int n_masks, DevPlan plan, float* gp)
 {
     __shared__ float red[256];
     const int tid = threadIdx.x;
-    for (int p = tid; p < plan.n_params; p += blockDim.x) gp[p] = 0.f;
-    __syncthreads();
-    for (int q = 0; q < 2 * n_masks; ++q) {
-        float s = 0.f;
-        for (int64_t b = tid; b < B; b += blockDim.x) s += part[b * 2 * n_masks + q];
-        red[tid] = s;
-        __syncthreads();
-        for (int k = blockDim.x >> 1; k > 0; k >>= 1) {
-            if (tid < k) red[tid] += red[tid + k];
-            __syncthreads();
+    const int q = blockIdx.x;
+    if (q == 0) {
+        for (int p = tid; p < plan.n_params; p += blockDim.x) {
+            bool bound = false;
+            for (int m = 0; m < n_masks; ++m) bound |= p == plan.mask_param[m] || p == plan.mask_param[m] + 1;
+            if (!bound) gp[p] = 0.f;
         }
-        if (tid == 0) gp[plan.mask_param[q >> 1] + (q & 1)] = red[0];
+    }
+    if (q >= 2 * n_masks) return;
+    float s = 0.f;
+    for (int64_t b = tid; b < B; b += blockDim.x) s += part[b * 2 * n_masks + q];
+    red[tid] = s;
+    __syncthreads();
+    for (int k = blockDim.x >> 1; k > 0; k >>= 1) {
+        if (tid < k) red[tid] += red[tid + k];
         __syncthreads();
     }
+    if (tid == 0) gp[plan.mask_param[q >> 1] + (q & 1)] = red[0];
 }
 
 __global__ void stl_zero_counter(int* c) { if (threadIdx.x < 2) c[threadIdx.x] = 0; }
@@ -1191,7 +1196,7 @@ size_t mask_tab_bytes() { return sizeof(MaskTab); }
 hipError_t launch_fused(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs& ka, size_t lds, hipStream_t s)
 {
     hipLaunchKernelGGL(stl_mask_tables, dim3(plan.fused.n), dim3(256), 0, s, plan, ka.params, (int)bt.T,
-                       (MaskTab*)ka.tabs);
+                       (MaskTab*)ka.tabs, ka.counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)bt.B), block(FNT);
@@ -1242,7 +1247,8 @@ hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s)
 
 hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& plan, float* gp, hipStream_t s)
 {
-    hipLaunchKernelGGL(stl_reduce_params, dim3(1), dim3(256), 0, s, part, B, plan.n_masks, plan, gp);
+    hipLaunchKernelGGL(stl_reduce_params, dim3(std::max(1, 2 * plan.n_masks)), dim3(256), 0, s, part, B,
+                       plan.n_masks, plan, gp);
     return hipGetLastError();
 }
 
