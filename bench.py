@@ -30,7 +30,7 @@ BYTES_BWD = 20       # per signal-step: x (8 B) + G (4 B) + dx (8 B)
 METRIC = "fwd+bwd signal-steps/s (B=4096,T=2048 smooth STL); % of HBM roofline"
 
 
-def cpu_baseline(n_traj=128):
+def cpu_baseline(n_traj=4096):
     """The FP64 oracle (unchanged) on a bounded sample of the same workload."""
     import oracle
     from paper_2501_04194_amd import workloads as W
@@ -44,8 +44,23 @@ def cpu_baseline(n_traj=128):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n_traj * x.shape[1] / dt, "unit": "signal-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of the 4096 trajectories (T=2048), forward + backward, FP64 C oracle with OpenMP, %.2f s"
+            "sample": "%d of the 4096 trajectories (T=2048), forward + backward, FP64 C oracle with OpenMP, %.1f s"
                       % (n_traj, dt)}
+
+
+def traffic_per_launch():
+    """HBM bytes per backward launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    tf = os.path.join(ROOT, "profiles", "traffic_bwd_smooth_mask_B4096_T2048.json")
+    if not os.path.exists(tf):
+        return None
+    rec = json.load(open(tf))
+    csrc = os.path.join(ROOT, "paper_2501_04194_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("stl_fused.h", "stl_kernels.hip", "stl_plan.h"))
+    if hashlib.sha256(src).hexdigest() != rec.get("sources_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def bench_graph(args):
@@ -143,7 +158,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rotate", type=int, default=4, help="input buffer sets cycled through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-traj", type=int, default=128)
+    ap.add_argument("--cpu-traj", type=int, default=4096)
     ap.add_argument("--recompute", action="store_true", help="backward recomputes the node traces")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer three times (the reference kernel for HBM counters)")
@@ -221,13 +236,7 @@ def main():
     dom_ms = bwd_ms if dom_is_bwd else fwd_ms
     dom_bytes = (BYTES_BWD if dom_is_bwd else BYTES_FWD) * steps_per_batch
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", "traffic_bwd_smooth_mask_B4096_T2048.json")
-    if dom_is_bwd and os.path.exists(tf):
-        try:
-            traffic = json.load(open(tf)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = traffic_per_launch() if dom_is_bwd else None
     out = {
         "metric": METRIC,
         "value": value,

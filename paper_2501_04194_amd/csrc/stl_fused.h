@@ -35,8 +35,10 @@ constexpr int FTAIL = 16;         // high-side zero padding (elements)
 constexpr int FMAXN = 4;          // mask nodes under the root
 // waves per SIMD the kernels are compiled for (VGPR budget 512 / waves); LDS
 // allows four work-groups (of one wave per SIMD) per compute unit
-constexpr int FWAVES_FWD = 4;
-constexpr int FWAVES_BWD = 3;
+constexpr int FWAVES_FWD = 3;
+constexpr int FWAVES_BWD = 2;
+// more mask nodes keep more per-mask state in registers: fewer waves
+constexpr int fused_waves(int n, int w) { return n <= 2 ? w : (n == 3 ? (w > 2 ? 2 : w) : 1); }
 
 // Per-mask tables, computed once per call by stl_mask_tables.
 struct MaskTab {
@@ -57,6 +59,13 @@ struct FShared {
     double wv[FNW];
     int wf[FNW];
     int wi[FNW];
+    int wn[FMAXN][FNW];
+    // per mask node (filled by fused_enter): sign, beta, predicate coefficient
+    // offset, gradient slot; read with a runtime mask index from LDS rather
+    // than from the kernel argument
+    float m_sg[FMAXN], m_beta[FMAXN];
+    int m_slot[FMAXN];
+    float m_coef[FMAXN][1 + MAX_D];     // linear predicate: c, w[0..D)
     int ints[8];
     int fragile;
 };
@@ -203,7 +212,7 @@ __host__ __device__ constexpr int fused_arr_len(int Lc) { return px_len(fused_ze
 DEV void load8z(double* r, const double* A, int p, int hi, int zp)
 {
     const int pp = (p >= 0 && p + 8 <= hi) ? p : zp;
-    const double* a = A + (pp >> 3) * 9;
+    const double* a = A + PX(pp);
 #pragma unroll
     for (int c = 0; c < 8; ++c) r[c] = a[c];
 }
@@ -339,13 +348,11 @@ struct FOp {
     int R;               // reference exponent
 };
 
-DEV void fop_init(const DevPlan& P, int m, const float* params, FOp& op)
+DEV void fop_init(const DevPlan& P, int m, const FShared& sh, FOp& op)
 {
-    const FusedDesc& F = P.fused;
-    const Instr& I = P.ins[F.ins[m]];
-    op.cf = P.coef + P.ins[F.pred[m]].coef;
-    op.sg = (I.flags & F_MIN) ? -1.f : 1.f;
-    op.beta = params[I.beta];
+    op.cf = sh.m_coef[m];
+    op.sg = sh.m_sg[m];
+    op.beta = sh.m_beta[m];
     op.bl = op.beta * LOG2E;
     op.R = 0;
 }
@@ -355,31 +362,93 @@ DEV void fop_init(const DevPlan& P, int m, const float* params, FOp& op)
 // thread's band window starts on a multiple of 8 whatever k0 is.
 DEV int band_shift(int k0) { return 8 - (k0 & 7); }
 
-// E[j] = 2^{z_j - R} for this thread's timesteps: registers e[] and two
-// padded LDS copies, A shifted by shA and B shifted by shB (one per band),
-// with a zero tail.  Sets op.R.  The barriers of the work-group maximum come
-// before the first write, so earlier reads of A and B by other threads are
-// complete.
-DEV void fused_terms(FOp& op, const float* x, int L, int D, double* e, double* A, double* B, int shA, int shB,
-                     FShared& sh, float* z, int tid)
+// Exponents z = sign * beta * log2(e) * (w . x_j - c) of every mask node for
+// this thread's timesteps (-inf past the end).  The thread's FNO state rows are
+// FNO*D consecutive floats, read once for all masks (as four 16-byte loads
+// when D == 2).
+template <int N>
+DEV void fused_exponents(const FShared& sh, const float* x, int L, int D, int c0, float (&z)[N][FNO])
 {
-    const int c0 = FNO * tid;
-    float zmax = -INFINITY;
+    const float* xr = x + (size_t)c0 * D;
+    if (D == 2 && c0 + FNO <= L && (((uintptr_t)xr) & 15) == 0) {
+        float v[2 * FNO];
+        const float4* q = (const float4*)xr;
+#pragma unroll
+        for (int k = 0; k < FNO / 2; ++k) {
+            const float4 a = q[k];
+            v[4 * k] = a.x;
+            v[4 * k + 1] = a.y;
+            v[4 * k + 2] = a.z;
+            v[4 * k + 3] = a.w;
+        }
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const float* cf = sh.m_coef[m];
+            const float sg = sh.m_sg[m], bl = sh.m_beta[m] * LOG2E;
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) {
+                float t = 0.f;
+                t = fmaf(cf[1], v[2 * i], t);
+                t = fmaf(cf[2], v[2 * i + 1], t);
+                z[m][i] = sg * bl * (t - cf[0]);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < FNO; ++i) {
         const int j = c0 + i;
-        float s = 0.f;
+        float t[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) t[m] = 0.f;
         if (j < L) {
-            const float* xr = x + (size_t)j * D;
-            for (int d = 0; d < D; ++d) s = fmaf(op.cf[1 + d], xr[d], s);
-            z[i] = op.sg * op.bl * (s - op.cf[0]);
-            zmax = fmaxf(zmax, z[i]);
-        } else {
-            z[i] = -INFINITY;
+            for (int d = 0; d < D; ++d) {
+                const float xv = xr[(size_t)i * D + d];
+#pragma unroll
+                for (int m = 0; m < N; ++m) t[m] = fmaf(sh.m_coef[m][1 + d], xv, t[m]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const float sg = sh.m_sg[m], bl = sh.m_beta[m] * LOG2E;
+            z[m][i] = j < L ? sg * bl * (t[m] - sh.m_coef[m][0]) : -INFINITY;
         }
     }
-    const int R = wg_max_i((int)ceilf(fminf(fmaxf(zmax, -1e9f), 1e9f)), sh);
-    op.R = R;
+}
+
+// Per-trajectory reference exponents R_m = ceil(max_j z_m[j]) of every mask,
+// one work-group reduction for all of them.
+template <int N>
+DEV void fused_refs(const float (&z)[N][FNO], int (&R)[N], FShared& sh)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        float zm = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) zm = fmaxf(zm, z[m][i]);
+        int v = (int)ceilf(fminf(fmaxf(zm, -1e9f), 1e9f));
+        for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d));
+        if (lane == 0) sh.wn[m][w] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        int r = sh.wn[m][0];
+        for (int k = 1; k < FNW; ++k) r = max(r, sh.wn[m][k]);
+        R[m] = r;
+    }
+}
+
+// E[j] = 2^{z_j - R} for this thread's timesteps: registers e[] and two
+// padded LDS copies, A shifted by shA and B shifted by shB (one per band),
+// with a zero tail.  Starts with a barrier, so earlier reads of A and B by
+// other threads are complete, and ends with one.
+DEV void fused_terms(const float* z, int R, int L, double* e, double* A, double* B, int shA, int shB, FShared& sh,
+                     int tid)
+{
+    const int c0 = FNO * tid;
+    __syncthreads();
     bool frag = false;
 #pragma unroll
     for (int i = 0; i < FNO; ++i) {
@@ -408,14 +477,13 @@ DEV void fused_terms(FOp& op, const float* x, int L, int D, double* e, double* A
 
 // Forward trace of one mask node for this thread's timesteps (out[0..FNO)).
 // Uses A (terms, then block prefixes) and Bs (block suffixes).
-DEV void mask_trace(const DevPlan& P, const MaskTab& T, FOp& op, const float* x, int L, int Lc, int D, double* A,
+DEV void mask_trace(const DevPlan& P, const MaskTab& T, FOp& op, const float* z, int L, int Lc, double* A,
                     double* Bs, float* out, FShared& sh, int tid)
 {
     const int c0 = FNO * tid;
     double e[FNO];
-    float z[FNO];
     const int shA = band_shift(T.kl0), shB = band_shift(T.kr0);
-    fused_terms(op, x, L, D, e, A, Bs, shA, shB, sh, z, tid);
+    fused_terms(z, op.R, L, e, A, Bs, shA, shB, sh, tid);
     if (!T.any) {
 #pragma unroll
         for (int i = 0; i < FNO; ++i) out[i] = -op.sg * P.rho_pad;
@@ -475,17 +543,40 @@ DEV int opaque_tid()
     return t;
 }
 
+// row m of a per-mask register array, for a runtime (uniform) m
+template <int N>
+DEV void select_row(const float (&a)[N][FNO], int m, float* r)
+{
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) {
+        r[i] = a[0][i];
+#pragma unroll
+        for (int k = 1; k < N; ++k) r[i] = k == m ? a[k][i] : r[i];
+    }
+}
+
+template <int N>
+DEV int select_int(const int (&a)[N], int m)
+{
+    int r = a[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) r = k == m ? a[k] : r;
+    return r;
+}
+
 // every mask trace for this thread's timesteps (tr[m][i]); ends with a barrier
 template <int N>
-DEV void mask_traces(const DevPlan& P, const KArgs& ka, const float* x, int L, int Lc, int D, double* A, double* Bs,
-                     float (&tr)[N][FNO], FShared& sh)
+DEV void mask_traces(const DevPlan& P, const KArgs& ka, const float (&z)[N][FNO], const int (&R)[N], int L, int Lc,
+                     double* A, double* Bs, float (&tr)[N][FNO], FShared& sh)
 {
 #pragma unroll 1
     for (int m = 0; m < N; ++m) {
         FOp op;
-        fop_init(P, m, ka.params, op);
-        float out[FNO];
-        mask_trace(P, ka.tabs[m], op, x, L, Lc, D, A, Bs, out, sh, opaque_tid());
+        fop_init(P, m, sh, op);
+        op.R = select_int<N>(R, m);
+        float zm[FNO], out[FNO];
+        select_row<N>(z, m, zm);
+        mask_trace(P, ka.tabs[m], op, zm, L, Lc, A, Bs, out, sh, opaque_tid());
 #pragma unroll
         for (int k = 0; k < N; ++k)
 #pragma unroll
@@ -530,6 +621,17 @@ __host__ __device__ inline size_t fused_lds_bytes(int Lc)
 DEV bool fused_enter(const DevPlan& P, const KArgs& ka, FShared& sh, double* A, double* Bs, int Lc)
 {
     if (threadIdx.x < 16) (threadIdx.x < 8 ? A : Bs)[(fused_zero_at(Lc) >> 3) * 9 + (threadIdx.x & 7)] = 0.0;
+    if (threadIdx.x < FMAXN && (int)threadIdx.x < P.fused.n) {
+        const int m = threadIdx.x;
+        const Instr& I = P.ins[P.fused.ins[m]];
+        sh.m_sg[m] = (I.flags & F_MIN) ? -1.f : 1.f;
+        sh.m_beta[m] = ka.params[I.beta];
+        sh.m_slot[m] = I.mslot;
+    }
+    if ((int)threadIdx.x < P.fused.n * (1 + MAX_D)) {
+        const int m = threadIdx.x / (1 + MAX_D), k = threadIdx.x % (1 + MAX_D);
+        sh.m_coef[m][k] = k <= P.D ? P.coef[P.ins[P.fused.pred[m]].coef + k] : 0.f;
+    }
     bool ok = true;
     for (int m = 0; m < P.fused.n; ++m) ok = ok && ka.tabs[m].ok;
     if (threadIdx.x == 0) sh.fragile = 0;
@@ -570,7 +672,7 @@ DEV void load8f(const float* p, int c0, int L, float* v)
 }
 
 template <int N>
-__global__ void __launch_bounds__(FNT, FWAVES_FWD) stl_fused_fwd(DevPlan plan, Batch bt, KArgs ka)
+__global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_FWD)) stl_fused_fwd(DevPlan plan, Batch bt, KArgs ka)
 {
     extern __shared__ double fsm[];
     __shared__ FShared sh;
@@ -587,8 +689,11 @@ __global__ void __launch_bounds__(FNT, FWAVES_FWD) stl_fused_fwd(DevPlan plan, B
     }
     const float* x = bt.x + b * (int64_t)L * D;
     const int c0 = FNO * threadIdx.x;
-    float tr[N][FNO];
-    mask_traces<N>(P, ka, x, L, Lc, D, A, Bs, tr, sh);
+    float z[N][FNO], tr[N][FNO];
+    int R[N];
+    fused_exponents<N>(sh, x, L, D, c0, z);
+    fused_refs<N>(z, R, sh);
+    mask_traces<N>(P, ka, z, R, L, Lc, A, Bs, tr, sh);
     if (sh.fragile) {
         if (ka.saved_flag && threadIdx.x == 0) ka.saved_flag[b] = 0;
         fused_handoff(ka, b);
@@ -627,7 +732,7 @@ DEV void deriv_band(const double* A, int base, const double* W, int nz, int nW, 
 }
 
 template <int N>
-__global__ void __launch_bounds__(FNT, FWAVES_BWD) stl_fused_bwd(DevPlan plan, Batch bt, KArgs ka)
+__global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd(DevPlan plan, Batch bt, KArgs ka)
 {
     extern __shared__ double fsm[];
     __shared__ FShared sh;
@@ -641,14 +746,17 @@ __global__ void __launch_bounds__(FNT, FWAVES_BWD) stl_fused_bwd(DevPlan plan, B
     if (!fused_enter(P, ka, sh, A, Bs, Lc)) { fused_handoff(ka, b); return; }
     const float* x = bt.x + b * (int64_t)L * D;
     const int c0 = FNO * threadIdx.x;
-    float tr[N][FNO];
+    float z[N][FNO], tr[N][FNO];
+    int R[N];
+    fused_exponents<N>(sh, x, L, D, c0, z);
+    fused_refs<N>(z, R, sh);
     if (ka.saved_in && ka.saved_flag[b] == 1) {
         // mask-node traces kept by the forward
 #pragma unroll
         for (int m = 0; m < N; ++m) load8f(ka.saved_in + ((int64_t)m * bt.B + b) * L, c0, L, tr[m]);
     } else {
         // forward recompute of every mask trace (the n-ary adjoint needs all of them)
-        mask_traces<N>(P, ka, x, L, Lc, D, A, Bs, tr, sh);
+        mask_traces<N>(P, ka, z, R, L, Lc, A, Bs, tr, sh);
         if (sh.fragile) { fused_handoff(ka, b); return; }
     }
     // adjoint of each mask trace, G_m = G * d root / d trace_m (gm), and its
@@ -673,15 +781,16 @@ __global__ void __launch_bounds__(FNT, FWAVES_BWD) stl_fused_bwd(DevPlan plan, B
         }
     }
     float* mp = ka.mask_part + b * P.n_masks * 2;
-    float* dx = ka.dx + b * (int64_t)L * D;
+    float gvs[N][FNO];            // per mask: d root / d (w_m . x_j) for this thread's j
 #pragma unroll 1
     for (int m = 0; m < N; ++m) {
         const int tid = opaque_tid();
         const int c0 = FNO * tid;
         const MaskTab& T = ka.tabs[m];
-        const Instr& I = P.ins[F.ins[m]];
+        const int mslot = sh.m_slot[m];
         FOp op;
-        fop_init(P, m, ka.params, op);
+        fop_init(P, m, sh, op);
+        op.R = select_int<N>(R, m);
         float g[FNO], om[FNO];        // this mask's G_m and O_t
 #pragma unroll
         for (int i = 0; i < FNO; ++i) {
@@ -695,15 +804,16 @@ __global__ void __launch_bounds__(FNT, FWAVES_BWD) stl_fused_bwd(DevPlan plan, B
         }
         float gv[FNO];
         if (!T.any) {
-            if (I.mslot >= 0 && tid == 0) { mp[2 * I.mslot] = 0.f; mp[2 * I.mslot + 1] = 0.f; }
+            if (mslot >= 0 && tid == 0) { mp[2 * mslot] = 0.f; mp[2 * mslot + 1] = 0.f; }
 #pragma unroll
             for (int i = 0; i < FNO; ++i) gv[i] = 0.f;
         } else {
-            float z[FNO];
+            float zm[FNO];
+            select_row<N>(z, m, zm);
             const int shA = band_shift(T.kl0), shB = band_shift(T.kr0);
             {
                 double e[FNO];
-                fused_terms(op, x, L, D, e, A, Bs, shA, shB, sh, z, tid);
+                fused_terms(zm, op.R, L, e, A, Bs, shA, shB, sh, tid);
             }
             // H_t = G_m[t] 2^{-O_t - Q}, Q the per-trajectory exponent of max |G_m 2^{-O}|
             int qloc = INT_MIN;
@@ -746,7 +856,7 @@ __global__ void __launch_bounds__(FNT, FWAVES_BWD) stl_fused_bwd(DevPlan plan, B
             }
             pa = wg_sum_d(pa, sh);     // (contains barriers: every E read above is done)
             pb = wg_sum_d(pb, sh);
-            if (I.mslot >= 0 && tid == 0) { mp[2 * I.mslot] = (float)pa; mp[2 * I.mslot + 1] = (float)pb; }
+            if (mslot >= 0 && tid == 0) { mp[2 * mslot] = (float)pa; mp[2 * mslot + 1] = (float)pb; }
             // adjoint terms H, two shifted copies (A for the left band, Bs for
             // the right) zero padded on both sides: H_t sits at PX(t + hA)
             // with hA = kl0 - 1 (mod 8), so that the transposed window of
@@ -814,16 +924,40 @@ __global__ void __launch_bounds__(FNT, FWAVES_BWD) stl_fused_bwd(DevPlan plan, B
 #pragma unroll
             for (int i = 0; i < FNO; ++i) {
                 // the term 2^{z_j - R} again, from the exponent kept in registers
-                gv[i] = c0 + i < L ? (float)ldexp(Bd[i] * exp2d_neg(z[i] - (float)op.R), op.R + Q) : 0.f;
+                gv[i] = c0 + i < L ? (float)ldexp(Bd[i] * exp2d_neg(zm[i] - (float)op.R), op.R + Q) : 0.f;
             }
         }
-        // dx += w_m gv on this thread's rows (the first mask initialises them;
-        // each row is read and written by its owning thread only)
-        const float* cf = op.cf;
-        const int n8 = min(FNO, L - c0);
-        for (int i = 0; i < n8; ++i) {
-            float* row = dx + (int64_t)(c0 + i) * D;
-            for (int d = 0; d < D; ++d) row[d] = (m == 0 ? 0.f : row[d]) + cf[1 + d] * gv[i];
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) gvs[k][i] = k == m ? gv[i] : gvs[k][i];
+    }
+    // dx_j = sum_m w_m gv_m[j] (masks in order), this thread's FNO*D consecutive floats
+    float* dxr = ka.dx + (b * (int64_t)L + c0) * D;
+    if (D == 2 && c0 + FNO <= L && (((uintptr_t)dxr) & 15) == 0) {
+        float v[2 * FNO];
+#pragma unroll
+        for (int i = 0; i < FNO; ++i)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                float acc = 0.f;
+#pragma unroll
+                for (int m = 0; m < N; ++m) acc = acc + sh.m_coef[m][1 + d] * gvs[m][i];
+                v[2 * i + d] = acc;
+            }
+        float4* q = (float4*)dxr;
+#pragma unroll
+        for (int k = 0; k < FNO / 2; ++k) q[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) {
+            if (c0 + i >= L) break;
+            for (int d = 0; d < D; ++d) {
+                float acc = 0.f;
+#pragma unroll
+                for (int m = 0; m < N; ++m) acc = acc + sh.m_coef[m][1 + d] * gvs[m][i];
+                dxr[(size_t)i * D + d] = acc;
+            }
         }
     }
 }
