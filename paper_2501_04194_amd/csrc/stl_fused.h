@@ -58,8 +58,12 @@ struct MaskTab {
 struct FShared {
     double wv[FNW];
     int wf[FNW];
+    double wv2[FNW];
+    int wf2[FNW];
     int wi[FNW];
     int wn[FMAXN][FNW];
+    int wq[FMAXN][FNW];
+    double wp[2 * FMAXN][FNW];
     // per mask node (filled by fused_enter): sign, beta, predicate coefficient
     // offset, gradient slot; read with a runtime mask index from LDS rather
     // than from the kernel argument
@@ -176,6 +180,73 @@ DEV void fscan(const double* vin, double* out, int n, int K, int off, FShared& s
 #pragma unroll
     for (int i = 0; i < FNO; ++i)
         if (c0 + i < n) out[PX(c0 + i)] = v[i];
+    __syncthreads();
+}
+
+// Both block scans of the same values in one pass (two barriers in all):
+// pre = segmented inclusive prefix with heads where (p + off) % K == 0, suf =
+// segmented inclusive suffix with tails where (p + off) % K == K-1 and at n-1
+// (the van Herk block prefixes and suffixes), written to the padded LDS
+// arrays pre[0..n) and suf[0..n).  Values past n must be 0.
+DEV void fscan2(const double* vin, double* pre, double* suf, int n, int K, int off, FShared& sh, int tid)
+{
+    const int lane = tid & 63, w = tid >> 6;
+    const int c0 = FNO * tid;
+    double vf[FNO], vr[FNO];
+    int hf = 0, hr = 0;
+    int rem = (c0 + off) % K;
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) {
+        const int p = c0 + i;
+        const bool in = p < n;
+        hf |= (in && rem == 0) ? (1 << i) : 0;
+        hr |= (in && (p == n - 1 || rem == K - 1)) ? (1 << i) : 0;
+        rem = rem + 1 == K ? 0 : rem + 1;
+    }
+    double af = 0.0, ar = 0.0;
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) { af = ((hf >> i) & 1) ? vin[i] : af + vin[i]; vf[i] = af; }
+#pragma unroll
+    for (int i = FNO - 1; i >= 0; --i) { ar = ((hr >> i) & 1) ? vin[i] : vin[i] + ar; vr[i] = ar; }
+    // wave-level segmented scans of the per-thread totals (forward: up; reverse: down)
+    double a = af, r = ar;
+    int f = hf != 0, g = hr != 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double ao = __shfl_up(a, d), ro = __shfl_down(r, d);
+        const int fo = __shfl_up(f, d), go = __shfl_down(g, d);
+        if (lane >= d) {
+            if (!f) a = ao + a;
+            f |= fo;
+        }
+        if (lane + d < 64) {
+            if (!g) r = ro + r;
+            g |= go;
+        }
+    }
+    double exf = __shfl_up(a, 1), exr = __shfl_down(r, 1);
+    int eff = __shfl_up(f, 1), efr = __shfl_down(g, 1);
+    if (lane == 0) { exf = 0.0; eff = 0; }
+    if (lane == 63) { exr = 0.0; efr = 0; }
+    if (lane == 63) { sh.wv[w] = a; sh.wf[w] = f; }
+    if (lane == 0) { sh.wv2[w] = r; sh.wf2[w] = g; }
+    __syncthreads();
+    double cf = 0.0, cr = 0.0;
+    for (int w2 = 0; w2 < w; ++w2) cf = sh.wf[w2] ? sh.wv[w2] : cf + sh.wv[w2];
+    for (int w2 = FNW - 1; w2 > w; --w2) cr = sh.wf2[w2] ? sh.wv2[w2] : cr + sh.wv2[w2];
+    const double carf = eff ? exf : cf + exf;
+    const double carr = efr ? exr : cr + exr;
+    bool gf = true, gr = true;
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) { gf = gf && !((hf >> i) & 1); if (gf) vf[i] += carf; }
+#pragma unroll
+    for (int i = FNO - 1; i >= 0; --i) { gr = gr && !((hr >> i) & 1); if (gr) vr[i] += carr; }
+#pragma unroll
+    for (int i = 0; i < FNO; ++i)
+        if (c0 + i < n) {
+            pre[PX(c0 + i)] = vf[i];
+            suf[PX(c0 + i)] = vr[i];
+        }
     __syncthreads();
 }
 
@@ -501,8 +572,7 @@ DEV void mask_trace(const DevPlan& P, const MaskTab& T, FOp& op, const float* z,
     }
     if (T.core) {
         __syncthreads();                              // band reads of the term copies are done
-        fscan<false>(e, A, L, T.K, T.off, sh, tid);   // block prefixes over the terms
-        fscan<true>(e, Bs, L, T.K, T.off, sh, tid);   // block suffixes
+        fscan2(e, A, Bs, L, T.K, T.off, sh, tid);      // block prefixes and suffixes of the terms
         if (c0 < L) {
             const int K = T.K, s0 = c0 + T.clo;
             const int qL = (L - 1 + T.off) / K;
@@ -781,7 +851,38 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
         }
     }
     float* mp = ka.mask_part + b * P.n_masks * 2;
+    // Q_m: the per-trajectory exponent of max |G_m 2^{-O}|, all masks in one reduction
+    int Qs[N];
+    {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const int klo = ka.tabs[m].klo;
+            int qloc = INT_MIN;
+#pragma unroll
+            for (int i = 0; i < FNO; ++i) {
+                const int t = c0 + i;
+                if (t < L && t + klo <= L - 1 && gm[m][i] != 0.f) {
+                    int eg;
+                    frexpf(gm[m][i], &eg);
+                    qloc = max(qloc, eg - (int)floorf(tr[m][i]));
+                }
+            }
+            for (int d = 32; d > 0; d >>= 1) qloc = max(qloc, __shfl_xor(qloc, d));
+            if (lane == 0) sh.wq[m][w] = qloc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            int q = sh.wq[m][0];
+            for (int k = 1; k < FNW; ++k) q = max(q, sh.wq[m][k]);
+            Qs[m] = q == INT_MIN ? 0 : q;
+        }
+    }
     float gvs[N][FNO];            // per mask: d root / d (w_m . x_j) for this thread's j
+    double pab[2 * N];            // per mask: this thread's d/da, d/db partials
+#pragma unroll
+    for (int k = 0; k < 2 * N; ++k) pab[k] = 0.0;
 #pragma unroll 1
     for (int m = 0; m < N; ++m) {
         const int tid = opaque_tid();
@@ -804,7 +905,6 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
         }
         float gv[FNO];
         if (!T.any) {
-            if (mslot >= 0 && tid == 0) { mp[2 * mslot] = 0.f; mp[2 * mslot + 1] = 0.f; }
 #pragma unroll
             for (int i = 0; i < FNO; ++i) gv[i] = 0.f;
         } else {
@@ -815,19 +915,8 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
                 double e[FNO];
                 fused_terms(zm, op.R, L, e, A, Bs, shA, shB, sh, tid);
             }
-            // H_t = G_m[t] 2^{-O_t - Q}, Q the per-trajectory exponent of max |G_m 2^{-O}|
-            int qloc = INT_MIN;
-#pragma unroll
-            for (int i = 0; i < FNO; ++i) {
-                const int t = c0 + i;
-                if (t < L && t + T.klo <= L - 1 && g[i] != 0.f) {
-                    int eg;
-                    frexpf(g[i], &eg);
-                    qloc = max(qloc, eg - (int)floorf(om[i]));
-                }
-            }
-            const int qm = wg_max_i(qloc, sh);
-            const int Q = qm == INT_MIN ? 0 : qm;
+            // H_t = G_m[t] 2^{-O_t - Q}
+            const int Q = select_int<N>(Qs, m);
             double h[FNO];
 #pragma unroll
             for (int i = 0; i < FNO; ++i) {
@@ -854,9 +943,12 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
                     deriv_band(Bs, c0 + T.kr0 + shB, T.Dbr, T.nz_br, nr, hr, zp, h, sc, k0, pb);
                 }
             }
-            pa = wg_sum_d(pa, sh);     // (contains barriers: every E read above is done)
-            pb = wg_sum_d(pb, sh);
-            if (mslot >= 0 && tid == 0) { mp[2 * mslot] = (float)pa; mp[2 * mslot + 1] = (float)pb; }
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                pab[2 * k] = k == m ? pa : pab[2 * k];
+                pab[2 * k + 1] = k == m ? pb : pab[2 * k + 1];
+            }
+            __syncthreads();              // every read of the term copies is done
             // adjoint terms H, two shifted copies (A for the left band, Bs for
             // the right) zero padded on both sides: H_t sits at PX(t + hA)
             // with hA = kl0 - 1 (mod 8), so that the transposed window of
@@ -899,8 +991,7 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
             // dx core: van Herk over t of H, windows [j - chi, j - clo] (heads at t % K == 0)
             if (T.core) {
                 __syncthreads();                         // H reads done: A, Bs receive the block sums
-                fscan<false>(h, A, L, T.K, 0, sh, tid);
-                fscan<true>(h, Bs, L, T.K, 0, sh, tid);
+                fscan2(h, A, Bs, L, T.K, 0, sh, tid);
                 const double wc = (double)T.wc;
                 const int K = T.K;
                 // window of j over t: [j - chi, j - clo]; j - clo <= L - 1 always, so
@@ -931,6 +1022,23 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
         for (int k = 0; k < N; ++k)
 #pragma unroll
             for (int i = 0; i < FNO; ++i) gvs[k][i] = k == m ? gv[i] : gvs[k][i];
+    }
+    // d/da, d/db per mask: deterministic work-group sums (fixed shuffle tree, waves in order)
+    {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int k = 0; k < 2 * N; ++k) {
+            double v = pab[k];
+            for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+            if (lane == 0) sh.wp[k][w] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * N) {
+            const int k = threadIdx.x, m = k >> 1;
+            double r = sh.wp[k][0];
+            for (int ww = 1; ww < FNW; ++ww) r += sh.wp[k][ww];
+            if (sh.m_slot[m] >= 0) mp[2 * sh.m_slot[m] + (k & 1)] = (float)r;
+        }
     }
     // dx_j = sum_m w_m gv_m[j] (masks in order), this thread's FNO*D consecutive floats
     float* dxr = ka.dx + (b * (int64_t)L + c0) * D;
