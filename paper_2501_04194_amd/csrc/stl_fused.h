@@ -610,6 +610,7 @@ DEV int opaque_tid()
 {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
+    __builtin_assume(t >= 0 && t < FNT);
     return t;
 }
 
@@ -666,18 +667,22 @@ DEV float fused_root(const DevPlan& P, const float* params, const float* v, floa
         return v[0];
     }
     const float sg = F.nary_min ? -1.f : 1.f;
-    const float bl = params[F.nary_beta] * LOG2E;
+    const float bl = params[F.nary_beta] * LOG2E, ibl = 1.f / bl;
     float m = -INFINITY;
 #pragma unroll
     for (int k = 0; k < N; ++k) m = fmaxf(m, sg * v[k]);
-    float s = 0.f;
+    float s = 0.f, ek[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) s += exp2f((sg * v[k] - m) * bl);
-    const float r = sg * (m + log2f(s) / bl);
+    for (int k = 0; k < N; ++k) {
+        ek[k] = exp2f((sg * v[k] - m) * bl);
+        s += ek[k];
+    }
+    const float r = sg * (m + log2f(s) * ibl);
     if (wts) {
-        const float o = sg * r;
+        // softmax weights e_k / s (s >= 1: the largest term is 1)
+        const float is = __builtin_amdgcn_rcpf(s);
 #pragma unroll
-        for (int k = 0; k < N; ++k) wts[k] = exp2f((sg * v[k] - o) * bl);
+        for (int k = 0; k < N; ++k) wts[k] = ek[k] * is;
     }
     return r;
 }
@@ -741,13 +746,16 @@ DEV void load8f(const float* p, int c0, int L, float* v)
     }
 }
 
-template <int N>
+// FULL: T == FNT * FNO exactly (every thread owns FNO valid timesteps; the
+// bounds checks fold away)
+template <int N, bool FULL>
 __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_FWD)) stl_fused_fwd(DevPlan plan, Batch bt, KArgs ka)
 {
     extern __shared__ double fsm[];
     __shared__ FShared sh;
     const DevPlan& P = plan;
-    const int L = (int)bt.T, Lc = bt.Lcap, D = bt.D;
+    const int L = FULL ? FNT * FNO : (int)bt.T, Lc = FULL ? FNT * FNO : bt.Lcap, D = bt.D;
+    __builtin_assume(threadIdx.x < FNT);
     const int64_t b = blockIdx.x;
     const int pl = fused_arr_len(Lc);
     double* A = fsm;
@@ -801,14 +809,15 @@ DEV void deriv_band(const double* A, int base, const double* W, int nz, int nW, 
     for (int i = 0; i < FNO; ++i) p = fma(ldexp(h[i], sc) * k0, S[i], p);     // sg G_m 2^{R - O_t} / beta
 }
 
-template <int N>
+template <int N, bool FULL>
 __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd(DevPlan plan, Batch bt, KArgs ka)
 {
     extern __shared__ double fsm[];
     __shared__ FShared sh;
     const DevPlan& P = plan;
     const FusedDesc& F = P.fused;
-    const int L = (int)bt.T, Lc = bt.Lcap, D = bt.D;
+    const int L = FULL ? FNT * FNO : (int)bt.T, Lc = FULL ? FNT * FNO : bt.Lcap, D = bt.D;
+    __builtin_assume(threadIdx.x < FNT);
     const int64_t b = blockIdx.x;
     const int pl = fused_arr_len(Lc);
     double* A = fsm;             // terms E, then adjoint terms H, then block prefixes (shifted copies
@@ -863,8 +872,8 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
             for (int i = 0; i < FNO; ++i) {
                 const int t = c0 + i;
                 if (t < L && t + klo <= L - 1 && gm[m][i] != 0.f) {
-                    int eg;
-                    frexpf(gm[m][i], &eg);
+                    // frexp exponent of a normal G_m (an upper bound for a subnormal one)
+                    const int eg = ((__float_as_int(gm[m][i]) >> 23) & 0xff) - 126;
                     qloc = max(qloc, eg - (int)floorf(tr[m][i]));
                 }
             }

@@ -1200,12 +1200,17 @@ hipError_t launch_fused(bool bwd, const DevPlan& plan, const Batch& bt, const KA
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)bt.B), block(FNT);
-#define STLMI_FUSED_CASE(NN)                                                              \
-    case NN:                                                                              \
-        if (bwd)                                                                          \
-            hipLaunchKernelGGL(stl_fused_bwd<NN>, grid, block, lds, s, plan, bt, ka);     \
-        else                                                                              \
-            hipLaunchKernelGGL(stl_fused_fwd<NN>, grid, block, lds, s, plan, bt, ka);     \
+    const bool full = bt.T == FNT * FNO && bt.Lcap == FNT * FNO;
+#define STLMI_FUSED_CASE(NN)                                                                            \
+    case NN:                                                                                            \
+        if (bwd && full)                                                                                \
+            hipLaunchKernelGGL((stl_fused_bwd<NN, true>), grid, block, lds, s, plan, bt, ka);           \
+        else if (bwd)                                                                                   \
+            hipLaunchKernelGGL((stl_fused_bwd<NN, false>), grid, block, lds, s, plan, bt, ka);          \
+        else if (full)                                                                                  \
+            hipLaunchKernelGGL((stl_fused_fwd<NN, true>), grid, block, lds, s, plan, bt, ka);           \
+        else                                                                                            \
+            hipLaunchKernelGGL((stl_fused_fwd<NN, false>), grid, block, lds, s, plan, bt, ka);          \
         break;
     switch (plan.fused.n) {
         STLMI_FUSED_CASE(1)
@@ -1221,9 +1226,13 @@ hipError_t launch_fused(bool bwd, const DevPlan& plan, const Batch& bt, const KA
 
 hipError_t set_max_lds_fused(size_t bytes)
 {
-    const void* fns[] = {(const void*)stl_fused_fwd<1>, (const void*)stl_fused_fwd<2>, (const void*)stl_fused_fwd<3>,
-                         (const void*)stl_fused_fwd<4>, (const void*)stl_fused_bwd<1>, (const void*)stl_fused_bwd<2>,
-                         (const void*)stl_fused_bwd<3>, (const void*)stl_fused_bwd<4>};
+    const void* fns[] = {
+        (const void*)stl_fused_fwd<1, false>, (const void*)stl_fused_fwd<2, false>, (const void*)stl_fused_fwd<3, false>,
+        (const void*)stl_fused_fwd<4, false>, (const void*)stl_fused_bwd<1, false>, (const void*)stl_fused_bwd<2, false>,
+        (const void*)stl_fused_bwd<3, false>, (const void*)stl_fused_bwd<4, false>, (const void*)stl_fused_fwd<1, true>,
+        (const void*)stl_fused_fwd<2, true>, (const void*)stl_fused_fwd<3, true>, (const void*)stl_fused_fwd<4, true>,
+        (const void*)stl_fused_bwd<1, true>, (const void*)stl_fused_bwd<2, true>, (const void*)stl_fused_bwd<3, true>,
+        (const void*)stl_fused_bwd<4, true>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
