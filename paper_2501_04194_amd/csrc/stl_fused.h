@@ -101,11 +101,16 @@ DEV double wg_sum_d(double v, FShared& sh)
     return r;
 }
 
+// hardware 2^x and log2(x) (one instruction each, about 1 ulp); used only
+// where the argument keeps the result a normal float
+DEV float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+DEV float lg2(float x) { return __builtin_amdgcn_logf(x); }
+
 DEV float log2d(double s)
 {
     int e;
-    double m = frexp(s, &e);
-    return (float)e + log2f((float)m);
+    double m = frexp(s, &e);                    // m in [0.5, 1)
+    return (float)e + lg2((float)m);
 }
 
 // 2^d as a double for d <= 0 (log2 units): exact exponent split
@@ -113,7 +118,7 @@ DEV double exp2d_neg(float d)
 {
     float fl = floorf(d);
     int ip = (int)fmaxf(fl, -1100.f);
-    return ldexp((double)exp2f(d - fl), ip);
+    return ldexp((double)ex2(d - fl), ip);      // d - fl in [0, 1)
 }
 
 // Segmented inclusive scan of the FNO values vin[] owned by this thread
@@ -674,10 +679,10 @@ DEV float fused_root(const DevPlan& P, const float* params, const float* v, floa
     float s = 0.f, ek[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        ek[k] = exp2f((sg * v[k] - m) * bl);
+        ek[k] = ex2((sg * v[k] - m) * bl);      // <= 1; tiny terms may flush to 0
         s += ek[k];
     }
-    const float r = sg * (m + log2f(s) * ibl);
+    const float r = sg * (m + lg2(s) * ibl);   // s in [1, N]
     if (wts) {
         // softmax weights e_k / s (s >= 1: the largest term is 1)
         const float is = __builtin_amdgcn_rcpf(s);
@@ -933,7 +938,7 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
                 h[i] = 0.0;
                 if (t < L && t + T.klo <= L - 1) {
                     const float fl = floorf(om[i]);
-                    h[i] = ldexp((double)(g[i] * exp2f(fl - om[i])), -(int)fl - Q);
+                    h[i] = ldexp((double)(g[i] * ex2(fl - om[i])), -(int)fl - Q);   // fl - om in (-1, 0]
                 }
             }
             // d/da, d/db: sum_t sg G_m[t]/beta * sum_k dw_k 2^{z_{t+k} - O_t}, over the bands
