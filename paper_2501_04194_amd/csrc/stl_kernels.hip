@@ -734,6 +734,263 @@ DEV void until_smooth_adj(const Env& e, const Instr& I, const SP* Ephi, const SP
     }
 }
 
+// Smooth Until in fp64 against one reference exponent per trajectory.  The
+// leaf terms 2^u, u = -beta log2(e) (phi or psi), are kept as the doubles
+// 2^{u - M} with M = ceil(max u) over both inputs: every term is <= 1, so the
+// running sums, their reciprocals and the outer sums stay inside the fp64
+// range while the exponent range max u - min u is below UF_RANGE.  Beyond it
+// (or with a non-finite value) the scaled-pair routines above take over.
+constexpr int UF_RANGE = 1000;
+
+// 2^{u - M} with exact exponent bookkeeping (u - ceil(u) is exact)
+DEV double uterm(float u, int M)
+{
+    const float c = ceilf(u);
+    return ldexp((double)__builtin_amdgcn_exp2f(u - c), (int)c - M);
+}
+
+// 1/d for a positive normal d: hardware estimate and one Newton step
+DEV double rcpd(double d)
+{
+    const double y = __builtin_amdgcn_rcp(d);
+    return fma(y, fma(-d, y, 1.0), y);
+}
+
+// log2 of a positive double, as the double (exponent - M) + log2(mantissa)
+DEV double log2_minus(double z, int M)
+{
+    int ez;
+    const double mz = frexp(z, &ez);
+    return (double)(ez - M) + (double)__builtin_amdgcn_logf((float)mz);
+}
+
+// Reference exponent M of the two leaf traces; false when the fp64 form
+// cannot hold them.
+DEV bool until_ref(const float* phi, const float* psi, int L, float bl, Shared& sh, int& M)
+{
+    int hi = INT_MIN, lo = INT_MAX, bad = 0;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        const float u1 = -bl * phi[j], u2 = -bl * psi[j];
+        if (!(fabsf(u1) < 1e9f) || !(fabsf(u2) < 1e9f)) {
+            bad = 1;                                 // also catches NaN
+        } else {
+            hi = max(hi, (int)ceilf(fmaxf(u1, u2)));
+            lo = min(lo, (int)floorf(fminf(u1, u2)));
+        }
+    }
+    if (threadIdx.x == 0) {
+        sh.ints[2] = INT_MIN;
+        sh.ints[3] = INT_MAX;
+        sh.ints[4] = 0;
+    }
+    __syncthreads();
+    atomicMax(&sh.ints[2], hi);
+    atomicMin(&sh.ints[3], lo);
+    if (bad) atomicOr(&sh.ints[4], 1);
+    __syncthreads();
+    M = sh.ints[2];
+    const bool ok = sh.ints[4] == 0 && (long long)M - (long long)sh.ints[3] <= UF_RANGE;
+    __syncthreads();
+    return ok;
+}
+
+// leaf terms of both inputs as doubles 2^{u - M} (Ep, Eq)
+DEV void until_terms(const float* phi, const float* psi, int L, float bl, int M, double* Ep, double* Eq)
+{
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        Ep[j] = uterm(-bl * phi[j], M);
+        Eq[j] = uterm(-bl * psi[j], M);
+    }
+    __syncthreads();
+}
+
+typedef __attribute__((address_space(3))) double lds_double;
+typedef __attribute__((address_space(3))) float lds_float;
+
+// true when p points into the work-group's LDS (the arena placement is chosen per launch)
+DEV bool in_lds(const void* p)
+{
+    return __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)p);
+}
+
+// Z = sum_{i=a}^{imax} 1 / (P_i + q_i), P_i = sum_{k<=i} p_k, over the terms of
+// one output.  The terms are read eight at a time (independent loads ahead of
+// the dependent sums); the additions keep the plain sequential order.
+template <class DP>
+DEV double until_z(DP ep, DP eq, int a, int imax)
+{
+    double P = 0.0, Z = 0.0;
+    int i = 0;
+    for (; i + 8 <= a; i += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = ep[i + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) P += v[k];
+    }
+    for (; i < a; ++i) P += ep[i];
+    for (; i + 8 <= imax + 1; i += 8) {
+        double v[8], q[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v[k] = ep[i + k];
+            q[k] = eq[i + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            P += v[k];
+            Z += rcpd(P + q[k]);
+        }
+    }
+    for (; i <= imax; ++i) {
+        P += ep[i];
+        Z += rcpd(P + eq[i]);
+    }
+    return Z;
+}
+
+// Forward on the fp64 terms: the same sums as until_smooth_fwd, with
+// Y_i = 2^{-M} / (P_i + Q_i) in true units, so log2 Z_true = log2 Z - M.
+template <class DP>
+DEV void until_fwd_d(const Env& e, const Instr& I, DP Ep, DP Eq, float* out, float bl, int M)
+{
+    const int L = e.L, a = I.a, b = I.b;
+    const float rho_pad = e.P->rho_pad;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
+        if (a > imax) { out[t] = -rho_pad; continue; }
+        const double Z = until_z(Ep + t, Eq + t, a, imax);
+        out[t] = (float)(log2_minus(Z, M) / (double)bl);
+    }
+}
+
+// value of the lane below (lane 0 receives 0): one DPP wave shift
+DEV float lane_shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+
+// Adjoint on the fp64 terms (the derivatives are ratios of terms, so the
+// reference cancels).  A forward sweep keeps P every UCK steps; the reverse
+// sweep rebuilds each block's P from its checkpoint and carries the suffix
+// sum A of Y_i^2:
+//   d out / d psi_{t+i} = Y_i^2 q_i / Z,  d out / d phi_{t+k} = p_k A_k / Z.
+// The lanes of a wave hold consecutive t and walk i downwards in step, so at
+// each step lane l adds to position t_0 + l + i: the wave keeps one register
+// accumulator per lane for these positions and moves them up one lane per
+// step.  The position leaving lane 63 is complete for this wave and is added
+// to the adjoint slot (one lane, one atomic); the rest are added at the end.
+template <class DP, class CP, class FP>
+DEV void until_adj_d(const Env& e, const Instr& I, DP Ep, DP Eq, const float* g, FP gphi, FP gpsi, CP ck,
+                     int ncks)
+{
+    const int L = e.L, a = I.a, b = I.b;
+    const int lane = threadIdx.x & 63;
+    for (int tb = (int)threadIdx.x - lane; tb < L; tb += blockDim.x) {
+        const int t = tb + lane;
+        const int imax = t >= L ? -1 : (b < 0 ? L - 1 - t : min(b, L - 1 - t));
+        const float gt = t < L ? g[t] : 0.f;
+        const bool act = a <= imax && gt != 0.f;
+        const int nblk = act ? imax / UCK + 1 : 0;
+        const DP ep = Ep + t;
+        const DP eq = Eq + t;
+        const CP myck = ck + (size_t)threadIdx.x * ncks;
+        double Z = 1.0;
+        if (act) {
+            double P = 0.0;
+            Z = 0.0;
+            for (int blk = 0; blk < nblk; ++blk) {
+                const int i0 = blk * UCK;
+                myck[blk] = P;
+                if (i0 + UCK <= imax + 1) {
+                    double v[UCK], q[UCK];
+#pragma unroll
+                    for (int k = 0; k < UCK; ++k) {
+                        v[k] = ep[i0 + k];
+                        q[k] = eq[i0 + k];
+                    }
+#pragma unroll
+                    for (int k = 0; k < UCK; ++k) {
+                        P += v[k];
+                        if (i0 + k >= a) Z += rcpd(P + q[k]);
+                    }
+                } else {
+                    for (int i = i0; i <= imax; ++i) {
+                        P += ep[i];
+                        if (i >= a) Z += rcpd(P + eq[i]);
+                    }
+                }
+            }
+        }
+        const double wz = act ? (double)gt / Z : 0.0;
+        int wblk = nblk;
+        for (int d = 32; d > 0; d >>= 1) wblk = max(wblk, __shfl_xor(wblk, d));
+        float accp = 0.f, accq = 0.f;
+        double A = 0.0;                     // suffix sum of Y_i^2
+        for (int blk = wblk - 1; blk >= 0; --blk) {
+            const int i0 = blk * UCK;
+            const int n = blk < nblk ? min(UCK, imax - i0 + 1) : 0;
+            double v[UCK], q[UCK], Ps[UCK];
+            double Pc = n > 0 ? myck[blk] : 0.0;
+#pragma unroll
+            for (int k = 0; k < UCK; ++k) {
+                v[k] = k < n ? ep[i0 + k] : 0.0;
+                q[k] = k < n ? eq[i0 + k] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < UCK; ++k) {
+                Pc += v[k];
+                Ps[k] = Pc;
+            }
+#pragma unroll
+            for (int k = UCK - 1; k >= 0; --k) {
+                const int i = i0 + k;
+                if (k < n) {
+                    if (i >= a) {
+                        const double y = rcpd(Ps[k] + q[k]);
+                        const double y2 = y * y;
+                        A += y2;
+                        accq += (float)(wz * y2 * q[k]);
+                    }
+                    accp += (float)(wz * A * v[k]);
+                }
+                if (i > 0) {
+                    if (lane == 63 && tb + 63 + i < L) {
+                        __hip_atomic_fetch_add(gphi + tb + 63 + i, accp, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_add(gpsi + tb + 63 + i, accq, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    accp = lane_shr1(accp);
+                    accq = lane_shr1(accq);
+                }
+            }
+        }
+        if (wblk > 0 && t < L) {
+            __hip_atomic_fetch_add(gphi + t, accp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(gpsi + t, accq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+}
+
+DEV void until_smooth_fwd_d(const Env& e, const Instr& I, double* Ep, double* Eq, float* out, float bl, int M)
+{
+    if (in_lds(Ep))
+        until_fwd_d(e, I, (const lds_double*)Ep, (const lds_double*)Eq, out, bl, M);
+    else
+        until_fwd_d(e, I, (const double*)Ep, (const double*)Eq, out, bl, M);
+}
+
+DEV void until_smooth_adj_d(const Env& e, const Instr& I, double* Ep, double* Eq, const float* g, float* gphi,
+                            float* gpsi, double* ck, int ncks)
+{
+    if (in_lds(Ep))
+        until_adj_d(e, I, (const lds_double*)Ep, (const lds_double*)Eq, g, (lds_float*)gphi, (lds_float*)gpsi,
+                    (lds_double*)ck, ncks);
+    else
+        until_adj_d(e, I, (const double*)Ep, (const double*)Eq, g, gphi, gpsi, ck, ncks);
+}
+
 // ------------------------------------------------------------------ instructions
 
 DEV bool is_smooth(const Instr& I) { return I.flags & F_SMOOTH; }
@@ -828,6 +1085,14 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
             until_hard(e, I, phi, psi, out, nullptr, nullptr, nullptr);
         } else {
             const float bl = pbeta(e, I) * LOG2E;
+            int M;
+            if (until_ref(phi, psi, L, bl, *e.sh, M)) {
+                double* Ep = (double*)S(e, 0);
+                double* Eq = (double*)S(e, 2);
+                until_terms(phi, psi, L, bl, M, Ep, Eq);
+                until_smooth_fwd_d(e, I, Ep, Eq, out, bl, M);
+                break;
+            }
             SP* Ephi = (SP*)S(e, 0);
             SP* Epsi = (SP*)S(e, 2);
             for (int j = threadIdx.x; j < L; j += blockDim.x) {
@@ -996,15 +1261,23 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
             until_hard(e, I, phi, psi, nullptr, g, gphi, gpsi);
         } else {
             const float bl = pbeta(e, I) * LOG2E;
-            SP* Ephi = (SP*)S(e, 0);
-            SP* Epsi = (SP*)S(e, 2);
-            for (int j = threadIdx.x; j < L; j += blockDim.x) {
-                Ephi[j] = sp_leaf(-bl * phi[j]);
-                Epsi[j] = sp_leaf(-bl * psi[j]);
-            }
-            __syncthreads();
             const int bmax = I.b < 0 ? L - 1 : min(I.b, L - 1);
-            until_smooth_adj(e, I, Ephi, Epsi, g, gphi, gpsi, (SP*)S(e, 4), bmax / UCK + 1);
+            int M;
+            if (until_ref(phi, psi, L, bl, *e.sh, M)) {
+                double* Ep = (double*)S(e, 0);
+                double* Eq = (double*)S(e, 2);
+                until_terms(phi, psi, L, bl, M, Ep, Eq);
+                until_smooth_adj_d(e, I, Ep, Eq, g, gphi, gpsi, (double*)S(e, 4), bmax / UCK + 1);
+            } else {
+                SP* Ephi = (SP*)S(e, 0);
+                SP* Epsi = (SP*)S(e, 2);
+                for (int j = threadIdx.x; j < L; j += blockDim.x) {
+                    Ephi[j] = sp_leaf(-bl * phi[j]);
+                    Epsi[j] = sp_leaf(-bl * psi[j]);
+                }
+                __syncthreads();
+                until_smooth_adj(e, I, Ephi, Epsi, g, gphi, gpsi, (SP*)S(e, 4), bmax / UCK + 1);
+            }
         }
         // d phi / d psi are sums of scaled terms: convert the scaled psi/phi sums in place
         break;
