@@ -150,6 +150,21 @@ def test_smooth_until(ab):
     check_formula(spec, x, what="until%s" % (ab,))
 
 
+def test_smooth_until_wide_range():
+    """Traces whose exponent range (beta log2(e) (max - min)) is far beyond the
+    fp64 form's limit take the scaled-pair path; a TRUE left child does too."""
+    rng = np.random.default_rng(6)
+    x = walk(rng, 3, 300, D=2, s=0.1) * np.float32(60.0)
+    for ab in [(0, 40), (10, None)]:
+        spec = {"op": "until", "a": ab[0], "b": ab[1], "smooth": True, "beta": 10.0,
+                "left": {"op": "linear", "w": [1, 0], "c": -0.5}, "right": {"op": "linear", "w": [0, 1], "c": 0.1}}
+        check_formula(spec, x, what="wide until%s" % (ab,))
+    x = walk(rng, 2, 200, D=2, s=0.1)
+    spec = {"op": "until", "a": 3, "b": 50, "smooth": True, "beta": 10.0,
+            "left": {"op": "true"}, "right": {"op": "linear", "w": [0, 1], "c": 0.1}}
+    check_formula(spec, x, what="true until")
+
+
 # --------------------------------------------------------------------------- smooth masks
 
 MASKS = [
