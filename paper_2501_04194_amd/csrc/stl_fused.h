@@ -51,7 +51,8 @@ struct MaskTab {
     int nz_ar, nz_br;           // right band: same
     float wc;                   // core weight
     double Wl[FMAXB], Wr[FMAXB];                          // band weights
-    double Dal[FMAXB], Dar[FMAXB], Dbl[FMAXB], Dbr[FMAXB];  // d w / d a, d w / d b
+    // reversed d w / d a and d w / d b (D[nW-1-s]), for the transposed sums of the backward
+    double Dalr[FMAXB + 8], Darr[FMAXB + 8], Dblr[FMAXB + 8], Dbrr[FMAXB + 8];
     double Wlr[FMAXB + 8], Wrr[FMAXB + 8];                // reversed (W[nW-1-s]), for transposed sums
 };
 
@@ -373,35 +374,36 @@ __global__ void __launch_bounds__(256) stl_mask_tables(DevPlan plan, const float
     if (!ok) return;
     const MaskP mp = mask_params(params + I.mask, I.flags & F_MASK_UNB);
     for (int s = threadIdx.x; s < FMAXB + 8; s += blockDim.x) {
-        float wl = 0.f, dal = 0.f, dbl = 0.f, wr = 0.f, dar = 0.f, dbr = 0.f;
+        float wl = 0.f, wr = 0.f;
         if (s < nWl) {
             const int k = kl0 + s;
-            if (k >= mi.klo && k < le) wl = mask_wk(mp, k, &dal, &dbl);
+            if (k >= mi.klo && k < le) wl = mask_wk(mp, k);
         }
         if (s < nWr) {
             const int k = kr0 + s;
-            if (k >= rs && k < re) wr = mask_wk(mp, k, &dar, &dbr);
+            if (k >= rs && k < re) wr = mask_wk(mp, k);
         }
         if (s < FMAXB) {
             T.Wl[s] = wl;
-            T.Dal[s] = dal;
-            T.Dbl[s] = dbl;
             T.Wr[s] = wr;
-            T.Dar[s] = dar;
-            T.Dbr[s] = dbr;
         }
-        // reversed: Wlr[s] = Wl[nWl - 1 - s] for 0 <= s < nWl
-        float wlr = 0.f, wrr = 0.f;
+        // reversed: Wlr[s] = Wl[nWl - 1 - s] for 0 <= s < nWl, and the same for
+        // the derivatives
+        float wlr = 0.f, dal = 0.f, dbl = 0.f, wrr = 0.f, dar = 0.f, dbr = 0.f;
         if (s < nWl) {
             const int k = kl0 + nWl - 1 - s;
-            if (k >= mi.klo && k < le) wlr = mask_wk(mp, k);
+            if (k >= mi.klo && k < le) wlr = mask_wk(mp, k, &dal, &dbl);
         }
         if (s < nWr) {
             const int k = kr0 + nWr - 1 - s;
-            if (k >= rs && k < re) wrr = mask_wk(mp, k);
+            if (k >= rs && k < re) wrr = mask_wk(mp, k, &dar, &dbr);
         }
         T.Wlr[s] = wlr;
         T.Wrr[s] = wrr;
+        T.Dalr[s] = dal;
+        T.Dblr[s] = dbl;
+        T.Darr[s] = dar;
+        T.Dbrr[s] = dbr;
         if (dal != 0.f) atomicOr(&sh.ints[4], 1);
         if (dbl != 0.f) atomicOr(&sh.ints[4], 2);
         if (dar != 0.f) atomicOr(&sh.ints[4], 4);
@@ -799,19 +801,81 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_FWD)) stl_fused_fwd
     }
 }
 
-// d/da, d/db contributions of one band: p += sum_i k_i * sum_s dW[s] E[t_i + s]
-// (one weight set at a time: a derivative that is zero over the whole band
-// is skipped, e.g. d/db over the band around a)
-DEV void deriv_band(const double* A, int base, const double* W, int nz, int nW, int hi, int zp, const double* h,
-                    int sc, double k0, double& p)
+// S[i] += sum_{dk<8} W[dk] window[i + dk] and Sd[i] += sum_{dk<8} Wd[dk]
+// window[i + dk]: two weight sets over one window
+DEV void fma_block2(double* S, double* Sd, const double* __restrict__ W, const double* __restrict__ Wd,
+                    const double* a, const double* b)
 {
-    if (nW <= 0 || !nz) return;
-    double S[FNO];
+    const cdptr Wc = (cdptr)W, Dc = (cdptr)Wd;
 #pragma unroll
-    for (int i = 0; i < FNO; ++i) S[i] = 0.0;
-    band_acc(A, base, W, 0, nW, hi, zp, S);
+    for (int dk = 0; dk < 8; ++dk) {
+        const double w = Wc[dk], d = Dc[dk];
 #pragma unroll
-    for (int i = 0; i < FNO; ++i) p = fma(ldexp(h[i], sc) * k0, S[i], p);     // sg G_m 2^{R - O_t} / beta
+        for (int i = 0; i < FNO; ++i) {
+            const int p = i + dk;
+            const double v = p < 8 ? a[p] : b[p - 8];
+            S[i] = fma(w, v, S[i]);
+            Sd[i] = fma(d, v, Sd[i]);
+        }
+    }
+}
+
+// band_acc with a second weight set Wd summed into Sd over the same windows
+DEV void band_acc2(const double* A, int base, const double* __restrict__ W, const double* __restrict__ Wd, int s0,
+                   int nW, int hi, int zp, double* S, double* Sd)
+{
+    if (s0 >= nW) return;
+    int p = base + s0;
+    double x[8], y[8];
+    load8z(x, A, p, hi, zp);
+    load8z(y, A, p + 8, hi, zp);
+    int s = s0;
+    for (;;) {
+        fma_block2(S, Sd, W + s, Wd + s, x, y);
+        s += 8;
+        if (s >= nW) break;
+        p += 8;
+        load8z(x, A, p + 8, hi, zp);
+        fma_block2(S, Sd, W + s, Wd + s, y, x);
+        s += 8;
+        if (s >= nW) break;
+        p += 8;
+        load8z(y, A, p + 8, hi, zp);
+    }
+}
+
+// sum_i E_i v[i] for this thread's timesteps, E_i = 2^{z_i - R} from the exponents
+DEV double edot(const float* zm, int R, int c0, int L, const double* v)
+{
+    double p = 0.0;
+#pragma unroll
+    for (int i = 0; i < FNO; ++i)
+        if (c0 + i < L) p = fma(exp2d_neg(zm[i] - (float)R), v[i], p);
+    return p;
+}
+
+// Transposed sums of one band over the adjoint terms H (window of output j
+// starting at base + s0): Bd += sum_s Wr[s] H, and for the band's derivative
+// tables (reversed d/da Dar, d/db Dbr) pa, pb += sum_j E_j sum_s Dr[s] H.
+// The first non-zero derivative table shares the pass with Bd; a second one
+// (a band that spans both a and b) takes a pass of its own.
+DEV void band_bwd(const double* A, int base, const double* Wr, const double* Dar, const double* Dbr, int nza,
+                  int nzb, int s0, int nW, int hi, int zp, const float* zm, int R, int c0, int L, double* Bd,
+                  double& pa, double& pb)
+{
+    double Dd[FNO];
+#pragma unroll
+    for (int i = 0; i < FNO; ++i) Dd[i] = 0.0;
+    band_acc2(A, base, Wr, nza ? Dar : Dbr, s0, nW, hi, zp, Bd, Dd);
+    const double p1 = edot(zm, R, c0, L, Dd);
+    if (nza) pa += p1;
+    else pb += p1;
+    if (nza && nzb) {
+#pragma unroll
+        for (int i = 0; i < FNO; ++i) Dd[i] = 0.0;
+        band_acc(A, base, Dbr, s0, nW, hi, zp, Dd);
+        pb += edot(zm, R, c0, L, Dd);
+    }
 }
 
 template <int N, bool FULL>
@@ -924,11 +988,6 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
         } else {
             float zm[FNO];
             select_row<N>(z, m, zm);
-            const int shA = band_shift(T.kl0), shB = band_shift(T.kr0);
-            {
-                double e[FNO];
-                fused_terms(zm, op.R, L, e, A, Bs, shA, shB, sh, tid);
-            }
             // H_t = G_m[t] 2^{-O_t - Q}
             const int Q = select_int<N>(Qs, m);
             double h[FNO];
@@ -941,28 +1000,7 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
                     h[i] = ldexp((double)(g[i] * ex2(fl - om[i])), -(int)fl - Q);   // fl - om in (-1, 0]
                 }
             }
-            // d/da, d/db: sum_t sg G_m[t]/beta * sum_k dw_k 2^{z_{t+k} - O_t}, over the bands
-            double pa = 0.0, pb = 0.0;
-            const int zp = fused_zero_at(Lc);
-            {
-                const double k0 = (double)(op.sg / op.beta);
-                const int lim = L - wave_c0(tid), sc = op.R + Q;
-                const int nl = min(T.nWl, max(0, round8(lim - T.kl0)));
-                const int hl = L + FTAIL + shA, hr = L + FTAIL + shB;
-                deriv_band(A, c0 + T.kl0 + shA, T.Dal, T.nz_al, nl, hl, zp, h, sc, k0, pa);
-                deriv_band(A, c0 + T.kl0 + shA, T.Dbl, T.nz_bl, nl, hl, zp, h, sc, k0, pb);
-                if (T.core) {
-                    const int nr = min(T.nWr, max(0, round8(lim - T.kr0)));
-                    deriv_band(Bs, c0 + T.kr0 + shB, T.Dar, T.nz_ar, nr, hr, zp, h, sc, k0, pa);
-                    deriv_band(Bs, c0 + T.kr0 + shB, T.Dbr, T.nz_br, nr, hr, zp, h, sc, k0, pb);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                pab[2 * k] = k == m ? pa : pab[2 * k];
-                pab[2 * k + 1] = k == m ? pb : pab[2 * k + 1];
-            }
-            __syncthreads();              // every read of the term copies is done
+            __syncthreads();              // every read of A and Bs by the previous mask is done
             // adjoint terms H, two shifted copies (A for the left band, Bs for
             // the right) zero padded on both sides: H_t sits at PX(t + hA)
             // with hA = kl0 - 1 (mod 8), so that the transposed window of
@@ -986,26 +1024,45 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
                 Bs[PX(j + hB)] = 0.0;
             }
             __syncthreads();
-            // dx bands: dx_j += sum_k w_k H_{j-k} = sum_s Wrev[s] H_{j - k0 - nW + 1 + s}
+            // band sums over H: dx_j += sum_k w_k H_{j-k} = sum_s Wrev[s] H_{j - k0 - nW + 1 + s},
+            // and for d/da, d/db the same sums with the derivative weights:
+            //   sum_t sg G_m[t]/beta sum_k dw_k 2^{z_{t+k} - O_t} = sg/beta 2^{R+Q} sum_j E_j sum_k dw_k H_{j-k}
             double Bd[FNO];
 #pragma unroll
             for (int i = 0; i < FNO; ++i) Bd[i] = 0.0;
+            const int zp = fused_zero_at(Lc);
             {
+                double pa = 0.0, pb = 0.0;
                 // blocks before t = 0 read as zeros; the wave's last lane (base + 8*63)
                 // fixes the first block any lane of the wave needs
                 const int w0 = wave_c0(tid) + FNO * 63;
                 const int base = c0 - T.kl0 - T.nWl + 1 + hA;      // a multiple of 8
-                band_acc(A, base, T.Wlr, max(0, -(w0 - T.kl0 - T.nWl + 1 + hA)), T.nWl, L + FTAIL + hA, zp, Bd);
+                band_bwd(A, base, T.Wlr, T.Dalr, T.Dblr, T.nz_al, T.nz_bl, max(0, -(w0 - T.kl0 - T.nWl + 1 + hA)),
+                         T.nWl, L + FTAIL + hA, zp, zm, op.R, c0, L, Bd, pa, pb);
                 if (T.core) {
                     const int base2 = c0 - T.kr0 - T.nWr + 1 + hB;
-                    band_acc(Bs, base2, T.Wrr, max(0, -(w0 - T.kr0 - T.nWr + 1 + hB)), T.nWr, L + FTAIL + hB, zp,
-                             Bd);
+                    band_bwd(Bs, base2, T.Wrr, T.Darr, T.Dbrr, T.nz_ar, T.nz_br,
+                             max(0, -(w0 - T.kr0 - T.nWr + 1 + hB)), T.nWr, L + FTAIL + hB, zp, zm, op.R, c0, L, Bd,
+                             pa, pb);
+                }
+                const double k0 = (double)(op.sg / op.beta);
+                pa = ldexp(pa, op.R + Q) * k0;
+                pb = ldexp(pb, op.R + Q) * k0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    pab[2 * k] = k == m ? pa : pab[2 * k];
+                    pab[2 * k + 1] = k == m ? pb : pab[2 * k + 1];
                 }
             }
             // dx core: van Herk over t of H, windows [j - chi, j - clo] (heads at t % K == 0)
             if (T.core) {
+                // H again, from this thread's own entries of the copy in A (not
+                // kept in registers across the band sums)
+                double hr[FNO];
+#pragma unroll
+                for (int i = 0; i < FNO; ++i) hr[i] = A[PX(c0 + i + hA)];
                 __syncthreads();                         // H reads done: A, Bs receive the block sums
-                fscan2(h, A, Bs, L, T.K, 0, sh, tid);
+                fscan2(hr, A, Bs, L, T.K, 0, sh, tid);
                 const double wc = (double)T.wc;
                 const int K = T.K;
                 // window of j over t: [j - chi, j - clo]; j - clo <= L - 1 always, so
@@ -1028,7 +1085,6 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
             }
 #pragma unroll
             for (int i = 0; i < FNO; ++i) {
-                // the term 2^{z_j - R} again, from the exponent kept in registers
                 gv[i] = c0 + i < L ? (float)ldexp(Bd[i] * exp2d_neg(zm[i] - (float)op.R), op.R + Q) : 0.f;
             }
         }
