@@ -79,9 +79,52 @@ DEV int PX(int j) { return j + (j >> 3); }
 __host__ __device__ constexpr int px_len(int n) { return n + (n >> 3) + 16; }
 DEV int round8(int v) { return (v + 7) & ~7; }
 
+// Wave reductions: xor butterflies over each 32-lane half with ds_swizzle
+// (the lane pattern is an immediate, so no per-lane address registers stay
+// live), then the two halves combined from lanes 0 and 32.  The result is
+// wave-uniform; sums use a fixed order.
+template <int XM>
+DEV int swz_xor(int v)
+{
+    return __builtin_amdgcn_ds_swizzle(v, (XM << 10) | 0x1F);
+}
+
+template <int XM>
+DEV double swz_xor(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = swz_xor<XM>((int)b), hi = swz_xor<XM>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+DEV int wave_max_i(int v)
+{
+    v = max(v, swz_xor<1>(v));
+    v = max(v, swz_xor<2>(v));
+    v = max(v, swz_xor<4>(v));
+    v = max(v, swz_xor<8>(v));
+    v = max(v, swz_xor<16>(v));
+    return max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 32));
+}
+
+DEV double wave_sum_d(double v)
+{
+    v += swz_xor<1>(v);
+    v += swz_xor<2>(v);
+    v += swz_xor<4>(v);
+    v += swz_xor<8>(v);
+    v += swz_xor<16>(v);
+    const long long b = __double_as_longlong(v);
+    const long long b0 = ((long long)__builtin_amdgcn_readlane((int)(b >> 32), 0) << 32) |
+                         (unsigned)__builtin_amdgcn_readlane((int)b, 0);
+    const long long b1 = ((long long)__builtin_amdgcn_readlane((int)(b >> 32), 32) << 32) |
+                         (unsigned)__builtin_amdgcn_readlane((int)b, 32);
+    return __longlong_as_double(b0) + __longlong_as_double(b1);
+}
+
 DEV int wg_max_i(int v, FShared& sh)
 {
-    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d));
+    v = wave_max_i(v);
     if ((threadIdx.x & 63) == 0) sh.wi[threadIdx.x >> 6] = v;
     __syncthreads();
     int r = sh.wi[0];
@@ -93,7 +136,7 @@ DEV int wg_max_i(int v, FShared& sh)
 // deterministic work-group sum (fixed shuffle tree, waves in order)
 DEV double wg_sum_d(double v, FShared& sh)
 {
-    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+    v = wave_sum_d(v);
     if ((threadIdx.x & 63) == 0) sh.wv[threadIdx.x >> 6] = v;
     __syncthreads();
     double r = sh.wv[0];
@@ -506,7 +549,7 @@ DEV void fused_refs(const float (&z)[N][FNO], int (&R)[N], FShared& sh)
 #pragma unroll
         for (int i = 0; i < FNO; ++i) zm = fmaxf(zm, z[m][i]);
         int v = (int)ceilf(fminf(fmaxf(zm, -1e9f), 1e9f));
-        for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d));
+        v = wave_max_i(v);
         if (lane == 0) sh.wn[m][w] = v;
     }
     __syncthreads();
@@ -946,7 +989,7 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
                     qloc = max(qloc, eg - (int)floorf(tr[m][i]));
                 }
             }
-            for (int d = 32; d > 0; d >>= 1) qloc = max(qloc, __shfl_xor(qloc, d));
+            qloc = wave_max_i(qloc);
             if (lane == 0) sh.wq[m][w] = qloc;
         }
         __syncthreads();
@@ -1099,7 +1142,7 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
 #pragma unroll
         for (int k = 0; k < 2 * N; ++k) {
             double v = pab[k];
-            for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+            v = wave_sum_d(v);
             if (lane == 0) sh.wp[k][w] = v;
         }
         __syncthreads();
