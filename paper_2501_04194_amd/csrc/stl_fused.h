@@ -46,6 +46,7 @@ struct MaskTab {
     int any;                    // support {w > 0} is non-empty
     int klo, khi, clo, chi;     // support and constant core (clo > chi: no core)
     int core, K, off;           // van Herk block length and head offset (core only)
+    unsigned kmag;              // div_magic(K)
     int kl0, nWl, kr0, nWr;     // bands: first offset and width (a multiple of 8; zero weights pad it)
     int nz_al, nz_bl;           // left band: d/da, d/db weights not all zero
     int nz_ar, nz_br;           // right band: same
@@ -78,6 +79,11 @@ struct FShared {
 DEV int PX(int j) { return j + (j >> 3); }
 __host__ __device__ constexpr int px_len(int n) { return n + (n >> 3) + 16; }
 DEV int round8(int v) { return (v + 7) & ~7; }
+
+// n / K for 0 <= n, n * K < 2^32, with mag = floor(2^32 / K) + 1 (exact in
+// that range); K = 1 is coded as mag = 0
+DEV int div_mag(int n, unsigned mag) { return mag ? (int)__umulhi((unsigned)n, mag) : n; }
+__host__ __device__ inline unsigned div_magic(int K) { return K > 1 ? (unsigned)(0x100000000ull / (unsigned)K) + 1u : 0u; }
 
 // Wave reductions: xor butterflies over each 32-lane half with ds_swizzle
 // (the lane pattern is an immediate, so no per-lane address registers stay
@@ -165,85 +171,19 @@ DEV double exp2d_neg(float d)
     return ldexp((double)ex2(d - fl), ip);      // d - fl in [0, 1)
 }
 
-// Segmented inclusive scan of the FNO values vin[] owned by this thread
-// (timesteps 8*tid .. 8*tid+7), written to the padded LDS array out[0..n).
-// Forward: heads where (p + off) % K == 0; reverse: where (p + off) % K ==
-// K-1 and at n-1.  Values past n must be 0.  Ends with a barrier.
-template <bool REV>
-DEV void fscan(const double* vin, double* out, int n, int K, int off, FShared& sh, int tid)
-{
-    const int lane = tid & 63, w = tid >> 6;
-    const int c0 = FNO * tid;
-    double v[FNO];
-    int hm = 0;
-    int rem = (c0 + off) % K;
-#pragma unroll
-    for (int i = 0; i < FNO; ++i) {
-        const int p = c0 + i;
-        v[i] = vin[i];
-        const bool h = REV ? (p == n - 1 || rem == K - 1) : (rem == 0);
-        hm |= (h && p < n) ? (1 << i) : 0;
-        rem = rem + 1 == K ? 0 : rem + 1;
-    }
-    double acc = 0.0;
-    if (!REV) {
-#pragma unroll
-        for (int i = 0; i < FNO; ++i) { acc = ((hm >> i) & 1) ? v[i] : acc + v[i]; v[i] = acc; }
-    } else {
-#pragma unroll
-        for (int i = FNO - 1; i >= 0; --i) { acc = ((hm >> i) & 1) ? v[i] : v[i] + acc; v[i] = acc; }
-    }
-    double a = acc;
-    int f = hm != 0;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double ao = REV ? __shfl_down(a, d) : __shfl_up(a, d);
-        const int fo = REV ? __shfl_down(f, d) : __shfl_up(f, d);
-        const bool valid = REV ? (lane + d < 64) : (lane >= d);
-        if (valid) {
-            if (!f) a = ao + a;
-            f |= fo;
-        }
-    }
-    double ex = REV ? __shfl_down(a, 1) : __shfl_up(a, 1);
-    int exf = REV ? __shfl_down(f, 1) : __shfl_up(f, 1);
-    if (REV ? lane == 63 : lane == 0) { ex = 0.0; exf = 0; }
-    if (REV ? lane == 0 : lane == 63) { sh.wv[w] = a; sh.wf[w] = f; }
-    __syncthreads();
-    double c = 0.0;
-    if (!REV) {
-        for (int w2 = 0; w2 < w; ++w2) c = sh.wf[w2] ? sh.wv[w2] : c + sh.wv[w2];
-    } else {
-        for (int w2 = FNW - 1; w2 > w; --w2) c = sh.wf[w2] ? sh.wv[w2] : c + sh.wv[w2];
-    }
-    const double carry = exf ? ex : c + ex;
-    if (!REV) {
-        bool go = true;
-#pragma unroll
-        for (int i = 0; i < FNO; ++i) { go = go && !((hm >> i) & 1); if (go) v[i] += carry; }
-    } else {
-        bool go = true;
-#pragma unroll
-        for (int i = FNO - 1; i >= 0; --i) { go = go && !((hm >> i) & 1); if (go) v[i] += carry; }
-    }
-#pragma unroll
-    for (int i = 0; i < FNO; ++i)
-        if (c0 + i < n) out[PX(c0 + i)] = v[i];
-    __syncthreads();
-}
-
 // Both block scans of the same values in one pass (two barriers in all):
 // pre = segmented inclusive prefix with heads where (p + off) % K == 0, suf =
 // segmented inclusive suffix with tails where (p + off) % K == K-1 and at n-1
 // (the van Herk block prefixes and suffixes), written to the padded LDS
 // arrays pre[0..n) and suf[0..n).  Values past n must be 0.
-DEV void fscan2(const double* vin, double* pre, double* suf, int n, int K, int off, FShared& sh, int tid)
+DEV void fscan2(const double* vin, double* pre, double* suf, int n, int K, unsigned kmag, int off, FShared& sh,
+                int tid)
 {
     const int lane = tid & 63, w = tid >> 6;
     const int c0 = FNO * tid;
     double vf[FNO], vr[FNO];
     int hf = 0, hr = 0;
-    int rem = (c0 + off) % K;
+    int rem = c0 + off - div_mag(c0 + off, kmag) * K;
 #pragma unroll
     for (int i = 0; i < FNO; ++i) {
         const int p = c0 + i;
@@ -406,6 +346,7 @@ __global__ void __launch_bounds__(256) stl_mask_tables(DevPlan plan, const float
         T.core = core;
         T.K = core ? mi.chi - mi.clo + 1 : 1;
         T.off = core ? (T.K - mi.clo % T.K) % T.K : 0;
+        T.kmag = div_magic(T.K);
         T.kl0 = kl0;
         T.nWl = nWl;
         T.kr0 = kr0;
@@ -621,12 +562,13 @@ DEV void mask_trace(const DevPlan& P, const MaskTab& T, FOp& op, const float* z,
             band_acc(Bs, c0 + T.kr0 + shB, T.Wr, 0, min(T.nWr, max(0, round8(lim - T.kr0))), L + FTAIL + shB, zp, S);
     }
     if (T.core) {
-        __syncthreads();                              // band reads of the term copies are done
-        fscan2(e, A, Bs, L, T.K, T.off, sh, tid);      // block prefixes and suffixes of the terms
+        // block prefixes and suffixes of the terms (A and Bs are overwritten only
+        // after the scan's own barrier, when every band read is done)
+        fscan2(e, A, Bs, L, T.K, T.kmag, T.off, sh, tid);
         if (c0 < L) {
             const int K = T.K, s0 = c0 + T.clo;
-            const int qL = (L - 1 + T.off) / K;
-            int q = (s0 + T.off) / K, rem = (s0 + T.off) % K;
+            const int qL = div_mag(L - 1 + T.off, T.kmag);
+            int q = div_mag(s0 + T.off, T.kmag), rem = s0 + T.off - q * K;
             const double wc = (double)T.wc;
 #pragma unroll
             for (int i = 0; i < FNO; ++i) {
@@ -939,13 +881,17 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
     const int c0 = FNO * threadIdx.x;
     float z[N][FNO], tr[N][FNO];
     int R[N];
-    fused_exponents<N>(sh, x, L, D, c0, z);
-    fused_refs<N>(z, R, sh);
-    if (ka.saved_in && ka.saved_flag[b] == 1) {
-        // mask-node traces kept by the forward
+    // the loads of G and of the kept mask traces go out first, so that their
+    // latency overlaps the exponents of x
+    float G8[FNO];
+    load8f(ka.G + b * (int64_t)L, c0, L, G8);
+    if (ka.saved_in) {
 #pragma unroll
         for (int m = 0; m < N; ++m) load8f(ka.saved_in + ((int64_t)m * bt.B + b) * L, c0, L, tr[m]);
-    } else {
+    }
+    fused_exponents<N>(sh, x, L, D, c0, z);
+    fused_refs<N>(z, R, sh);
+    if (!(ka.saved_in && ka.saved_flag[b] == 1)) {
         // forward recompute of every mask trace (the n-ary adjoint needs all of them)
         mask_traces<N>(P, ka, z, R, L, Lc, A, Bs, tr, sh);
         if (sh.fragile) { fused_handoff(ka, b); return; }
@@ -954,8 +900,6 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
     // exponent O_t = sg beta log2(e) trace_m (in place of the trace)
     float gm[N][FNO];
     {
-        float G8[FNO];
-        load8f(ka.G + b * (int64_t)L, c0, L, G8);
 #pragma unroll
         for (int i = 0; i < FNO; ++i) {
             float v[N], wts[N];
@@ -1104,14 +1048,14 @@ __global__ void __launch_bounds__(FNT, fused_waves(N, FWAVES_BWD)) stl_fused_bwd
                 double hr[FNO];
 #pragma unroll
                 for (int i = 0; i < FNO; ++i) hr[i] = A[PX(c0 + i + hA)];
-                __syncthreads();                         // H reads done: A, Bs receive the block sums
-                fscan2(hr, A, Bs, L, T.K, 0, sh, tid);
+                // A and Bs receive the block sums after the scan's own barrier
+                fscan2(hr, A, Bs, L, T.K, T.kmag, 0, sh, tid);
                 const double wc = (double)T.wc;
                 const int K = T.K;
                 // window of j over t: [j - chi, j - clo]; j - clo <= L - 1 always, so
                 // only the start can be clipped (at t = 0, a block start)
                 const int stu = c0 - T.chi;
-                int rem = stu > 0 ? stu % K : 0;      // (max(0, j - chi)) % K
+                int rem = stu > 0 ? stu - div_mag(stu, T.kmag) * K : 0;      // (max(0, j - chi)) % K
 #pragma unroll
                 for (int i = 0; i < FNO; ++i) {
                     const int j = c0 + i;

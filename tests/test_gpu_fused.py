@@ -43,7 +43,7 @@ def test_fused_headline_formula(T):
     both_paths(spec, x, params, G, "cfg2 T=%d" % T)
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(7))
 def test_fused_shapes(case):
     rng = np.random.default_rng(40 + case)
     x = np.cumsum(rng.normal(size=(5, 900, 3)) * 0.05, axis=1).astype(np.float32)
@@ -60,6 +60,8 @@ def test_fused_shapes(case):
         {"op": "and", "smooth": True, "beta": 4.0, "children": [
             mask("always", p0, 880.0, 1200.0), mask("eventually", p1, "a", "b")]},   # support past the end
         mask("always", p2, 2000.0, 3000.0),                                          # empty support
+        {"op": "or", "smooth": True, "beta": 10.0, "children": [
+            mask("eventually", p0, 10.0, 44.5), mask("always", p1, 10.0, 45.0)]},     # cores of 1 and 2 steps
     ]
     params = {"a": 100.0, "b": 400.0}
     spec = specs[case]

@@ -173,6 +173,7 @@ MASKS = [
     (20.0, 24.0, 0.3, 1e-4),      # no core: everything is band
     (50.0, None, 2.0, 1e-6),      # unbounded mask
     (0.0, 30.0, 1.0, 1e-6),       # sigmoid tail clipped at offset 0
+    (10.0, 44.5, 1.0, 1e-6),      # core of a single step
 ]
 
 
