@@ -171,6 +171,42 @@ DEV double exp2d_neg(float d)
     return ldexp((double)ex2(d - fl), ip);      // d - fl in [0, 1)
 }
 
+// DPP lane moves (bound_ctrl: lanes with no source read 0): 0x101 + k row_shl,
+// 0x111 + k row_shr (within rows of 16), 0x130 wave_shl:1, 0x138 wave_shr:1
+template <int CTRL>
+DEV int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+
+template <int CTRL>
+DEV double dpp_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+DEV double readlane_d(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    return __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(b >> 32), l) << 32) |
+                                (unsigned)__builtin_amdgcn_readlane((int)b, l));
+}
+
+// one level of both segmented scans inside the rows: up from the lane SHR
+// below, down from the lane SHL above
+template <int SHR, int SHL>
+DEV void scan_row_step(double& a, int& f, double& r, int& g)
+{
+    const double ao = dpp_d<SHR>(a), ro = dpp_d<SHL>(r);
+    const int fo = dpp_i<SHR>(f), go = dpp_i<SHL>(g);
+    if (!f) a = ao + a;
+    f |= fo;
+    if (!g) r = r + ro;
+    g |= go;
+}
+
 // Both block scans of the same values in one pass (two barriers in all):
 // pre = segmented inclusive prefix with heads where (p + off) % K == 0, suf =
 // segmented inclusive suffix with tails where (p + off) % K == K-1 and at n-1
@@ -197,26 +233,46 @@ DEV void fscan2(const double* vin, double* pre, double* suf, int n, int K, unsig
     for (int i = 0; i < FNO; ++i) { af = ((hf >> i) & 1) ? vin[i] : af + vin[i]; vf[i] = af; }
 #pragma unroll
     for (int i = FNO - 1; i >= 0; --i) { ar = ((hr >> i) & 1) ? vin[i] : vin[i] + ar; vr[i] = ar; }
-    // wave-level segmented scans of the per-thread totals (forward: up; reverse: down)
+    // wave-level segmented scans of the per-thread totals (forward: up; reverse:
+    // down): DPP row shifts within each row of 16 lanes (lanes shifted in from
+    // outside the row read the identity (0, no head)), then the row totals
+    // (read with readlane) carried into the later (earlier) rows
     double a = af, r = ar;
     int f = hf != 0, g = hr != 0;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double ao = __shfl_up(a, d), ro = __shfl_down(r, d);
-        const int fo = __shfl_up(f, d), go = __shfl_down(g, d);
-        if (lane >= d) {
-            if (!f) a = ao + a;
-            f |= fo;
+    scan_row_step<0x111, 0x101>(a, f, r, g);
+    scan_row_step<0x112, 0x102>(a, f, r, g);
+    scan_row_step<0x114, 0x104>(a, f, r, g);
+    scan_row_step<0x118, 0x108>(a, f, r, g);
+    {
+        const int row = lane >> 4;
+        // up: carries C1 = T0, C2 = C1 (+) T1, C3 = C2 (+) T2 (T_q = row q's total, at lane 16q + 15)
+        const double t0 = readlane_d(a, 15), t1 = readlane_d(a, 31), t2 = readlane_d(a, 47);
+        const int u0 = __builtin_amdgcn_readlane(f, 15), u1 = __builtin_amdgcn_readlane(f, 31),
+                  u2 = __builtin_amdgcn_readlane(f, 47);
+        const double c2 = u1 ? t1 : t0 + t1, c3 = u2 ? t2 : c2 + t2;
+        const int h2 = u0 | u1, h3 = h2 | u2;
+        const double cu = row == 1 ? t0 : (row == 2 ? c2 : c3);
+        const int hu = row == 1 ? u0 : (row == 2 ? h2 : h3);
+        if (row > 0) {
+            if (!f) a = cu + a;
+            f |= hu;
         }
-        if (lane + d < 64) {
-            if (!g) r = ro + r;
-            g |= go;
+        // down: carries D2 = T3, D1 = T2 (+) D2, D0 = T1 (+) D1 (T_q at lane 16q)
+        const double s1 = readlane_d(r, 16), s2 = readlane_d(r, 32), s3 = readlane_d(r, 48);
+        const int v1 = __builtin_amdgcn_readlane(g, 16), v2 = __builtin_amdgcn_readlane(g, 32),
+                  v3 = __builtin_amdgcn_readlane(g, 48);
+        const double d1 = v2 ? s2 : s2 + s3, d0 = v1 ? s1 : s1 + d1;
+        const int k1 = v2 | v3, k0 = v1 | k1;
+        const double cd = row == 2 ? s3 : (row == 1 ? d1 : d0);
+        const int hd = row == 2 ? v3 : (row == 1 ? k1 : k0);
+        if (row < 3) {
+            if (!g) r = r + cd;
+            g |= hd;
         }
     }
-    double exf = __shfl_up(a, 1), exr = __shfl_down(r, 1);
-    int eff = __shfl_up(f, 1), efr = __shfl_down(g, 1);
-    if (lane == 0) { exf = 0.0; eff = 0; }
-    if (lane == 63) { exr = 0.0; efr = 0; }
+    // the previous lane's inclusive value (up) and the next lane's (down)
+    const double exf = dpp_d<0x138>(a), exr = dpp_d<0x130>(r);
+    const int eff = dpp_i<0x138>(f), efr = dpp_i<0x130>(g);
     if (lane == 63) { sh.wv[w] = a; sh.wf[w] = f; }
     if (lane == 0) { sh.wv2[w] = r; sh.wf2[w] = g; }
     __syncthreads();
