@@ -150,6 +150,20 @@ def test_smooth_until(ab):
     check_formula(spec, x, what="until%s" % (ab,))
 
 
+def test_smooth_until_sparse_gradient():
+    """Upstream gradients that are zero at most timesteps: lanes of one wave
+    that skip their output still take part in the adjoint's lane-shifted sums."""
+    rng = np.random.default_rng(7)
+    x = walk(rng, 2, 700, D=2, s=0.1)
+    G = rng.normal(size=(2, 700)).astype(np.float32)
+    G[rng.random(G.shape) < 0.8] = 0.0
+    G[1, 300:] = 0.0
+    for ab in [(5, 90), (0, None)]:
+        spec = {"op": "until", "a": ab[0], "b": ab[1], "smooth": True, "beta": 10.0,
+                "left": {"op": "linear", "w": [1, 0], "c": -0.5}, "right": {"op": "linear", "w": [0, 1], "c": 0.1}}
+        check_formula(spec, x, G=G, what="sparse-G until%s" % (ab,))
+
+
 def test_smooth_until_wide_range():
     """Traces whose exponent range (beta log2(e) (max - min)) is far beyond the
     fp64 form's limit take the scaled-pair path; a TRUE left child does too."""
