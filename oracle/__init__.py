@@ -321,3 +321,31 @@ def mask_weights(a, b, c, eps, L):
 
 def node_count(spec, D, params=None):
     return len(Compiled(spec, params, D).nodes)
+
+
+def interval_sweep(x, a, b, w, c=0.0, op="always", smooth=True, beta=10.0, mask_c=1.0, mask_eps=1e-6,
+                   rho_pad=RHO_PAD):
+    """Robustness at t = 0 of op_{mask(a_n, b_n)}(w . x - c) for every
+    trajectory of x [B, T, D] and every interval n, with d/da_n and d/db_n
+    (Sec. VI: the masked form evaluated for many time-interval values).
+
+    Plain composition of the pinned single-formula oracle: one forward and one
+    backward (upstream gradient 1 at t = 0) per trajectory and interval.
+    Returns (rho, drho_da, drho_db), each [B, N] float64."""
+    x = np.asarray(x, dtype=np.float32)
+    B, T, D = x.shape
+    N = len(a)
+    rho, ga, gb = np.zeros((B, N)), np.zeros((B, N)), np.zeros((B, N))
+    spec = {"op": op, "smooth": bool(smooth), "beta": float(beta),
+            "child": {"op": "linear", "w": [float(v) for v in w], "c": float(c)},
+            "mask": {"a": "a", "b": "b", "c": float(mask_c), "eps": float(mask_eps)}}
+    G = np.zeros((1, T), dtype=np.float32)
+    G[0, 0] = 1.0
+    for n in range(N):
+        params = {"a": float(a[n]), "b": float(b[n])}
+        r = forward(spec, x, params=params, rho_pad=rho_pad)
+        rho[:, n] = r[:, 0]
+        for k in range(B):
+            _, dp = backward(spec, x[k:k + 1], G, params=params, rho_pad=rho_pad)
+            ga[k, n], gb[k, n] = dp.get("a", 0.0), dp.get("b", 0.0)
+    return rho, ga, gb

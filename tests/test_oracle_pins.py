@@ -435,3 +435,44 @@ def test_fd_mask_bounds_gradients(orc):
     spec2 = {"op": "eventually", "smooth": True, "beta": 4.0, "mask": {"a": "a", "b": None, "c": 2.0,
              "eps": 1e-6}, "child": {"op": "linear", "w": [1, 0], "c": 0}}
     _fd_check(orc, spec2, x, G, params={"a": 7.4}, names=("a",))
+
+
+def test_interval_sweep_pins(orc):
+    """Interval sweep (Sec. VI, many (a, b) values at once): hard sweep over
+    half-integer bounds with a steep mask equals the plain min / max over
+    [k, m]; the smooth value lies in the logsumexp bounds of that window; its
+    a, b derivatives agree with central differences of the sweep itself."""
+    rng = np.random.default_rng(31)
+    x = np.cumsum(rng.normal(size=(2, 40, 1)) * 0.3, axis=1).astype(np.float32)
+    ks = np.array([0, 3, 10, 25, 39, 12])
+    ms = np.array([0, 9, 10, 39, 39, 30])
+    a = (ks - 0.5).astype(np.float64)
+    b = (ms + 0.5).astype(np.float64)
+    u = x[:, :, 0].astype(np.float64)
+    for op, red in (("always", np.min), ("eventually", np.max)):
+        rho, ga, gb = orc.interval_sweep(x, a, b, [1.0], op=op, smooth=False, mask_c=50.0)
+        for n in range(len(a)):
+            assert np.array_equal(rho[:, n], red(u[:, ks[n]:ms[n] + 1], axis=1)), (op, n)
+        assert not ga.any() and not gb.any()
+        # weights inside the window are 1 - eps - O(e^-25): the weighted logsumexp
+        # can pass the hard value by at most -log(w)/beta
+        beta = 40.0
+        rs, _, _ = orc.interval_sweep(x, a, b, [1.0], op=op, smooth=True, beta=beta, mask_c=50.0)
+        slack = -np.log(1.0 - 1e-6 - 1e-10) / beta + 1e-12
+        for n in range(len(a)):
+            hard = red(u[:, ks[n]:ms[n] + 1], axis=1)
+            width = np.log(ms[n] - ks[n] + 1) / beta + slack
+            if op == "always":
+                assert np.all(rs[:, n] <= hard + slack) and np.all(rs[:, n] >= hard - width)
+            else:
+                assert np.all(rs[:, n] >= hard - slack) and np.all(rs[:, n] <= hard + width)
+    # derivatives against central differences (smooth mask, moderate steepness)
+    a2, b2 = np.array([4.3, 11.7]), np.array([20.2, 33.9])
+    rho, ga, gb = orc.interval_sweep(x, a2, b2, [1.0], op="always", beta=5.0, mask_c=1.5)
+    h = 1e-4
+    rp, _, _ = orc.interval_sweep(x, a2 + h, b2, [1.0], op="always", beta=5.0, mask_c=1.5)
+    rm, _, _ = orc.interval_sweep(x, a2 - h, b2, [1.0], op="always", beta=5.0, mask_c=1.5)
+    assert np.allclose(ga, (rp - rm) / (2 * h), rtol=1e-5, atol=1e-8)
+    rp, _, _ = orc.interval_sweep(x, a2, b2 + h, [1.0], op="always", beta=5.0, mask_c=1.5)
+    rm, _, _ = orc.interval_sweep(x, a2, b2 - h, [1.0], op="always", beta=5.0, mask_c=1.5)
+    assert np.allclose(gb, (rp - rm) / (2 * h), rtol=1e-5, atol=1e-8)
