@@ -264,6 +264,52 @@ stl_status stl_graph_capture(const stl_plan* plan, const stl_batch* batch, const
 stl_status stl_graph_launch(stl_graph* graph, void* stream);
 stl_status stl_graph_destroy(stl_graph* graph);
 
+/*
+ * Interval-vectorised evaluation (Sec. VI, after eq. (smooth mask): with the
+ * masking form, the robustness of one formula for many time-interval
+ * values is a batch of independent masked reductions).  For every
+ * trajectory b and every interval n it computes the robustness at t = 0 of
+ *
+ *     op_{mask(a_n, b_n)} (w . x_t - c)        op = STL_ALWAYS or STL_EVENTUALLY
+ *
+ * where the smooth mask weights offset k by
+ * w_k = max(sig(c_mask (k - a_n)) - sig(c_mask (k - b_n)) - eps, 0) (a_n, b_n
+ * in timesteps: a_n = a_frac * T for the paper's fractional form).  Smooth:
+ * rho = smax_w / smin_w of the trace with weights inside the logsumexp
+ * (beta = 1/temperature); hard: max / min over the support {k : w_k > 0}.
+ * An interval whose support misses [0, T) yields -rho_pad (Eventually) or
+ * +rho_pad (Always).
+ *
+ * Arguments (device pointers unless noted, all caller-owned):
+ *   desc       host struct below; w[0..D) are read from it
+ *   d_x        [B][T][D] float32, D innermost
+ *   d_a, d_b   [N] float32 interval bounds in timesteps (b > a not required)
+ *   d_rho      [B][N] float32 output
+ *   d_grad_a, d_grad_b   [B][N] float32 d rho / d a_n, d rho / d b_n, or NULL
+ *              (both or neither; zero for the hard variant)
+ *   stream     hipStream_t; the call launches one kernel on it and allocates
+ *              nothing, so it can be captured in a HIP graph.
+ * Limits: 1 <= T <= 4096, 1 <= D <= 16, B, N >= 0, mask_c > 0, mask_eps >= 0,
+ * beta > 0 when smooth; otherwise STL_E_ARG / STL_E_SHAPE.  The smooth sums
+ * use FP64 terms against the trajectory's largest exponent, and an interval
+ * whose support terms all underflow against it is summed again against its
+ * own largest exponent.
+ */
+typedef struct {
+    int32_t op;              /* STL_ALWAYS or STL_EVENTUALLY */
+    int32_t smooth;          /* 0 hard, 1 logsumexp */
+    float beta;              /* smooth only */
+    float mask_c, mask_eps;  /* sigmoid steepness (> 0) and tolerance (>= 0) */
+    int32_t D;
+    float w[16];             /* predicate w . x - c */
+    float c;
+    float rho_pad;           /* empty-support value magnitude (e.g. 1e6) */
+} stl_interval_desc;
+
+stl_status stl_interval_sweep(const stl_interval_desc* desc, const float* d_x, int64_t B, int64_t T,
+                              const float* d_a, const float* d_b, int64_t N, float* d_rho, float* d_grad_a,
+                              float* d_grad_b, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,6 +32,10 @@ hipError_t launch_fused(bool bwd, const DevPlan& plan, const struct Batch& bt, c
                         hipStream_t s);
 hipError_t set_max_lds_fused(size_t bytes);
 size_t mask_tab_bytes();
+int interval_max_T();
+hipError_t launch_interval_sweep(int op_sg, int smooth, float beta, float mc, float meps, int D, const float* w,
+                                 float c, float rho_pad, const float* x, int64_t B, int T, const float* a,
+                                 const float* b, int64_t N, float* rho, float* ga, float* gb, hipStream_t s);
 
 }  // namespace stlmi
 
@@ -969,5 +973,30 @@ extern "C" stl_status stl_graph_destroy(stl_graph* graph)
     if (graph->exec) hipGraphExecDestroy(graph->exec);
     if (graph->graph) hipGraphDestroy(graph->graph);
     delete graph;
+    return STL_OK;
+}
+
+// ------------------------------------------------------------------ interval sweep
+
+extern "C" stl_status stl_interval_sweep(const stl_interval_desc* desc, const float* d_x, int64_t B, int64_t T,
+                                         const float* d_a, const float* d_b, int64_t N, float* d_rho,
+                                         float* d_grad_a, float* d_grad_b, void* stream)
+{
+    if (!desc) return fail(STL_E_ARG, "desc is NULL");
+    if (desc->op != STL_ALWAYS && desc->op != STL_EVENTUALLY)
+        return fail(STL_E_ARG, "op must be STL_ALWAYS or STL_EVENTUALLY");
+    if (desc->D < 1 || desc->D > 16) return fail(STL_E_ARG, "D must be in [1, 16]");
+    if (!(desc->mask_c > 0.f)) return fail(STL_E_ARG, "mask_c must be > 0");
+    if (!(desc->mask_eps >= 0.f)) return fail(STL_E_ARG, "mask_eps must be >= 0");
+    if (desc->smooth && !(desc->beta > 0.f)) return fail(STL_E_ARG, "beta must be > 0");
+    if (B < 0 || N < 0) return fail(STL_E_SHAPE, "B and N must be >= 0");
+    if (T < 1 || T > interval_max_T()) return fail(STL_E_SHAPE, "T must be in [1, %d]", interval_max_T());
+    if ((d_grad_a == nullptr) != (d_grad_b == nullptr)) return fail(STL_E_ARG, "pass both gradients or neither");
+    if (B == 0 || N == 0) return STL_OK;
+    if (!d_x || !d_a || !d_b || !d_rho) return fail(STL_E_ARG, "null device pointer");
+    hipError_t e = launch_interval_sweep(desc->op == STL_EVENTUALLY ? 1 : -1, desc->smooth ? 1 : 0, desc->beta,
+                                         desc->mask_c, desc->mask_eps, desc->D, desc->w, desc->c, desc->rho_pad, d_x,
+                                         B, (int)T, d_a, d_b, N, d_rho, d_grad_a, d_grad_b, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     return STL_OK;
 }

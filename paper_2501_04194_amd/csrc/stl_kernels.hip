@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <math.h>
+#include <algorithm>
 #include "stl_plan.h"
 
 namespace stlmi {
@@ -554,19 +555,26 @@ DEV float mask_wk(const MaskP& m, int k, float* dwa = nullptr, float* dwb = null
 {
     const float x1 = m.c * ((float)k - m.a);
     const float s1 = 1.f / (1.f + expf(-x1));
-    float wk, s2 = 0.f;
+    float wk;
     if (m.unb) {
         wk = s1 - m.eps;
     } else {
         const float y1 = m.c * ((float)k - m.b);
-        s2 = 1.f / (1.f + expf(-y1));
         const float sny = 1.f / (1.f + expf(y1));
         wk = s1 * sny * m.band - m.eps;
     }
     wk = wk > 0.f ? wk : 0.f;
     if (dwa) {
-        *dwa = wk > 0.f ? -m.c * s1 * (1.f - s1) : 0.f;
-        *dwb = (wk > 0.f && !m.unb) ? m.c * s2 * (1.f - s2) : 0.f;
+        // sig'(x) = e^{-|x|} / (1 + e^{-|x|})^2: accurate in both tails (the
+        // form s (1 - s) loses all digits where s rounds to 1)
+        const float t1 = expf(-fabsf(x1));
+        *dwa = wk > 0.f ? -m.c * (t1 / ((1.f + t1) * (1.f + t1))) : 0.f;
+        if (wk > 0.f && !m.unb) {
+            const float t2 = expf(-fabsf(m.c * ((float)k - m.b)));
+            *dwb = m.c * (t2 / ((1.f + t2) * (1.f + t2)));
+        } else {
+            *dwb = 0.f;
+        }
     }
     return wk;
 }
@@ -1416,6 +1424,7 @@ __global__ void stl_fill_int(int* p, int64_t n, int v)
 }  // namespace stlmi
 
 #include "stl_fused.h"
+#include "stl_interval.h"
 
 namespace stlmi {
 

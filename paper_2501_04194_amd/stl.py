@@ -51,9 +51,17 @@ class Launch(ctypes.Structure):
 
 
 _lib = None
+class IntervalDesc(ctypes.Structure):
+    """stl_interval_desc"""
+    _fields_ = [("op", ctypes.c_int32), ("smooth", ctypes.c_int32), ("beta", ctypes.c_float),
+                ("mask_c", ctypes.c_float), ("mask_eps", ctypes.c_float), ("D", ctypes.c_int32),
+                ("w", ctypes.c_float * 16), ("c", ctypes.c_float), ("rho_pad", ctypes.c_float)]
+
+
 EXPORTS = ["stl_compile", "stl_plan_destroy", "stl_plan_info", "stl_workspace_size", "stl_forward",
            "stl_backward", "stl_saved_size", "stl_forward_saving", "stl_backward_saved", "stl_last_error",
-           "stl_lpt_order", "stl_autotune", "stl_graph_capture", "stl_graph_launch", "stl_graph_destroy"]
+           "stl_lpt_order", "stl_autotune", "stl_graph_capture", "stl_graph_launch", "stl_graph_destroy",
+           "stl_interval_sweep"]
 
 
 def lib():
@@ -85,6 +93,7 @@ def lib():
                                     vp, ctypes.POINTER(vp)]
     L.stl_graph_launch.argtypes = [vp, vp]
     L.stl_graph_destroy.argtypes = [vp]
+    L.stl_interval_sweep.argtypes = [ctypes.POINTER(IntervalDesc), vp, i64, i64, vp, vp, i64, vp, vp, vp, vp]
     for f in EXPORTS:
         if f != "stl_last_error":
             getattr(L, f).restype = ctypes.c_int
@@ -339,6 +348,38 @@ def _require_gpu(torch, x):
         raise StlError("stlmi runs on the GPU only: move the tensors to a HIP device")
     if x.dtype != torch.float32:
         raise StlError("x must be float32")
+
+
+def interval_sweep(x, a, b, w, c=0.0, op="always", smooth=True, beta=10.0, mask_c=1.0, mask_eps=1e-6,
+                   rho_pad=1e6, grads=True):
+    """Robustness at t = 0 of op_{mask(a_n, b_n)}(w . x - c) for every trajectory of
+    x [B, T, D] and every interval n (``stl_interval_sweep``): returns rho [B, N]
+    and, with ``grads``, d rho / d a and d rho / d b [B, N] (a, b in timesteps)."""
+    import torch
+    _require_gpu(torch, x)
+    x = x.contiguous()
+    a = a.contiguous()
+    b = b.contiguous()
+    if a.dtype != torch.float32 or b.dtype != torch.float32 or a.shape != b.shape or a.dim() != 1:
+        raise ValueError("a and b must be float32 vectors of one length")
+    B, T, D = x.shape
+    if len(w) != D:
+        raise ValueError("predicate width must equal D")
+    d = IntervalDesc()
+    d.op = STL_ALWAYS if op == "always" else STL_EVENTUALLY
+    d.smooth = 1 if smooth else 0
+    d.beta, d.mask_c, d.mask_eps = float(beta), float(mask_c), float(mask_eps)
+    d.D = D
+    for k, v in enumerate(w):
+        d.w[k] = float(v)
+    d.c, d.rho_pad = float(c), float(rho_pad)
+    N = a.shape[0]
+    rho = torch.empty((B, N), dtype=torch.float32, device=x.device)
+    ga = torch.empty_like(rho) if grads else None
+    gb = torch.empty_like(rho) if grads else None
+    _check(lib().stl_interval_sweep(ctypes.byref(d), _ptr(x), B, T, _ptr(a), _ptr(b), N, _ptr(rho), _ptr(ga),
+                                    _ptr(gb), _stream(torch, x.device)))
+    return (rho, ga, gb) if grads else rho
 
 
 def lpt_order(offsets_host):

@@ -1,0 +1,93 @@
+"""GPU parity of the interval sweep (``stl_interval_sweep``: the robustness at
+t = 0 of one masked Always / Eventually for many (a, b) values, Sec. VI)
+against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_close
+from paper_2501_04194_amd import stl
+
+pytestmark = pytest.mark.gpu
+
+RHO_PAD = 1e6
+
+
+def walk(rng, B, T, D=1, s=0.3):
+    return np.cumsum(rng.normal(size=(B, T, D)) * s, axis=1).astype(np.float32)
+
+
+def run(x, a, b, w, **kw):
+    xd = torch.from_numpy(x).cuda()
+    ad = torch.from_numpy(np.asarray(a, dtype=np.float32)).cuda()
+    bd = torch.from_numpy(np.asarray(b, dtype=np.float32)).cuda()
+    rho, ga, gb = stl.interval_sweep(xd, ad, bd, w, **kw)
+    return rho.cpu().numpy(), ga.cpu().numpy(), gb.cpu().numpy()
+
+
+def intervals(rng, N, T):
+    a = rng.uniform(-8.0, T + 4.0, size=N).astype(np.float32)
+    b = (a + rng.uniform(-2.0, T, size=N)).astype(np.float32)
+    return a, b
+
+
+@pytest.mark.parametrize("T", [20, 100, 333])
+@pytest.mark.parametrize("op", ["always", "eventually"])
+def test_interval_sweep_smooth(T, op):
+    rng = np.random.default_rng(T)
+    x = walk(rng, 3, T, D=2)
+    a, b = intervals(rng, 300 if T == 20 else 90, T)
+    kw = dict(c=0.1, op=op, smooth=True, beta=10.0, mask_c=1.5, mask_eps=1e-6)
+    rho, ga, gb = run(x, a, b, [1.0, -0.5], **kw)
+    r0, ga0, gb0 = oracle.interval_sweep(x, a.astype(np.float64), b.astype(np.float64), [1.0, -0.5], **kw)
+    assert_close(rho, r0, what="sweep rho %s T=%d" % (op, T))
+    # d/da, d/db: |d rho/da| <= c/(4 beta) * (sum of |dw| E)/S; compare against that scale
+    sc = 1.5 / (4 * 10.0)
+    assert_close(ga, ga0, scale=sc, what="sweep d/da")
+    assert_close(gb, gb0, scale=sc, what="sweep d/db")
+
+
+@pytest.mark.parametrize("op", ["always", "eventually"])
+def test_interval_sweep_hard_bitexact(op):
+    rng = np.random.default_rng(4)
+    x = walk(rng, 2, 64)
+    # half-integer bounds and a steep mask: the support is an integer window
+    k = rng.integers(-3, 70, size=200)
+    m = k + rng.integers(-2, 40, size=200)
+    a, b = (k - 0.5).astype(np.float32), (m + 0.5).astype(np.float32)
+    kw = dict(op=op, smooth=False, mask_c=50.0, mask_eps=1e-6)
+    rho, ga, gb = run(x, a, b, [1.0], **kw)
+    r0, _, _ = oracle.interval_sweep(x, a.astype(np.float64), b.astype(np.float64), [1.0], **kw)
+    assert np.array_equal(rho.astype(np.float32), r0.astype(np.float32))
+    assert not ga.any() and not gb.any()
+
+
+def test_interval_sweep_edges():
+    rng = np.random.default_rng(5)
+    x = walk(rng, 2, 1)
+    # T = 1, intervals covering, missing and reversed
+    a = np.array([-1.0, 0.0, 12.0, 3.0], dtype=np.float32)
+    b = np.array([2.0, 0.5, 16.0, -3.0], dtype=np.float32)
+    kw = dict(op="eventually", smooth=True, beta=10.0, mask_c=2.0, mask_eps=1e-6)
+    rho, _, _ = run(x, a, b, [1.0], **kw)
+    r0, _, _ = oracle.interval_sweep(x, a.astype(np.float64), b.astype(np.float64), [1.0], **kw)
+    assert_close(rho, r0, what="T=1 sweep")
+    assert rho[0, 2] == -RHO_PAD and rho[0, 3] == -RHO_PAD
+    # N not a multiple of the work-group size, eps = 0 (every offset in the support)
+    x = walk(rng, 2, 50)
+    a, b = intervals(rng, 257, 50)
+    kw = dict(op="always", smooth=True, beta=3.0, mask_c=0.7, mask_eps=0.0)
+    rho, ga, gb = run(x, a, b, [1.0], **kw)
+    r0, ga0, gb0 = oracle.interval_sweep(x, a.astype(np.float64), b.astype(np.float64), [1.0], **kw)
+    assert_close(rho, r0, what="eps=0 sweep")
+    assert_close(ga, ga0, scale=0.7 / 12, what="eps=0 d/da")
+    # empty batch / no intervals, and argument errors
+    xd = torch.from_numpy(x).cuda()
+    e = torch.zeros(0, dtype=torch.float32, device="cuda")
+    assert stl.interval_sweep(xd, e, e, [1.0])[0].shape == (2, 0)
+    one = torch.ones(3, dtype=torch.float32, device="cuda")
+    with pytest.raises(stl.StlError, match="mask_c"):
+        stl.interval_sweep(xd, one, one, [1.0], mask_c=0.0)
+    with pytest.raises(stl.StlError, match="T must be"):
+        stl.interval_sweep(torch.zeros((1, 5000, 1), device="cuda"), one, one, [1.0])
