@@ -151,6 +151,72 @@ def bench_graph(args):
     print(json.dumps(out), flush=True)
 
 
+FP32_PEAK_TFLOPS = 157.3
+OPS_PER_TERM = 30    # one weighted term of the interval sweep: the mask weight (two sigmoids: 2 exp,
+                     # 2 reciprocals, ~8 mul/add), its a and b derivatives (2 exp, 2 reciprocals, ~8),
+                     # three FP64 fused multiply-adds (6), transcendental and reciprocal counted as 1
+
+
+def bench_intervals(args):
+    """Interval sweep: robustness at t = 0 of Always~_[aT, bT](s > 0) for a
+    300 x 300 grid of (a, b) fractions (90,000 intervals) on random-walk
+    signals of T = 20 steps, with d/da and d/db (the paper's vectorised
+    time-interval evaluation, Sec. VI); --interval-batch signals at once."""
+    import torch
+    from paper_2501_04194_amd import stl
+    T, B = 20, max(1, args.interval_batch)
+    g = np.linspace(0.0, 1.0, 300)
+    af, bf = np.meshgrid(g, g, indexing="ij")
+    a = (af.ravel() * T).astype(np.float32)
+    b = (bf.ravel() * T).astype(np.float32)
+    N = a.size
+    rng = np.random.default_rng(6)
+    x = np.cumsum(rng.normal(size=(B, T, 1)) * 0.3, axis=1).astype(np.float32)
+    kw = dict(op="always", smooth=True, beta=10.0, mask_c=1.0, mask_eps=1e-6)
+    dev = torch.device("cuda:0")
+    xd, ad, bd = (torch.from_numpy(v).to(dev) for v in (x, a, b))
+    for _ in range(args.warmup):
+        stl.interval_sweep(xd, ad, bd, [1.0], **kw)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_rep = max(args.steps, 20)
+    e0.record(stream)
+    for _ in range(n_rep):
+        stl.interval_sweep(xd, ad, bd, [1.0], **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n_rep
+    # weighted terms: offsets with a positive weight, per interval and signal
+    j = np.arange(T, dtype=np.float64)[None, :]
+    sig = lambda z: 1.0 / (1.0 + np.exp(-z))
+    w = sig(kw["mask_c"] * (j - a[:, None])) - sig(kw["mask_c"] * (j - b[:, None])) - kw["mask_eps"]
+    terms = int((w > 0).sum()) * B
+    achieved = OPS_PER_TERM * terms / (ms * 1e-3) / 1e12
+    out = {"metric": "interval evaluations/s (Always~[aT,bT](s>0), T=20, 90,000 (a,b) values, with d/da, d/db)",
+           "value": B * N / (ms * 1e-3), "unit": "intervals/s", "n_gpus": 1, "steps": n_rep, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "interval_sweep_T20_N90000", "signals": B, "T": T, "intervals": N,
+                      "grid": "300 x 300 (a, b) fractions, a = a_frac T", "beta": 10.0, "mask_c": 1.0,
+                      "mask_eps": 1e-6},
+           "roofline": {"bound": "alu", "kernel": "stl_interval_kernel", "achieved": achieved,
+                        "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                        "traffic": None, "terms": terms}}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        n = 24000                   # about ten seconds of CPU work
+        idx = np.random.default_rng(7).choice(N, n, replace=False)
+        t0 = time.perf_counter()
+        oracle.interval_sweep(x[:1], a[idx].astype(np.float64), b[idx].astype(np.float64), [1.0], **kw)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n / dt, "unit": "intervals/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d random intervals of the grid on the first signal, FP64 oracle "
+                                         "(one forward and one backward per interval), %.2f s" % (n, dt)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,8 +228,9 @@ def main():
     ap.add_argument("--recompute", action="store_true", help="backward recomputes the node traces")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer three times (the reference kernel for HBM counters)")
-    ap.add_argument("--workload", default="smooth_mask", choices=["smooth_mask", "smooth_until", "ragged"],
+    ap.add_argument("--workload", default="smooth_mask", choices=["smooth_mask", "smooth_until", "ragged", "intervals"],
                     help="smooth_mask: the headline workload; the others are secondary measurements")
+    ap.add_argument("--interval-batch", type=int, default=1, help="signals per interval sweep (--workload intervals)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (trajectories shard with no "
@@ -177,6 +244,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "intervals":
+        return bench_intervals(args)
     if args.workload != "smooth_mask":
         return bench_graph(args)
 

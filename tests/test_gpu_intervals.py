@@ -63,6 +63,20 @@ def test_interval_sweep_hard_bitexact(op):
     assert not ga.any() and not gb.any()
 
 
+def test_interval_sweep_trajectory_groups():
+    """Batches that span several work-group trajectory groups, with a group
+    size cut by the LDS capacity (T = 700: five trajectories per group)."""
+    rng = np.random.default_rng(8)
+    x = walk(rng, 11, 700, s=0.1)
+    a, b = intervals(rng, 40, 700)
+    kw = dict(op="eventually", smooth=True, beta=10.0, mask_c=0.5, mask_eps=1e-6)
+    rho, ga, gb = run(x, a, b, [1.0], **kw)
+    r0, ga0, gb0 = oracle.interval_sweep(x, a.astype(np.float64), b.astype(np.float64), [1.0], **kw)
+    assert_close(rho, r0, what="grouped sweep rho")
+    assert_close(ga, ga0, scale=0.5 / 40, what="grouped sweep d/da")
+    assert_close(gb, gb0, scale=0.5 / 40, what="grouped sweep d/db")
+
+
 def test_interval_sweep_edges():
     rng = np.random.default_rng(5)
     x = walk(rng, 2, 1)
