@@ -217,6 +217,64 @@ def bench_intervals(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_table2(args):
+    """Table II suite: phi_1 .. phi_6 (smooth, beta = 10) on B = 8 random-walk
+    signals for T = 64 .. 2048 (the paper's batch size; it stops at T = 512):
+    forward and forward + backward times, eager launches."""
+    import torch
+    from paper_2501_04194_amd import stl, workloads as W
+    dev = torch.device("cuda:0")
+    forms = W.table2_formulas(smooth=True)
+    B, Ts = 8, [64, 128, 256, 512, 1024, 2048]
+    stream = torch.cuda.current_stream(dev)
+    n_rep = max(args.steps, 20)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n_rep):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n_rep
+
+    sweep = {}
+    for name, spec in forms.items():
+        plan = stl.Plan(spec, 2)
+        pv = torch.from_numpy(plan.param_vector()).to(dev)
+        sweep[name] = {}
+        for T in Ts:
+            x = torch.from_numpy(W.random_walks(60 + T, B, T, 2, 0.1)).to(dev)
+            G = torch.from_numpy(W.upstream_grad(61 + T, (B, T))).to(dev)
+            f = timed(lambda: plan.forward(x, pv))
+            fb = timed(lambda: (plan.forward(x, pv), plan.backward(x, G, pv)))
+            sweep[name][T] = {"fwd_ms": round(f, 4), "fwd_bwd_ms": round(fb, 4)}
+    rates = sorted(B * 512 / (sweep[n][512]["fwd_bwd_ms"] * 1e-3) for n in forms)
+    out = {"metric": "fwd+bwd signal-steps/s, median over the Table II formulas (B=8, T=512)",
+           "value": rates[len(rates) // 2], "unit": "signal-steps/s", "n_gpus": 1, "steps": n_rep, "warmup": 3,
+           "ms_per_step": float(np.median([sweep[n][512]["fwd_bwd_ms"] for n in forms])),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "table2_suite_B8", "B": B, "T": Ts, "beta": 10.0,
+                      "interval": list(W.TABLE2_INTERVAL)},
+           "sweep": sweep}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        t0 = time.perf_counter()
+        for name, spec in forms.items():
+            x = W.random_walks(60 + 512, B, 512, 2, 0.1)
+            G = W.upstream_grad(61 + 512, (B, 512))
+            oracle.forward(spec, x)
+            oracle.backward(spec, x, G)
+        dt = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": 6 * B * 512 / dt, "unit": "signal-steps/s", "cores": cores, "kind": "oracle",
+                               "sample": "the six formulas at B=8, T=512, forward + backward, FP64 C oracle, %.2f s" % dt}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,7 +286,7 @@ def main():
     ap.add_argument("--recompute", action="store_true", help="backward recomputes the node traces")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer three times (the reference kernel for HBM counters)")
-    ap.add_argument("--workload", default="smooth_mask", choices=["smooth_mask", "smooth_until", "ragged", "intervals"],
+    ap.add_argument("--workload", default="smooth_mask", choices=["smooth_mask", "smooth_until", "ragged", "intervals", "table2"],
                     help="smooth_mask: the headline workload; the others are secondary measurements")
     ap.add_argument("--interval-batch", type=int, default=1, help="signals per interval sweep (--workload intervals)")
     args = ap.parse_args()
@@ -246,6 +304,8 @@ def main():
         del src, dst
     if args.workload == "intervals":
         return bench_intervals(args)
+    if args.workload == "table2":
+        return bench_table2(args)
     if args.workload != "smooth_mask":
         return bench_graph(args)
 

@@ -85,7 +85,7 @@ typedef enum {
 #define STL_MAX_CHILDREN 8
 #define STL_MAX_D 16
 #define STL_MAX_NODES 48
-#define STL_MAX_PREDS 16
+#define STL_MAX_PREDS 32
 
 /* One formula node.  Children are child_idx[child_off .. child_off+n_child). */
 typedef struct {

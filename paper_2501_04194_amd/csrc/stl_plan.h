@@ -36,7 +36,7 @@ enum Flag : int8_t {
 constexpr int MAX_INSTR = 48;
 constexpr int MAX_COEF = 160;
 constexpr int MAX_NCH = 4;
-constexpr int MAX_PRED = 16;
+constexpr int MAX_PRED = 32;
 constexpr int MAX_MASKS = 16;
 constexpr int MAX_D = 16;
 

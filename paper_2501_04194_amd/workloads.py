@@ -161,3 +161,57 @@ def ragged_workload(n: int | None = None, seed: int | None = None):
     x, off = ragged_walks(c["seed"] if seed is None else seed, c["N"] if n is None else n,
                           c["lmin"], c["lmax"], c["D"], c["sigma"])
     return cfg1_formula(c["D"]), {}, x, off
+
+
+# ---------------------------------------------------------------------------
+# the formula suite of Table II (computational-properties study)
+# ---------------------------------------------------------------------------
+
+TABLE2_INTERVAL = (2, 20)      # the table leaves I open: a fixed bounded window
+
+
+def _region(k: int):
+    """phi_k and psi_k of region k on a 2-D state: x0 > c_k and x1 < d_k (linear
+    predicates at distinct, fixed thresholds)."""
+    return lin([1, 0], -0.9 + 0.17 * k), lin([0, -1], -(0.9 - 0.13 * k))
+
+
+def _conj(children, smooth, beta):
+    """n-ary And as a tree of at most four children per node (the plan's limit;
+    min and logsumexp are associative, so the value is that of the flat And)."""
+    while len(children) > 4:
+        children = [{"op": "and", "smooth": smooth, "beta": beta, "children": children[i:i + 4]}
+                    if len(children[i:i + 4]) > 1 else children[i]
+                    for i in range(0, len(children), 4)]
+    return {"op": "and", "smooth": smooth, "beta": beta, "children": children}
+
+
+def table2_formulas(smooth: bool = True, beta: float = BETA, interval=TABLE2_INTERVAL) -> dict:
+    """phi_1 .. phi_6 of Table II with synthetic linear predicates on D = 2
+    (invariance, stabilization, strict ordering, sequenced visits, sequenced
+    visit + stabilization, ten regions in any order)."""
+    a, b = interval
+    s = {"smooth": smooth, "beta": beta}
+
+    def both(k):
+        p, q = _region(k)
+        return dict({"op": "and", "children": [p, q]}, **s)
+
+    def ev(child, lo=a, hi=b):
+        return dict({"op": "eventually", "a": lo, "b": hi, "child": child}, **s)
+
+    def al(child, lo=a, hi=b):
+        return dict({"op": "always", "a": lo, "b": hi, "child": child}, **s)
+
+    p0, q0 = _region(0)
+    phi4 = ev(both(0))
+    for k in (1, 2, 3):
+        phi4 = ev(dict({"op": "and", "children": [_region(k)[0], _region(k)[1], phi4]}, **s))
+    return {
+        "phi1": al(both(0), 0, None),
+        "phi2": ev(al(both(0), 0, None), 0, None),
+        "phi3": dict({"op": "until", "a": 0, "b": None, "left": p0, "right": q0}, **s),
+        "phi4": phi4,
+        "phi5": ev(dict({"op": "and", "children": [_region(2)[0], _region(2)[1], ev(al(both(0)))]}, **s)),
+        "phi6": _conj([ev(both(k)) for k in range(10)], smooth, beta),
+    }
