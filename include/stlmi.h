@@ -310,6 +310,30 @@ stl_status stl_interval_sweep(const stl_interval_desc* desc, const float* d_x, i
                               const float* d_a, const float* d_b, int64_t N, float* d_rho, float* d_grad_a,
                               float* d_grad_b, void* stream);
 
+/*
+ * Parametric-STL mining by gradient descent over the time interval (Sec. VII-B,
+ * the pSTL problem): minimise
+ *
+ *     L(a, b) = (1/B) sum_i max(-rho_i, 0) + gamma (a - b),
+ *     rho_i = robustness at t = 0 of op_{mask(aT, bT)}(w . x_i - c)
+ *
+ * over a = sig(p_a), b = sig(p_b) (fractions of the horizon T), for `steps`
+ * steps of p -= lr dL/dp, with the mask steepness and beta annealed from
+ * (c0, beta0) to (c1, beta1) along the sigmoid schedule
+ * v_k = v0 + (v1 - v0) / (1 + exp(-12 (k/(steps-1) - 1/2))).
+ * The loop runs on the GPU in one launch.
+ *
+ * Arguments: desc (op, w, c, mask_eps are used; beta and mask_c are taken
+ * from the schedules), d_x [B][T][D] float32, d_logits [2] float32 device
+ * (p_a, p_b) read and overwritten, d_loss [steps] float32 device (the loss
+ * at each step before its update) or NULL, stream.  Limits: 1 <= T <= 1024,
+ * B >= 1, B * T <= 12288, steps >= 0, c0, c1, beta0, beta1 > 0; otherwise
+ * STL_E_ARG / STL_E_SHAPE.  Allocates nothing.
+ */
+stl_status stl_pstl_descent(const stl_interval_desc* desc, const float* d_x, int64_t B, int64_t T, float c0,
+                            float c1, float beta0, float beta1, int32_t steps, float lr, float gamma,
+                            float* d_logits, float* d_loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

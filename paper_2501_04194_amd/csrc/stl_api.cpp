@@ -33,6 +33,10 @@ hipError_t launch_fused(bool bwd, const DevPlan& plan, const struct Batch& bt, c
 hipError_t set_max_lds_fused(size_t bytes);
 size_t mask_tab_bytes();
 int interval_max_T();
+int pstl_max_BT();
+hipError_t launch_pstl_descent(const float* x, int B, int T, int D, const float* w, float c, int op_sg, float eps,
+                               float c0, float c1, float beta0, float beta1, int steps, float lr, float gamma,
+                               float* p, float* loss, hipStream_t s);
 hipError_t launch_interval_sweep(int op_sg, int smooth, float beta, float mc, float meps, int D, const float* w,
                                  float c, float rho_pad, const float* x, int64_t B, int T, const float* a,
                                  const float* b, int64_t N, float* rho, float* ga, float* gb, hipStream_t s);
@@ -997,6 +1001,27 @@ extern "C" stl_status stl_interval_sweep(const stl_interval_desc* desc, const fl
     hipError_t e = launch_interval_sweep(desc->op == STL_EVENTUALLY ? 1 : -1, desc->smooth ? 1 : 0, desc->beta,
                                          desc->mask_c, desc->mask_eps, desc->D, desc->w, desc->c, desc->rho_pad, d_x,
                                          B, (int)T, d_a, d_b, N, d_rho, d_grad_a, d_grad_b, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return STL_OK;
+}
+
+extern "C" stl_status stl_pstl_descent(const stl_interval_desc* desc, const float* d_x, int64_t B, int64_t T, float c0,
+                                       float c1, float beta0, float beta1, int32_t steps, float lr, float gamma,
+                                       float* d_logits, float* d_loss, void* stream)
+{
+    if (!desc) return fail(STL_E_ARG, "desc is NULL");
+    if (desc->op != STL_ALWAYS && desc->op != STL_EVENTUALLY)
+        return fail(STL_E_ARG, "op must be STL_ALWAYS or STL_EVENTUALLY");
+    if (desc->D < 1 || desc->D > 16) return fail(STL_E_ARG, "D must be in [1, 16]");
+    if (!(desc->mask_eps >= 0.f)) return fail(STL_E_ARG, "mask_eps must be >= 0");
+    if (!(c0 > 0.f && c1 > 0.f && beta0 > 0.f && beta1 > 0.f)) return fail(STL_E_ARG, "schedules must be > 0");
+    if (steps < 0 || !std::isfinite(lr) || !std::isfinite(gamma)) return fail(STL_E_ARG, "bad steps, lr or gamma");
+    if (T < 1 || T > 1024) return fail(STL_E_SHAPE, "T must be in [1, 1024]");
+    if (B < 1 || B * T > pstl_max_BT()) return fail(STL_E_SHAPE, "need B >= 1 and B * T <= %d", pstl_max_BT());
+    if (!d_x || !d_logits) return fail(STL_E_ARG, "null device pointer");
+    hipError_t e = launch_pstl_descent(d_x, (int)B, (int)T, desc->D, desc->w, desc->c,
+                                       desc->op == STL_EVENTUALLY ? 1 : -1, desc->mask_eps, c0, c1, beta0, beta1,
+                                       steps, lr, gamma, d_logits, d_loss, (hipStream_t)stream);
     if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     return STL_OK;
 }

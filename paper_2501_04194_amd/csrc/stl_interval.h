@@ -196,6 +196,157 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_kernel(IntervalArgs A)
     }
 }
 
+// ------------------------------------------------------------------ pSTL descent
+
+// Gradient descent on the parametric-STL mining loss (Sec. VII-B)
+//   L(a, b) = mean_i max(-rho_i, 0) + gamma (a - b),
+//   rho_i = robustness at t = 0 of op_[aT, bT](w . x_i - c) with a smooth mask,
+// over a = sig(p_a), b = sig(p_b) (fractions of the horizon), the mask
+// steepness and beta annealed from (c0, beta0) to (c1, beta1) along a sigmoid
+// schedule.  The whole loop runs in one work-group: the dataset's predicate
+// traces stay in LDS, each step evaluates the mask weights once (one thread
+// per offset) and every signal's rho, d rho/da, d rho/db (threads over
+// signals), reduces the hinge gradient in a fixed order and updates (p_a, p_b)
+// in LDS; no launch per step.
+constexpr int PD_MAXBT = 12288;
+
+struct DescentArgs {
+    const float* x;
+    float* p;            // [2] logits of (a, b), read and written
+    float* loss;         // [steps] or NULL
+    int B, T, D, steps, op_sg;
+    float eps, c0, c1, beta0, beta1, lr, gamma, c;
+    float w[16];
+};
+
+DEV float sched(int k, int steps, float lo, float hi)
+{
+    const float u = (float)k / (float)max(1, steps - 1) - 0.5f;
+    return lo + (hi - lo) / (1.f + expf(-12.f * u));
+}
+
+__global__ void __launch_bounds__(IV_NT) stl_pstl_descent_kernel(DescentArgs A)
+{
+    __shared__ float U[PD_MAXBT];
+    __shared__ float Wt[IV_MAXT / 4][3];     // w_j, dw_j/da, dw_j/db for the current step
+    __shared__ double red[3][IV_NT / 64];
+    __shared__ float pab[2];
+    const int B = A.B, T = A.T, D = A.D;
+    const float sg = (float)A.op_sg;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < B * T; i += IV_NT) {
+        float u = 0.f;
+        for (int d = 0; d < D; ++d) u = fmaf(A.w[d], A.x[(int64_t)i * D + d], u);
+        U[i] = u - A.c;
+    }
+    if (threadIdx.x < 2) pab[threadIdx.x] = A.p[threadIdx.x];
+    __syncthreads();
+    for (int k = 0; k < A.steps; ++k) {
+        const float c = sched(k, A.steps, A.c0, A.c1), beta = sched(k, A.steps, A.beta0, A.beta1);
+        const float bl = beta * LOG2E;
+        const float af = 1.f / (1.f + expf(-pab[0])), bf = 1.f / (1.f + expf(-pab[1]));
+        MaskP mp;
+        mp.a = af * (float)T;
+        mp.b = bf * (float)T;
+        mp.c = c;
+        mp.eps = A.eps;
+        mp.unb = false;
+        mp.band = 1.f - expf(-c * (mp.b - mp.a));
+        for (int j = threadIdx.x; j < T; j += IV_NT) {
+            float da, db;
+            Wt[j][0] = mask_wk(mp, j, &da, &db);
+            Wt[j][1] = da;
+            Wt[j][2] = db;
+        }
+        __syncthreads();
+        double ha = 0.0, hb = 0.0, hl = 0.0;      // this thread's hinge sums
+        for (int i = threadIdx.x; i < B; i += IV_NT) {
+            const float* u = U + i * T;
+            int R = INT_MIN;
+            bool any = false;
+            for (int j = 0; j < T; ++j)
+                if (Wt[j][0] > 0.f) {
+                    R = max(R, (int)ceilf(fminf(fmaxf(sg * bl * u[j], -1e9f), 1e9f)));
+                    any = true;
+                }
+            float rho = -sg * 1e6f, ga = 0.f, gb = 0.f;
+            if (any) {
+                double S = 0.0, Sa = 0.0, Sb = 0.0;
+                for (int j = 0; j < T; ++j) {
+                    const float wj = Wt[j][0];
+                    if (!(wj > 0.f)) continue;
+                    const double e = exp2d_neg(sg * bl * u[j] - (float)R);
+                    S = fma((double)wj, e, S);
+                    Sa = fma((double)Wt[j][1], e, Sa);
+                    Sb = fma((double)Wt[j][2], e, Sb);
+                }
+                rho = sg * ((float)R + log2d(S)) / bl;
+                ga = (float)((double)(sg / beta) * (Sa / S));
+                gb = (float)((double)(sg / beta) * (Sb / S));
+            }
+            if (rho < 0.f) {
+                ha -= ga;
+                hb -= gb;
+                hl -= rho;
+            }
+        }
+        for (int d = 32; d > 0; d >>= 1) {
+            ha += __shfl_xor(ha, d);
+            hb += __shfl_xor(hb, d);
+            hl += __shfl_xor(hl, d);
+        }
+        if (lane == 0) {
+            red[0][wv] = ha;
+            red[1][wv] = hb;
+            red[2][wv] = hl;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sa = 0.0, sb = 0.0, sl = 0.0;
+            for (int q = 0; q < IV_NT / 64; ++q) {
+                sa += red[0][q];
+                sb += red[1][q];
+                sl += red[2][q];
+            }
+            // d L / d a_frac = T mean(-[rho < 0] d rho / d a_steps) + gamma (b: - gamma)
+            const float dla = (float)(T * sa / B) + A.gamma, dlb = (float)(T * sb / B) - A.gamma;
+            if (A.loss) A.loss[k] = (float)(sl / B) + A.gamma * (af - bf);
+            pab[0] -= A.lr * dla * af * (1.f - af);
+            pab[1] -= A.lr * dlb * bf * (1.f - bf);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) A.p[threadIdx.x] = pab[threadIdx.x];
+}
+
+int pstl_max_BT() { return PD_MAXBT; }
+
+hipError_t launch_pstl_descent(const float* x, int B, int T, int D, const float* w, float c, int op_sg, float eps,
+                               float c0, float c1, float beta0, float beta1, int steps, float lr, float gamma,
+                               float* p, float* loss, hipStream_t s)
+{
+    DescentArgs A;
+    A.x = x;
+    A.p = p;
+    A.loss = loss;
+    A.B = B;
+    A.T = T;
+    A.D = D;
+    A.steps = steps;
+    A.op_sg = op_sg;
+    A.eps = eps;
+    A.c0 = c0;
+    A.c1 = c1;
+    A.beta0 = beta0;
+    A.beta1 = beta1;
+    A.lr = lr;
+    A.gamma = gamma;
+    A.c = c;
+    for (int d = 0; d < 16; ++d) A.w[d] = d < D ? w[d] : 0.f;
+    hipLaunchKernelGGL(stl_pstl_descent_kernel, dim3(1), dim3(IV_NT), 0, s, A);
+    return hipGetLastError();
+}
+
 int interval_max_T() { return IV_MAXT; }
 
 hipError_t launch_interval_sweep(int op_sg, int smooth, float beta, float mc, float meps, int D, const float* w,

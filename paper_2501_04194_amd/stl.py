@@ -61,7 +61,7 @@ class IntervalDesc(ctypes.Structure):
 EXPORTS = ["stl_compile", "stl_plan_destroy", "stl_plan_info", "stl_workspace_size", "stl_forward",
            "stl_backward", "stl_saved_size", "stl_forward_saving", "stl_backward_saved", "stl_last_error",
            "stl_lpt_order", "stl_autotune", "stl_graph_capture", "stl_graph_launch", "stl_graph_destroy",
-           "stl_interval_sweep"]
+           "stl_interval_sweep", "stl_pstl_descent"]
 
 
 def lib():
@@ -94,6 +94,9 @@ def lib():
     L.stl_graph_launch.argtypes = [vp, vp]
     L.stl_graph_destroy.argtypes = [vp]
     L.stl_interval_sweep.argtypes = [ctypes.POINTER(IntervalDesc), vp, i64, i64, vp, vp, i64, vp, vp, vp, vp]
+    f32 = ctypes.c_float
+    L.stl_pstl_descent.argtypes = [ctypes.POINTER(IntervalDesc), vp, i64, i64, f32, f32, f32, f32, i32, f32, f32, vp,
+                                   vp, vp]
     for f in EXPORTS:
         if f != "stl_last_error":
             getattr(L, f).restype = ctypes.c_int
@@ -380,6 +383,30 @@ def interval_sweep(x, a, b, w, c=0.0, op="always", smooth=True, beta=10.0, mask_
     _check(lib().stl_interval_sweep(ctypes.byref(d), _ptr(x), B, T, _ptr(a), _ptr(b), N, _ptr(rho), _ptr(ga),
                                     _ptr(gb), _stream(torch, x.device)))
     return (rho, ga, gb) if grads else rho
+
+
+def pstl_descent(x, logits, steps, lr=1e-2, gamma=0.1, c_range=(1.0, 20.0), beta_range=(1.0, 20.0), w=(1.0,),
+                 c=0.0, op="always", mask_eps=1e-6, want_loss=False):
+    """Gradient descent on the pSTL loss in one launch (``stl_pstl_descent``):
+    logits (a float32 device tensor [2], p_a and p_b) is updated in place;
+    returns the per-step loss tensor when ``want_loss``."""
+    import torch
+    _require_gpu(torch, x)
+    x = x.contiguous()
+    B, T, D = x.shape
+    d = IntervalDesc()
+    d.op = STL_ALWAYS if op == "always" else STL_EVENTUALLY
+    d.smooth = 1
+    d.mask_eps = float(mask_eps)
+    d.D = D
+    for k, v in enumerate(w):
+        d.w[k] = float(v)
+    d.c = float(c)
+    loss = torch.empty(max(1, steps), dtype=torch.float32, device=x.device) if want_loss else None
+    _check(lib().stl_pstl_descent(ctypes.byref(d), _ptr(x), B, T, float(c_range[0]), float(c_range[1]),
+                                  float(beta_range[0]), float(beta_range[1]), int(steps), float(lr), float(gamma),
+                                  _ptr(logits), _ptr(loss), _stream(torch, x.device)))
+    return loss
 
 
 def lpt_order(offsets_host):
