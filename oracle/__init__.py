@@ -168,7 +168,10 @@ class Compiled:
                 raise ValueError("bad interval")
         else:
             raise ValueError("unknown op %r" % op)
-        nd.smooth = 1 if f.get("smooth", False) else 0
+        sm = f.get("smooth", False)
+        nd.smooth = 2 if sm == "softmax" else (1 if sm else 0)
+        if nd.smooth == 2 and (op not in ("and", "or", "eventually", "always") or "mask" in f):
+            raise ValueError("the softmax-weighted form applies to and/or and unmasked windows")
         nd.beta = _val(f.get("beta", 10.0), self.params)
         nd.nch = len(kids)
         for i, k in enumerate(kids):

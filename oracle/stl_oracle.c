@@ -29,6 +29,10 @@
  *     Until always clip (NEUTRAL).
  *   - smooth operators use beta (= 1/temperature) inside the exponent:
  *     smax(V) = (1/beta) log sum exp(beta v), smin(V) = -smax(-V).
+ *     smooth = 2 selects the softmax-weighted form of Sec. III-C instead,
+ *     smax(V) = sum v exp(beta v) / sum exp(beta v) (the printed denominator
+ *     index is read as running over all of V), smin(V) = -smax(-V); on And/Or
+ *     and on unmasked Eventually/Always windows.
  *   - the smooth mask weight enters the logsumexp as a multiplicative weight:
  *     out_t = (1/beta) log sum_{k>=0, t+k<L} w_k exp(beta u_{t+k}),
  *     w_k = max(sig(c(k-a)) - sig(c(k-b)) - eps, 0), a and b in timesteps.
@@ -155,6 +159,30 @@ static double wlse(const welem *e, int n, double beta)
     return m + log(s) / beta;
 }
 
+/* softmax-weighted mean sum w v exp(beta v) / sum w exp(beta v), max-shifted */
+static double wsoft(const welem *e, int n, double beta)
+{
+    double m = e[0].v;
+    for (int i = 1; i < n; ++i) if (e[i].v > m) m = e[i].v;
+    double s0 = 0, s1 = 0;
+    for (int i = 0; i < n; ++i) {
+        double q = e[i].w * exp(beta * (e[i].v - m));
+        s0 += q;
+        s1 += q * e[i].v;
+    }
+    return s1 / s0;
+}
+
+/* d wsoft / d v_k = p_k (1 + beta (v_k - r)), p_k = w_k exp(beta v_k) / sum */
+static void wsoft_grad(const welem *e, int n, double beta, double r, double *d)
+{
+    double m = e[0].v;
+    for (int i = 1; i < n; ++i) if (e[i].v > m) m = e[i].v;
+    double s0 = 0;
+    for (int i = 0; i < n; ++i) s0 += e[i].w * exp(beta * (e[i].v - m));
+    for (int i = 0; i < n; ++i) d[i] = e[i].w * exp(beta * (e[i].v - m)) / s0 * (1.0 + beta * (e[i].v - r));
+}
+
 /* ------------------------------------------------------------- forward */
 
 static void fwd_node(const onode *nodes, int idx, const double *x, int L, int D,
@@ -197,7 +225,8 @@ static void fwd_node(const onode *nodes, int idx, const double *x, int L, int D,
             for (int k = 0; k < nd->nch; ++k) {
                 buf[k].v = sg * tr[(size_t)nd->ch[k] * L + t]; buf[k].w = 1; buf[k].src = k;
             }
-            double r = nd->smooth ? wlse(buf, nd->nch, nd->beta) : buf[hard_argmax(buf, nd->nch)].v;
+            double r = nd->smooth == 2 ? wsoft(buf, nd->nch, nd->beta)
+                       : nd->smooth ? wlse(buf, nd->nch, nd->beta) : buf[hard_argmax(buf, nd->nch)].v;
             out[t] = sg * r;
         }
         break;
@@ -211,6 +240,7 @@ static void fwd_node(const onode *nodes, int idx, const double *x, int L, int D,
             int n = gather_window(nd, u, L, t, sg, wtab, buf);
             double r;
             if (n == 0) r = -rho_pad;
+            else if (nd->smooth == 2) r = wsoft(buf, n, nd->beta);
             else if (nd->smooth) r = wlse(buf, n, nd->beta);
             else r = buf[hard_argmax(buf, n)].v;
             out[t] = sg * r;
@@ -325,7 +355,11 @@ static void bwd_node(const onode *nodes, int idx, const double *x, int L, int D,
             for (int k = 0; k < nd->nch; ++k) {
                 buf[k].v = sg * tr[(size_t)nd->ch[k] * L + t]; buf[k].w = 1; buf[k].src = k;
             }
-            if (nd->smooth) {
+            if (nd->smooth == 2) {
+                double d[OMAXCH];
+                wsoft_grad(buf, nd->nch, nd->beta, sg * out[t], d);
+                for (int k = 0; k < nd->nch; ++k) gb[(size_t)nd->ch[k] * L + t] += g[t] * d[k];
+            } else if (nd->smooth) {
                 double o = sg * out[t];
                 for (int k = 0; k < nd->nch; ++k)
                     gb[(size_t)nd->ch[k] * L + t] += g[t] * exp(nd->beta * (buf[k].v - o));
@@ -349,6 +383,12 @@ static void bwd_node(const onode *nodes, int idx, const double *x, int L, int D,
             if (!nd->smooth) {
                 int k = hard_argmax(buf, n);
                 if (buf[k].src >= 0) gu[buf[k].src] += g[t];
+                continue;
+            }
+            if (nd->smooth == 2) {
+                wsoft_grad(buf, n, nd->beta, sg * out[t], tmpV);
+                for (int k = 0; k < n; ++k)
+                    if (buf[k].src >= 0) gu[buf[k].src] += g[t] * tmpV[k];
                 continue;
             }
             double o = sg * out[t];
@@ -455,7 +495,10 @@ static int scratch_alloc(scratch_t *s, const onode *nodes, int n, int L)
     s->dwa = (double *)malloc(sizeof(double) * Lz);
     s->dwb = (double *)malloc(sizeof(double) * Lz);
     s->tmpR = (double *)malloc(sizeof(double) * Lz);
-    s->tmpV = (double *)malloc(sizeof(double) * Lz);
+    {   /* also the per-element softmax gradients of the widest window */
+        size_t wc = window_cap(nodes, n, L);
+        s->tmpV = (double *)malloc(sizeof(double) * (wc > Lz ? wc : Lz));
+    }
     s->tmpRb = (double *)malloc(sizeof(double) * Lz);
     s->tr = (double *)malloc(sizeof(double) * (size_t)n * Lz);
     s->gb = (double *)malloc(sizeof(double) * (size_t)n * Lz);

@@ -23,6 +23,10 @@ the formula; named entries are the learnable (or annealable) scalars.
   {"op": "until", "left": f, "right": f, "a": int, "b": int | None,
    "smooth": bool, "beta": num}
 
+``"smooth": "softmax"`` selects the softmax-weighted smooth max/min of
+Sec. III-C (sum v exp(beta v) / sum exp(beta v)) on and/or and on unmasked
+windows; ``True`` the logsumexp form.
+
 ``b: None`` means an unbounded interval.  Intervals are inclusive timestep
 offsets.  The workloads mirror the shapes and value laws of the benchmark
 configurations (random walks started uniformly in [-1, 1]^D with Gaussian

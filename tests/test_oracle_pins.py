@@ -476,3 +476,64 @@ def test_interval_sweep_pins(orc):
     rp, _, _ = orc.interval_sweep(x, a2, b2 + h, [1.0], op="always", beta=5.0, mask_c=1.5)
     rm, _, _ = orc.interval_sweep(x, a2, b2 - h, [1.0], op="always", beta=5.0, mask_c=1.5)
     assert np.allclose(gb, (rp - rm) / (2 * h), rtol=1e-5, atol=1e-8)
+
+
+def test_softmax_weighted_form(orc):
+    """Softmax-weighted smooth max/min of Sec. III-C (smooth = "softmax"): a
+    weighted mean of the window, so it lies between min and max, equals a
+    constant window's value, tends to the plain mean as beta -> 0 and to the max
+    as beta grows; unlike logsumexp it is not associative (Sec. IV-D: nesting it
+    changes the value); duality with Not; gradients match central differences."""
+    rng = np.random.default_rng(12)
+    L = 40
+    u = rng.normal(size=L)
+    x = sig1(u)
+    for (a, b) in [(0, 6), (3, 11), (0, None)]:
+        spec = ev(S, a, b, smooth="softmax", beta=3.0)
+        r = orc.forward(spec, x)[0]
+        for t in range(L):
+            hi = L - 1 if b is None else min(L - 1, t + b)
+            if t + a > L - 1:
+                assert r[t] == -RHO
+                continue
+            win = u[t + a:hi + 1]
+            assert win.min() - 1e-12 <= r[t] <= win.max() + 1e-12
+        # beta -> 0: the plain mean of the window; large beta: the max
+        r0 = orc.forward(ev(S, a, b, smooth="softmax", beta=1e-9), x)[0]
+        r1 = orc.forward(ev(S, a, b, smooth="softmax", beta=400.0), x)[0]
+        for t in range(L - (a or 0)):
+            hi = L - 1 if b is None else min(L - 1, t + b)
+            win = u[t + a:hi + 1]
+            assert abs(r0[t] - win.mean()) <= 1e-8
+            assert abs(r1[t] - win.max()) <= 2e-2
+    # constant window
+    c = orc.forward(ev(S, 2, 9, smooth="softmax", beta=5.0), sig1(np.full(20, 0.7)))[0]
+    assert np.allclose(c[:11], 0.7, rtol=0, atol=1e-15)
+    # not associative: softmax-max of (softmax-max of {0, 1}, 0.5) differs from that of {0, 1, 0.5}
+    x3 = np.array([[[0.0, 1.0, 0.5]]], dtype=np.float64).reshape(1, 1, 3)
+    p = [{"op": "linear", "w": [1.0 if i == k else 0.0 for i in range(3)], "c": 0.0} for k in range(3)]
+    flat = orc.forward({"op": "or", "smooth": "softmax", "beta": 2.0, "children": p}, x3)[0, 0]
+    nest = orc.forward({"op": "or", "smooth": "softmax", "beta": 2.0, "children": [
+        {"op": "or", "smooth": "softmax", "beta": 2.0, "children": p[:2]}, p[2]]}, x3)[0, 0]
+    assert abs(flat - nest) > 1e-3
+    lse_flat = orc.forward({"op": "or", "smooth": True, "beta": 2.0, "children": p}, x3)[0, 0]
+    lse_nest = orc.forward({"op": "or", "smooth": True, "beta": 2.0, "children": [
+        {"op": "or", "smooth": True, "beta": 2.0, "children": p[:2]}, p[2]]}, x3)[0, 0]
+    assert abs(lse_flat - lse_nest) < 1e-12
+    # duality: Always = Not Eventually Not, exactly
+    alw = orc.forward(al(S, 1, 7, smooth="softmax", beta=3.0), x)[0]
+    dual = orc.forward({"op": "not", "child": ev({"op": "not", "child": S}, 1, 7, smooth="softmax", beta=3.0)}, x)[0]
+    assert np.array_equal(alw, dual)
+    # gradients against central differences (windows and and/or)
+    for spec in [ev(S, 2, 9, smooth="softmax", beta=2.5), al(S, 0, None, smooth="softmax", beta=1.5),
+                 {"op": "and", "smooth": "softmax", "beta": 4.0, "children": [
+                     S, ev(S, 1, 4, smooth="softmax", beta=2.0)]}]:
+        G = rng.normal(size=(1, L))
+        dx, _ = orc.backward(spec, x, G)
+        h = 1e-6
+        fd = np.zeros(L)
+        for j in range(L):
+            xp = x.copy(); xp[0, j, 0] += h
+            xm = x.copy(); xm[0, j, 0] -= h
+            fd[j] = ((orc.forward(spec, xp) - orc.forward(spec, xm)) * G).sum() / (2 * h)
+        assert np.allclose(dx[0, :, 0], fd, rtol=1e-6, atol=1e-7)
