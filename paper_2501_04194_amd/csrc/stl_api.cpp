@@ -136,11 +136,25 @@ stl_status emit(Builder& B, int id, int depth, int* out)
         kid_ins.push_back(ci);
     }
     const bool smooth = n.smooth != 0;
+    if (n.smooth < 0 || n.smooth > 2) return fail(STL_E_ARG, "node %d: smooth must be 0, 1 or 2", id);
     if (smooth) {
         if (n.beta_param < 0 || n.beta_param >= B.n_params)
             return fail(STL_E_ARG, "node %d: smooth node needs beta_param in [0, n_params)", id);
         I.beta = (int8_t)n.beta_param;
         I.flags |= F_SMOOTH;
+    }
+    if (n.smooth == 2) {
+        // softmax-weighted form: And/Or with at most MAX_NCH children (it is not
+        // associative, so no regrouping) and unmasked windows with the NEUTRAL pad
+        const bool win = (n.op == STL_EVENTUALLY || n.op == STL_ALWAYS) && n.mask_param < 0 &&
+                         (n.b < 0 || n.pad == STL_PAD_NEUTRAL);
+        const bool nary = (n.op == STL_AND || n.op == STL_OR) && n.n_child <= MAX_NCH;
+        if (!win && !nary)
+            return fail(STL_E_UNSUPPORTED,
+                        "node %d: the softmax-weighted form applies to And/Or with up to %d children and to "
+                        "unmasked Eventually/Always with the NEUTRAL pad",
+                        id, MAX_NCH);
+        I.flags |= F_SOFT;
     }
     switch (n.op) {
     case STL_TRUE:
@@ -397,7 +411,7 @@ extern "C" stl_status stl_compile(const stl_node* nodes, int32_t n_nodes, const 
             F.root_nary = 0;
             F.ins[0] = (int8_t)rootk;
             F.pred[0] = (int8_t)B.kids[rootk][0];
-        } else if (R.kind == K_NARY && (R.flags & F_SMOOTH) && B.kids[rootk].size() <= 4) {
+        } else if (R.kind == K_NARY && (R.flags & F_SMOOTH) && !(R.flags & F_SOFT) && B.kids[rootk].size() <= 4) {
             bool ok = true;
             for (int c : B.kids[rootk]) ok = ok && is_fmask(c);
             if (ok) {

@@ -344,6 +344,21 @@ DEV void op_nary_fwd(const Env& e, const Instr& I, const int8_t* ch, float* out)
             }
             out[t] = sg * best;
         }
+    } else if (I.flags & F_SOFT) {
+        // softmax-weighted mean of the oriented values (Sec. III-C)
+        const float bl = pbeta(e, I) * LOG2E;
+        for (int t = threadIdx.x; t < e.L; t += blockDim.x) {
+            float v[MAX_NCH];
+            float m = -INFINITY;
+            for (int k = 0; k < n; ++k) { v[k] = sg * c[k][t]; m = fmaxf(m, v[k]); }
+            float s0 = 0.f, s1 = 0.f;
+            for (int k = 0; k < n; ++k) {
+                const float q = exp2f((v[k] - m) * bl);
+                s0 += q;
+                s1 = fmaf(q, v[k], s1);
+            }
+            out[t] = sg * (s1 / s0);
+        }
     } else {
         const float bl = pbeta(e, I) * LOG2E;
         for (int t = threadIdx.x; t < e.L; t += blockDim.x) {
@@ -381,6 +396,16 @@ DEV void op_nary_bwd(const Env& e, const Instr& I)
                 if (v > best) { best = v; kb = k; }
             }
             for (int k = 0; k < n; ++k) gc[k][t] = (k == kb) ? gt : 0.f;
+        } else if (I.flags & F_SOFT) {
+            // d r / d v_k = p_k (1 + beta (v_k - r)), r = sg out
+            const float r = sg * out[t], beta = bl / LOG2E;
+            float v[MAX_NCH];
+            float m = -INFINITY;
+            for (int k = 0; k < n; ++k) { v[k] = sg * c[k][t]; m = fmaxf(m, v[k]); }
+            float s0 = 0.f;
+            for (int k = 0; k < n; ++k) s0 += exp2f((v[k] - m) * bl);
+            for (int k = 0; k < n; ++k)
+                gc[k][t] = gt * (exp2f((v[k] - m) * bl) / s0) * (1.f + beta * (v[k] - r));
         } else {
             const float o = sg * out[t];
             for (int k = 0; k < n; ++k) gc[k][t] = gt * exp2f((sg * c[k][t] - o) * bl);
@@ -497,6 +522,43 @@ DEV void win_smooth_sum(const Env& e, const float* u, SP* acc, float sgz, int kl
 // Transposed window sum for adjoints: for each position j,
 // out[j] = sum over t in [j-khi, j-klo] (clipped to [0, nt_valid)) of h[t].
 // h (scaled pairs) is consumed (overwritten by the scans).
+// Window sums of u_j 2^{sgz u_j} (signed scaled pairs) over [t+klo, t+khi]
+// (khi < 0: to the end), NEUTRAL pad: the numerator of the softmax-weighted
+// mean whose denominator win_smooth_sum gives.
+DEV void win_smooth_sum_w(const Env& e, const float* u, SP* acc, float sgz, int klo, int khi, SP* Pre, SP* Suf)
+{
+    const int L = e.L;
+    const bool unb = khi < 0;
+    const int n = L - klo;
+    const int K = unb ? n : khi - klo + 1;
+    if (n > 0) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            SP v = sp_leaf(sgz * u[klo + i]);
+            v.s *= u[klo + i];
+            Suf[i] = v;
+            if (!unb) Pre[i] = v;
+        }
+        __syncthreads();
+        seg_scan(Suf, n, unb ? 0 : K, true, sp_zero(), OpSP(), *e.sh);
+        if (!unb) seg_scan(Pre, n, K, false, sp_zero(), OpSP(), *e.sh);
+    }
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        SP a = sp_zero();
+        if (t < n) {
+            int e2 = min(t + K - 1, n - 1);
+            a = (unb || t / K == e2 / K) ? Suf[t] : sp_add(Suf[t], Pre[e2]);
+        }
+        acc[t] = a;
+    }
+    __syncthreads();
+}
+
+// ratio of two scaled pairs as a float (den > 0)
+DEV float sp_ratio(SP num, SP den)
+{
+    return ldexpf(num.s / den.s, clampe((long long)num.r - den.r));
+}
+
 DEV void win_smooth_adj_sum(const Env& e, SP* h, SP* hPre, SP* res, int klo, int khi, int n_valid)
 {
     const int L = e.L;
@@ -1034,6 +1096,15 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
         const float padv = e.P->coef[I.coef];
         if (!is_smooth(I)) {
             win_hard(e, u, out, nullptr, sg, I.a, khi, I.pad, padv, (VI*)S(e, 0), (VI*)S(e, 2));
+        } else if (I.flags & F_SOFT) {
+            // softmax-weighted mean over the window (NEUTRAL pad): out = sum u 2^{z} / sum 2^{z}
+            const float bl = pbeta(e, I) * LOG2E;
+            SP* den = (SP*)S(e, 4);
+            SP* num = (SP*)S(e, 6);
+            win_smooth_sum(e, u, den, sg * bl, I.a, khi, PAD_NEUTRAL, 0.f, (SP*)S(e, 0), (SP*)S(e, 2));
+            win_smooth_sum_w(e, u, num, sg * bl, I.a, khi, (SP*)S(e, 0), (SP*)S(e, 2));
+            for (int t = threadIdx.x; t < L; t += blockDim.x)
+                out[t] = t + I.a <= L - 1 ? sp_ratio(num[t], den[t]) : -sg * e.P->rho_pad;
         } else {
             const float bl = pbeta(e, I) * LOG2E;
             SP* acc = (SP*)S(e, 4);
@@ -1147,6 +1218,39 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
             int* js = (int*)S(e, 4);
             win_hard(e, u, S(e, 5), js, sg, I.a, khi, I.pad, padv, (VI*)S(e, 0), (VI*)S(e, 2));
             win_hard_adj(e, g, gu, js, (double*)S(e, 6));
+            break;
+        }
+        if (I.flags & F_SOFT) {
+            // d out_t / d u_j = p_j(t) (1 + k (u_j - out_t)), p_j(t) = 2^{z_j} / S0(t), k = sg beta:
+            // gu_j = 2^{z_j} [(1 + k u_j) sum_t G_t / S0(t) - k sum_t G_t out_t / S0(t)]
+            // over the t whose window holds j (transposed window sums)
+            const float bl = pbeta(e, I) * LOG2E, kap = sg * bl / LOG2E;
+            const float* out = slot(e, I.b_out);
+            const int n = L - I.a;
+            SP* den = (SP*)S(e, 6);
+            win_smooth_sum(e, u, den, sg * bl, I.a, khi, PAD_NEUTRAL, 0.f, (SP*)S(e, 0), (SP*)S(e, 2));
+            SP* h = (SP*)S(e, 0);
+            SP* h2 = (SP*)S(e, 8);
+            for (int t = threadIdx.x; t < L; t += blockDim.x) {
+                SP a = sp_zero(), b2 = sp_zero();
+                if (t < n) {
+                    const SP d = den[t];
+                    a = SP{g[t] / d.s, -d.r};
+                    b2 = SP{g[t] * out[t] / d.s, -d.r};
+                }
+                h[t] = a;
+                h2[t] = b2;
+            }
+            __syncthreads();
+            SP* res = (SP*)S(e, 4);
+            SP* res2 = (SP*)S(e, 10);
+            win_smooth_adj_sum(e, h, (SP*)S(e, 2), res, I.a, khi, n);
+            win_smooth_adj_sum(e, h2, (SP*)S(e, 2), res2, I.a, khi, n);
+            for (int j = threadIdx.x; j < L; j += blockDim.x) {
+                const SP r1 = res[j], r2 = res2[j];
+                const SP c = sp_add(SP{r1.s * (1.f + kap * u[j]), r1.r}, SP{-kap * r2.s, r2.r});
+                gu[j] = sp_times_exp2(c, sg * bl * u[j]);
+            }
             break;
         }
         const float bl = pbeta(e, I) * LOG2E;

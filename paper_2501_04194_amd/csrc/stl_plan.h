@@ -30,7 +30,8 @@ enum Flag : int8_t {
     F_SMOOTH = 1,
     F_MIN = 2,        // min-type (and, always): evaluated as max on negated values
     F_UNB = 4,        // unbounded integer interval
-    F_MASK_UNB = 8    // smooth mask with b = +inf
+    F_MASK_UNB = 8,   // smooth mask with b = +inf
+    F_SOFT = 16       // smooth form is the softmax-weighted mean (Sec. III-C), not logsumexp
 };
 
 constexpr int MAX_INSTR = 48;

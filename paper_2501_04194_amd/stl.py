@@ -185,7 +185,8 @@ class _Emitter:
             nd.b = -1 if f.get("b") is None else int(f["b"])
         else:
             raise ValueError("unknown op %r" % op)
-        nd.smooth = 1 if f.get("smooth", False) else 0
+        sm = f.get("smooth", False)
+        nd.smooth = 2 if sm == "softmax" else (1 if sm else 0)
         if nd.smooth:
             nd.beta_param = self.slot(f.get("beta", 10.0))
         nd.n_child = len(kids)

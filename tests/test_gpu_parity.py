@@ -365,3 +365,37 @@ def test_autotune_candidates_agree():
     r0 = g.plan.forward(xt, g.pv)
     r1 = g.plan.forward(xt, g.pv, launch=best)
     assert_close(r1.cpu().numpy(), r0.cpu().numpy(), rel=2e-6, what="tuned")
+
+
+# --------------------------------------------------------------------------- softmax-weighted form
+
+@pytest.mark.parametrize("ab", [(0, 0), (0, 7), (3, 40), (0, None), (12, None)])
+@pytest.mark.parametrize("kind", ["eventually", "always"])
+def test_softmax_windows(ab, kind):
+    """Softmax-weighted smooth max/min (Sec. III-C) over windows, against the oracle."""
+    rng = np.random.default_rng(21)
+    x = walk(rng, 3, 517, s=0.1)
+    spec = dict({"op": kind, "a": ab[0], "b": ab[1], "child": S1, "smooth": "softmax", "beta": 6.0})
+    check_formula(spec, x, what="softmax %s%s" % (kind, ab))
+
+
+def test_softmax_nary_and_nesting():
+    rng = np.random.default_rng(22)
+    x = walk(rng, 3, 300, D=3, s=0.1)
+    p = [{"op": "linear", "w": [1.0 if i == k else 0.0 for i in range(3)], "c": 0.1 * k} for k in range(3)]
+    spec = {"op": "and", "smooth": "softmax", "beta": 4.0, "children": [
+        p[0], {"op": "or", "smooth": "softmax", "beta": 2.0, "children": [p[1], p[2]]},
+        ev(p[2], 2, 30, smooth="softmax", beta=8.0)]}
+    check_formula(spec, x, what="softmax nary")
+    # mixed with logsumexp and hard nodes
+    spec = al({"op": "or", "smooth": "softmax", "beta": 3.0, "children": [p[0], p[1]]}, 0, None, smooth=True,
+              beta=10.0)
+    check_formula(spec, x, what="softmax under logsumexp")
+
+
+def test_softmax_unsupported_forms():
+    from paper_2501_04194_amd import stl
+    with pytest.raises(stl.StlError, match="softmax"):
+        stl.Plan(ev(S1, 0, 5, smooth="softmax", beta=1.0, pad="last"), 1)
+    with pytest.raises(stl.StlError, match="softmax"):
+        stl.Plan({"op": "until", "a": 0, "b": 3, "smooth": "softmax", "beta": 1.0, "left": S1, "right": S1}, 1)
