@@ -316,6 +316,24 @@ def bench_mining(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_planning(args):
+    """Trajectory planning with a learnable interval (Sec. VII-A): T = 51, one
+    problem, 2000 Adam steps; one step (two library calls, the cost terms,
+    backward and Adam) captured in a HIP graph and replayed."""
+    from paper_2501_04194_amd import planning
+    planning.plan(steps=20)                       # warm-up
+    u, a, b, rho, dt = planning.plan(steps=2000)
+    out = {"metric": "trajectory-planning gradient steps/s (T=51, learnable Always interval)",
+           "value": 1.0 / dt, "unit": "steps/s", "n_gpus": 1, "steps": 2000, "warmup": 20,
+           "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "traj_planning_T51", "T": 51, "dt": 0.1, "u_max": 2.0, "I_nom": 0.2,
+                      "gamma": [1.1, 0.05, 2.0, 0.5], "init_ab": [0.14, 0.82], "regions": planning.REGIONS},
+           "result": {"a": float(a[0]), "b": float(b[0]), "rho": float(rho[0])},
+           "roofline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,7 +345,8 @@ def main():
     ap.add_argument("--recompute", action="store_true", help="backward recomputes the node traces")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer three times (the reference kernel for HBM counters)")
-    ap.add_argument("--workload", default="smooth_mask", choices=["smooth_mask", "smooth_until", "ragged", "intervals", "table2", "mining"],
+    ap.add_argument("--workload", default="smooth_mask", choices=["smooth_mask", "smooth_until", "ragged", "intervals", "table2", "mining",
+                             "planning"],
                     help="smooth_mask: the headline workload; the others are secondary measurements")
     ap.add_argument("--interval-batch", type=int, default=1, help="signals per interval sweep (--workload intervals)")
     args = ap.parse_args()
@@ -349,6 +368,8 @@ def main():
         return bench_table2(args)
     if args.workload == "mining":
         return bench_mining(args)
+    if args.workload == "planning":
+        return bench_planning(args)
     if args.workload != "smooth_mask":
         return bench_graph(args)
 
