@@ -96,6 +96,18 @@ class Compiled:
         n = len(self.nodes)
         self.arr = (ONode * n)(*self.nodes)
 
+    def _mask(self, nd, m):
+        """Smooth time-interval mask (Sec. VI) on a temporal node; returns
+        the names of its learnable bounds."""
+        nd.masked = 1
+        nd.ma = _val(m["a"], self.params)
+        nd.mb_inf = 1 if m.get("b") is None else 0
+        nd.mb = 0.0 if nd.mb_inf else _val(m["b"], self.params)
+        nd.mc = _val(m["c"], self.params)
+        nd.meps = _val(m.get("eps", 1e-6), self.params)
+        return (m["a"] if isinstance(m["a"], str) else None,
+                m.get("b") if isinstance(m.get("b"), str) else None)
+
     def _emit(self, f):
         op = f["op"]
         nd = ONode()
@@ -141,31 +153,26 @@ class Compiled:
             nd.op = O_EV if op == "eventually" else O_ALW
             kids = [self._emit(f["child"])]
             if "mask" in f:
-                m = f["mask"]
-                nd.masked = 1
-                nd.ma = _val(m["a"], self.params)
-                nd.mb_inf = 1 if m.get("b") is None else 0
-                nd.mb = 0.0 if nd.mb_inf else _val(m["b"], self.params)
-                nd.mc = _val(m["c"], self.params)
-                nd.meps = _val(m.get("eps", 1e-6), self.params)
-                names = (m["a"] if isinstance(m["a"], str) else None,
-                         m.get("b") if isinstance(m.get("b"), str) else None)
+                names = self._mask(nd, f["mask"])
             else:
                 nd.a = int(f.get("a", 0))
                 b = f.get("b")
                 nd.b = -1 if b is None else int(b)
                 if nd.a < 0 or (nd.b >= 0 and nd.b < nd.a):
                     raise ValueError("bad interval")
-                nd.pad = PADS[f.get("pad", "neutral")]
-                nd.pad_value = float(f.get("pad_value", 0.0))
+            nd.pad = PADS[f.get("pad", "neutral")]
+            nd.pad_value = float(f.get("pad_value", 0.0))
         elif op == "until":
             nd.op = O_UNTIL
             kids = [self._emit(f["left"]), self._emit(f["right"])]
-            nd.a = int(f.get("a", 0))
-            b = f.get("b")
-            nd.b = -1 if b is None else int(b)
-            if nd.a < 0 or (nd.b >= 0 and nd.b < nd.a):
-                raise ValueError("bad interval")
+            if "mask" in f:
+                names = self._mask(nd, f["mask"])
+            else:
+                nd.a = int(f.get("a", 0))
+                b = f.get("b")
+                nd.b = -1 if b is None else int(b)
+                if nd.a < 0 or (nd.b >= 0 and nd.b < nd.a):
+                    raise ValueError("bad interval")
         else:
             raise ValueError("unknown op %r" % op)
         sm = f.get("smooth", False)

@@ -15,7 +15,8 @@ reduces them with numpy, as an independent check of the loop oracle in
   min over the stacked pair (S1, S2) and a max over i (S3).
 
 Smooth variants replace the reductions by logsumexp (Sec. III-C) with masked
-entries excluded; the smooth time mask (Sec. VI) enters as log-weights.
+entries excluded; the smooth time mask (Sec. VI) enters as log-weights, on
+the window offset (Eventually / Always) or on the Until index i.
 P (number of pad rows) is b: the largest offset a window can reach.  The
 paper pads by K = b - a + 1 rows, which is enough only when a <= 1 (as in
 its Example 1).
@@ -71,18 +72,42 @@ def window_op(s, a, b, kind="max", smooth=False, beta=10.0, pad="neutral", pad_v
     return sg * R
 
 
-def smooth_mask_op(s, a, b, c, eps, kind="max", smooth=True, beta=10.0):
-    """Eventually / Always with the smooth time mask of Sec. VI as weights."""
+def _smooth_mask(k, a, b, c, eps):
+    """Sec. VI smooth mask at offsets k (before the clamp at 0)."""
+    sig = lambda z: 1.0 / (1.0 + np.exp(-z))
+    return sig(c * (k - a)) - (0.0 if b is None else sig(c * (k - b))) - eps
+
+
+def _mask_support_end(a, b, c, eps):
+    """Largest offset with a positive weight (bounded masks)."""
+    k, last = 0, -1
+    while True:
+        if _smooth_mask(float(k), a, b, c, eps) > 0:
+            last = k
+        elif k > b:
+            return last
+        k += 1
+
+
+def smooth_mask_op(s, a, b, c, eps, kind="max", smooth=True, beta=10.0, pad="neutral", pad_value=0.0):
+    """Eventually / Always with the smooth time mask of Sec. VI as weights.
+
+    With pad 'last' / 'const' (bounded masks) the unrolled signal of Step 1
+    gets as many pad rows as the mask support reaches, and every padded entry
+    keeps the weight of its offset.
+    """
     s = np.asarray(s, dtype=np.float64)
     L = len(s)
-    j = np.arange(L)[:, None]
+    padded = pad != "neutral" and b is not None
+    P = max(0, _mask_support_end(a, b, c, eps)) if padded else 0
+    fill = {"last": s[-1], "const": pad_value, "neutral": 0.0}[pad]
+    j = np.arange(L + P)[:, None]
     t = np.arange(L)[None, :]
     k = (j - t).astype(np.float64)
-    sig = lambda z: 1.0 / (1.0 + np.exp(-z))
-    w = sig(c * (k - a)) - (0.0 if b is None else sig(c * (k - b))) - eps
+    w = _smooth_mask(k, a, b, c, eps)
     w = np.where((j >= t) & (w > 0), w, 0.0)               # subsignal mask and clamp
     sg = 1.0 if kind == "max" else -1.0
-    V = sg * np.repeat(s[:, None], L, axis=1)
+    V = sg * unroll(s, P, fill)
     keep = w > 0
     if not smooth:
         R = np.where(keep, V, -BIG).max(axis=0)
@@ -128,6 +153,39 @@ def until_op(phi, psi, a, b, smooth=False, beta=10.0):
         return S2.max(axis=1)
     S2 = -_lse(-beta * S1, axis=0) / beta
     Z = np.where(valid, beta * S2, -np.inf)
+    out = _lse(Z, axis=1) / beta
+    return np.where(valid.any(axis=1), out, -BIG)
+
+
+def smooth_mask_until_op(phi, psi, a, b, c, eps, smooth=True, beta=10.0):
+    """phi U psi with the smooth time mask of Sec. VI on the Until index i:
+    the 3-D unroll of Sec. IV-C over every i, the S3 reduction weighted by
+    w_i (kept where w_i > 0)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    psi = np.asarray(psi, dtype=np.float64)
+    L = len(phi)
+    P = L - 1
+    Sphi = unroll(phi, P, BIG)
+    Spsi = unroll(psi, P, -BIG)
+    I = np.arange(L)
+    S1 = np.empty((2, L, L))
+    for i in I:
+        kphi = masks(L, P, 0, i)
+        kpsi = masks(L, P, i, i)
+        if not smooth:
+            S1[0, :, i] = np.where(kphi, Sphi, BIG).min(axis=0)
+            S1[1, :, i] = np.where(kpsi, Spsi, BIG).min(axis=0)
+        else:
+            S1[0, :, i] = _smin_cols(Sphi, kphi, beta)
+            S1[1, :, i] = _smin_cols(Spsi, kpsi, beta)
+    w = _smooth_mask(I.astype(np.float64), a, b, c, eps)
+    valid = np.array([[t + i <= L - 1 and w[i] > 0 for i in I] for t in range(L)])
+    if not smooth:
+        S2 = np.where(valid, S1.min(axis=0), -BIG)
+        return S2.max(axis=1)
+    S2 = -_lse(-beta * S1, axis=0) / beta
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Z = np.where(valid, beta * S2 + np.log(np.where(w > 0, w, 1.0))[None, :], -np.inf)
     out = _lse(Z, axis=1) / beta
     return np.where(valid.any(axis=1), out, -BIG)
 

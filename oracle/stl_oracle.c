@@ -26,7 +26,13 @@
  *     empty window gives -rho_pad for max-type and +rho_pad for min-type
  *     operators.  LAST: positions past the end read u[L-1] (each counts once
  *     in a smooth sum).  CONST: they read pad_value.  Unbounded windows and
- *     Until always clip (NEUTRAL).
+ *     Until always clip (NEUTRAL).  On a window with a bounded smooth mask,
+ *     LAST / CONST give every offset k of the mask support with t+k past
+ *     the end one pad copy of weight w_k (the support ends where w_k drops
+ *     to zero, which it does past b for eps > 0).
+ *   - a smooth mask on Until weights the outer index i (the psi index, the
+ *     one the interval [a,b] constrains); the running smooth min of phi over
+ *     [0,i] is not weighted.  The hard variant keeps {i : w_i > 0}.
  *   - smooth operators use beta (= 1/temperature) inside the exponent:
  *     smax(V) = (1/beta) log sum exp(beta v), smin(V) = -smax(-V).
  *     smooth = 2 selects the softmax-weighted form of Sec. III-C instead,
@@ -113,7 +119,7 @@ static double orient(int op)
 }
 
 /* One window element: value (already oriented), weight, gradient target. */
-typedef struct { double v, w; int src; } welem;
+typedef struct { double v, w; int src, off; } welem;   /* off: mask offset k */
 
 /* Collect the window of a temporal node at time t (oriented values). */
 static int gather_window(const onode *nd, const double *u, int L, int t, double sg,
@@ -123,18 +129,33 @@ static int gather_window(const onode *nd, const double *u, int L, int t, double 
     if (nd->masked) {
         for (int k = 0; t + k < L; ++k) {
             double w = wtab[k];
-            if (w > 0) { out[n].v = sg * u[t + k]; out[n].w = w; out[n].src = t + k; ++n; }
+            if (w > 0) { out[n].v = sg * u[t + k]; out[n].w = w; out[n].src = t + k; out[n].off = k; ++n; }
+        }
+        if (nd->pad != P_NEUTRAL && !nd->mb_inf) {
+            /* offsets past the signal end: one pad copy per support offset */
+            for (int k = L - t; ; ++k) {
+                double w = mask_weight(nd, k);
+                if (w > 0) {
+                    out[n].v = sg * (nd->pad == P_LAST ? u[L - 1] : nd->pad_value);
+                    out[n].w = w;
+                    out[n].src = nd->pad == P_LAST ? L - 1 : -1;
+                    out[n].off = k;
+                    ++n;
+                } else if ((double)k > nd->mb) {
+                    break;
+                }
+            }
         }
         return n;
     }
     int ihi = nd->b < 0 ? (L - 1 - t) : nd->b;
     for (int i = nd->a; i <= ihi; ++i) {
         int j = t + i;
-        if (j <= L - 1) { out[n].v = sg * u[j]; out[n].w = 1; out[n].src = j; ++n; }
+        if (j <= L - 1) { out[n].v = sg * u[j]; out[n].w = 1; out[n].src = j; out[n].off = i; ++n; }
         else if (nd->b >= 0 && nd->pad == P_LAST) {
-            out[n].v = sg * u[L - 1]; out[n].w = 1; out[n].src = L - 1; ++n;
+            out[n].v = sg * u[L - 1]; out[n].w = 1; out[n].src = L - 1; out[n].off = i; ++n;
         } else if (nd->b >= 0 && nd->pad == P_CONST) {
-            out[n].v = sg * nd->pad_value; out[n].w = 1; out[n].src = -1; ++n;
+            out[n].v = sg * nd->pad_value; out[n].w = 1; out[n].src = -1; out[n].off = i; ++n;
         }
     }
     return n;
@@ -251,21 +272,23 @@ static void fwd_node(const onode *nodes, int idx, const double *x, int L, int D,
         const double *phi = tr + (size_t)nd->ch[0] * L;
         const double *psi = tr + (size_t)nd->ch[1] * L;
         double beta = nd->beta;
+        if (nd->masked) for (int k = 0; k < L; ++k) wtab[k] = mask_weight(nd, k);
         for (int t = 0; t < L; ++t) {
-            int imax = nd->b < 0 ? L - 1 - t : (nd->b < L - 1 - t ? nd->b : L - 1 - t);
-            if (nd->a > imax) { out[t] = -rho_pad; continue; }
+            /* a masked Until walks every i to the end and keeps those with w_i > 0 */
+            int imax = (nd->b < 0 || nd->masked) ? L - 1 - t : (nd->b < L - 1 - t ? nd->b : L - 1 - t);
+            if (!nd->masked && nd->a > imax) { out[t] = -rho_pad; continue; }
             if (!nd->smooth) {
                 double R = 0, best = 0;
                 int have = 0;
                 for (int i = 0; i <= imax; ++i) {
                     double f = phi[t + i];
                     if (i == 0 || f < R) R = f;              /* running min over k in [0,i] */
-                    if (i >= nd->a) {
+                    if (nd->masked ? wtab[i] > 0 : i >= nd->a) {
                         double v = (R <= psi[t + i]) ? R : psi[t + i];  /* min(R, psi) */
                         if (!have || v > best) { best = v; have = 1; }
                     }
                 }
-                out[t] = best;
+                out[t] = have ? best : -rho_pad;
             } else {
                 /* R_i = smin(phi_t..phi_{t+i}) via a max-shifted running sum of
                  * exp(-beta phi); v_i = smin(R_i, psi_{t+i}); out = smax_i v_i. */
@@ -278,15 +301,16 @@ static void fwd_node(const onode *nodes, int idx, const double *x, int L, int D,
                     else s += exp(beta * (q - mneg));
                     double R = -(mneg + log(s) / beta);
                     tmpR[i] = R;
-                    if (i >= nd->a) {
+                    if (nd->masked ? wtab[i] > 0 : i >= nd->a) {
                         double p = psi[t + i];
                         /* smin of the pair (R, psi) */
                         double lo = R < p ? R : p;
                         double v = lo - log(exp(-beta * (R - lo)) + exp(-beta * (p - lo))) / beta;
-                        buf[nv].v = v; buf[nv].w = 1; buf[nv].src = i; ++nv;
+                        buf[nv].v = v; buf[nv].w = nd->masked ? wtab[i] : 1; buf[nv].src = i; buf[nv].off = i;
+                        ++nv;
                     }
                 }
-                out[t] = wlse(buf, nv, beta);
+                out[t] = nv ? wlse(buf, nv, beta) : -rho_pad;
             }
         }
         break;
@@ -397,9 +421,12 @@ static void bwd_node(const onode *nodes, int idx, const double *x, int L, int D,
                 double e = exp(nd->beta * (buf[k].v - o));        /* d out / d (w_k e^{beta v}) * ... */
                 if (buf[k].src >= 0) gu[buf[k].src] += g[t] * buf[k].w * e;
                 if (nd->masked) {
-                    int off = buf[k].src - t;
-                    ga += dwa[off] * e;
-                    gbb += dwb[off] * e;
+                    int off = buf[k].off;
+                    double da, db;
+                    if (off < L) { da = dwa[off]; db = dwb[off]; }
+                    else mask_weight_grad(nd, off, &da, &db);   /* a pad copy past the end */
+                    ga += da * e;
+                    gbb += db * e;
                 }
             }
             if (nd->masked) {
@@ -415,51 +442,65 @@ static void bwd_node(const onode *nodes, int idx, const double *x, int L, int D,
         double *gphi = gb + (size_t)nd->ch[0] * L;
         double *gpsi = gb + (size_t)nd->ch[1] * L;
         double beta = nd->beta;
+        if (nd->masked)
+            for (int k = 0; k < L; ++k) { wtab[k] = mask_weight(nd, k); mask_weight_grad(nd, k, &dwa[k], &dwb[k]); }
         for (int t = 0; t < L; ++t) {
-            int imax = nd->b < 0 ? L - 1 - t : (nd->b < L - 1 - t ? nd->b : L - 1 - t);
-            if (nd->a > imax || g[t] == 0) continue;
+            int imax = (nd->b < 0 || nd->masked) ? L - 1 - t : (nd->b < L - 1 - t ? nd->b : L - 1 - t);
+            if ((!nd->masked && nd->a > imax) || g[t] == 0) continue;
             if (!nd->smooth) {
                 double R = 0, best = 0;
                 int kR = 0, have = 0, tgt_phi = 0, tgt = 0;
                 for (int i = 0; i <= imax; ++i) {
                     double f = phi[t + i];
                     if (i == 0 || f < R) { R = f; kR = i; }
-                    if (i >= nd->a) {
+                    if (nd->masked ? wtab[i] > 0 : i >= nd->a) {
                         int phiwin = R <= psi[t + i];
                         double v = phiwin ? R : psi[t + i];
                         if (!have || v > best) { best = v; have = 1; tgt_phi = phiwin; tgt = phiwin ? kR : i; }
                     }
                 }
+                if (!have) continue;                         /* empty window: constant output */
                 if (tgt_phi) gphi[t + tgt] += g[t]; else gpsi[t + tgt] += g[t];
                 continue;
             }
             /* forward recompute: R_i (running smin of phi) and v_i = smin(R_i, psi_{t+i}) */
             double mneg = 0, s = 0;
+            int nv = 0;
             for (int i = 0; i <= imax; ++i) {
                 double q = -phi[t + i];
                 if (i == 0) { mneg = q; s = 1; }
                 else if (q > mneg) { s = s * exp(beta * (mneg - q)) + 1; mneg = q; }
                 else s += exp(beta * (q - mneg));
                 tmpR[i] = -(mneg + log(s) / beta);
-                if (i >= nd->a) {
+                if (nd->masked ? wtab[i] > 0 : i >= nd->a) {
+                    ++nv;
                     double R = tmpR[i], p = psi[t + i];
                     double lo = R < p ? R : p;
                     tmpV[i] = lo - log(exp(-beta * (R - lo)) + exp(-beta * (p - lo))) / beta;
                 }
             }
+            if (nv == 0) continue;                           /* empty window: constant output */
             double o = out[t];
+            double ga = 0, gbb = 0;
             /* reverse sweep: R_i = smin2(R_{i-1}, phi_{t+i}) (Sec. IV-D: the
              * running smooth min equals the flat one) */
             for (int i = 0; i <= imax; ++i) tmpRb[i] = 0;
             for (int i = imax; i >= 0; --i) {
-                if (i >= nd->a) {
-                    double gv = g[t] * exp(beta * (tmpV[i] - o));            /* d out / d v_i */
+                if (nd->masked ? wtab[i] > 0 : i >= nd->a) {
+                    double e = exp(beta * (tmpV[i] - o));
+                    double gv = g[t] * (nd->masked ? wtab[i] : 1.0) * e;    /* d out / d v_i */
+                    if (nd->masked) { ga += dwa[i] * e; gbb += dwb[i] * e; }
                     tmpRb[i] += gv * exp(-beta * (tmpR[i] - tmpV[i]));       /* d v_i / d R_i */
                     gpsi[t + i] += gv * exp(-beta * (psi[t + i] - tmpV[i])); /* d v_i / d psi */
                 }
                 if (i == 0) { gphi[t] += tmpRb[0]; break; }
                 gphi[t + i] += tmpRb[i] * exp(-beta * (phi[t + i] - tmpR[i]));
                 tmpRb[i - 1] += tmpRb[i] * exp(-beta * (tmpR[i - 1] - tmpR[i]));
+            }
+            if (nd->masked) {
+                /* d out / d w_i = exp(beta (v_i - out)) / beta */
+                dpar[2 * idx + 0] += g[t] * ga / beta;
+                dpar[2 * idx + 1] += g[t] * gbb / beta;
             }
         }
         break;
@@ -479,11 +520,23 @@ typedef struct {
 static size_t window_cap(const onode *nodes, int n, int L)
 {
     size_t cap = (size_t)L + OMAXCH + 16;
-    for (int i = 0; i < n; ++i)
-        if ((nodes[i].op == O_EV || nodes[i].op == O_ALW) && !nodes[i].masked && nodes[i].b >= 0) {
-            size_t k = (size_t)(nodes[i].b - nodes[i].a + 1) + 16;
+    for (int i = 0; i < n; ++i) {
+        const onode *nd = &nodes[i];
+        if ((nd->op == O_EV || nd->op == O_ALW) && !nd->masked && nd->b >= 0) {
+            size_t k = (size_t)(nd->b - nd->a + 1) + 16;
             if (k > cap) cap = k;
         }
+        if ((nd->op == O_EV || nd->op == O_ALW) && nd->masked && nd->pad != P_NEUTRAL && !nd->mb_inf) {
+            /* pad copies: at most one per offset up to the end of the mask support */
+            int kend = 0;
+            for (int k = 0; ; ++k) {
+                if (mask_weight(nd, k) > 0) kend = k;
+                else if ((double)k > nd->mb) break;
+            }
+            size_t k = (size_t)L + (size_t)kend + 1 + 16;
+            if (k > cap) cap = k;
+        }
+    }
     return cap;
 }
 

@@ -537,3 +537,155 @@ def test_softmax_weighted_form(orc):
             xm = x.copy(); xm[0, j, 0] -= h
             fd[j] = ((orc.forward(spec, xp) - orc.forward(spec, xm)) * G).sum() / (2 * h)
         assert np.allclose(dx[0, :, 0], fd, rtol=1e-6, atol=1e-7)
+
+
+# --------------------------------------------------------------------------- masks on Until, pads on masks
+
+def _m(a, b, c, eps=1e-6):
+    return {"a": a, "b": b, "c": c, "eps": eps}
+
+
+@pytest.mark.parametrize("smooth", [False, True])
+def test_masked_until_matches_literal(orc, smooth):
+    """Smooth mask on the Until index (Sec. VI on the interval mask of
+    Sec. IV-C) against the literal 3-D unroll with weighted S3."""
+    rng = np.random.default_rng(35)
+    for L in (1, 4, 11, 23):
+        for (a, b, c, eps) in [(2.0, 7.0, 1.0, 1e-6), (0.4, 3.6, 3.0, 1e-3), (4.0, None, 0.8, 1e-6),
+                               (1.5, 2.5, 6.0, 1e-2)]:
+            phi, psi = rng.normal(size=L), rng.normal(size=L)
+            x = np.stack([phi, psi], -1)[None]
+            spec = {"op": "until", "smooth": smooth, "beta": 2.5, "mask": _m(a, b, c, eps),
+                    "left": {"op": "linear", "w": [1, 0], "c": 0},
+                    "right": {"op": "linear", "w": [0, 1], "c": 0}}
+            got = orc.forward(spec, x, rho_pad=LM.BIG)[0]
+            ref = LM.smooth_mask_until_op(phi, psi, a, b, c, eps, smooth, 2.5)
+            np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-11)
+
+
+def test_masked_until_sharp_mask_is_the_integer_interval(orc):
+    """A steep mask with bounds half-way between integers and a small eps has
+    support exactly {3..6} with weights 1 - 1e-9, so it matches the Until over
+    the integer interval [3, 6]: exactly for the hard form, to log(1-1e-9)/beta
+    for the smooth one, and with the same dx."""
+    rng = np.random.default_rng(31)
+    L = 30
+    x = rng.normal(size=(2, L, 2))
+    G = rng.normal(size=(2, L))
+    phi = {"op": "linear", "w": [1.0, 0.3], "c": -0.8}
+    psi = {"op": "linear", "w": [-0.4, 1.0], "c": 0.1}
+    for kw in ({}, dict(smooth=True, beta=3.0)):
+        um = dict({"op": "until", "left": phi, "right": psi, "mask": _m(2.5, 6.5, 60.0, 1e-9)}, **kw)
+        ui = dict({"op": "until", "left": phi, "right": psi, "a": 3, "b": 6}, **kw)
+        rm, ri = orc.forward(um, x), orc.forward(ui, x)
+        if kw:
+            assert np.abs(rm - ri).max() <= 1e-9
+        else:
+            assert np.array_equal(rm, ri)
+        dm, _ = orc.backward(um, x, G)
+        di, _ = orc.backward(ui, x, G)
+        assert np.abs(dm - di).max() <= 1e-12
+
+
+def test_masked_until_with_true_left_is_masked_eventually(orc):
+    """phi = True keeps every running min of phi at rho_max, so the inner min
+    picks psi and the masked Until is the masked Eventually of psi: values,
+    dx and the mask-bound gradients agree (hard and smooth)."""
+    rng = np.random.default_rng(32)
+    L = 60
+    x = np.cumsum(rng.normal(size=(3, L, 2)) * 0.3, axis=1)
+    G = rng.normal(size=(3, L))
+    psi = {"op": "linear", "w": [1.0, -0.5], "c": 0.2}
+    params = {"a": 4.3, "b": 17.8}
+    m = _m("a", "b", 1.5)
+    for kw in ({}, dict(smooth=True, beta=2.5)):
+        u = dict({"op": "until", "left": {"op": "true"}, "right": psi, "mask": m}, **kw)
+        e = dict({"op": "eventually", "child": psi, "mask": m}, **kw)
+        ru, re = orc.forward(u, x, params=params), orc.forward(e, x, params=params)
+        assert np.abs(ru - re).max() <= 1e-12 * (1 + np.abs(re).max())
+        du, pu = orc.backward(u, x, G, params=params)
+        de, pe = orc.backward(e, x, G, params=params)
+        assert np.abs(du - de).max() <= 1e-10
+        for k in ("a", "b"):
+            assert pu[k] == pytest.approx(pe[k], rel=1e-10, abs=1e-12)
+
+
+def test_fd_masked_until_gradients(orc):
+    rng = np.random.default_rng(33)
+    x = np.cumsum(rng.normal(size=(2, 50, 2)) * 0.2, axis=1)
+    G = rng.normal(size=(2, 50))
+    spec = {"op": "until", "smooth": True, "beta": 3.0, "mask": _m("a", "b", 1.2),
+            "left": {"op": "linear", "w": [1.0, 0.2], "c": -1.0},
+            "right": {"op": "linear", "w": [0.3, 1.0], "c": 0.0}}
+    _fd_check(orc, spec, x, G, params={"a": 3.4, "b": 15.2}, names=("a", "b"))
+    spec["mask"] = _m("a", None, 2.0)
+    _fd_check(orc, spec, x, G, params={"a": 6.1}, names=("a",))
+
+
+@pytest.mark.parametrize("smooth", [False, True])
+@pytest.mark.parametrize("kind", ["max", "min"])
+def test_mask_pads_match_literal(orc, smooth, kind):
+    """LAST / CONST on a bounded smooth mask against the literal unroll with
+    weighted pad rows."""
+    rng = np.random.default_rng(36)
+    for L in (1, 5, 17, 40):
+        for (a, b, c, eps) in [(2.0, 9.0, 1.0, 1e-6), (0.3, 3.7, 4.0, 1e-3), (10.5, 12.5, 2.0, 1e-2),
+                               (30.0, 45.0, 1.5, 1e-6)]:
+            s = rng.normal(size=L)
+            for pad in ("last", "const"):
+                spec = {"op": "eventually" if kind == "max" else "always", "smooth": smooth, "beta": 4.0,
+                        "mask": _m(a, b, c, eps), "child": S, "pad": pad, "pad_value": 0.4}
+                got = orc.forward(spec, sig1(s), rho_pad=LM.BIG)[0]
+                ref = LM.smooth_mask_op(s, a, b, c, eps, kind, smooth, 4.0, pad=pad, pad_value=0.4)
+                np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("pad", ["last", "const"])
+@pytest.mark.parametrize("kind", ["eventually", "always"])
+def test_mask_pad_equals_extended_signal(orc, pad, kind):
+    """LAST / CONST on a bounded smooth mask equals the NEUTRAL mask on the
+    signal extended past its end by copies of its last sample (or of the pad
+    value) far enough to cover the mask support; the adjoint of the last
+    sample collects those of its copies, and the mask-bound gradients agree."""
+    rng = np.random.default_rng(34)
+    L, ext = 40, 80
+    u = rng.normal(size=L)
+    pv = 0.35
+    ue = np.concatenate([u, np.full(ext, u[-1] if pad == "last" else pv)])
+    params = {"a": 6.2, "b": 21.5}
+    G = rng.normal(size=L)
+    Ge = np.concatenate([G, np.zeros(ext)])
+    for kw in ({}, dict(smooth=True, beta=2.0)):
+        m = _m("a", "b", 1.0)
+        sp = dict({"op": kind, "child": S, "mask": m, "pad": pad, "pad_value": pv}, **kw)
+        sn = dict({"op": kind, "child": S, "mask": m}, **kw)
+        r = orc.forward(sp, sig1(u), params=params)[0]
+        re = orc.forward(sn, sig1(ue), params=params)[0][:L]
+        assert np.abs(r - re).max() <= 1e-12
+        d, p = orc.backward(sp, sig1(u), G.reshape(1, L), params=params)
+        de, pe = orc.backward(sn, sig1(ue), Ge.reshape(1, -1), params=params)
+        de = de.reshape(-1)
+        want = de[:L].copy()
+        if pad == "last":
+            want[L - 1] += de[L:].sum()
+        assert np.abs(d.reshape(-1) - want).max() <= 1e-11
+        for k in ("a", "b"):
+            assert p[k] == pytest.approx(pe[k], rel=1e-10, abs=1e-12)
+    # a sharp mask with a small eps is the integer window [7, 21] with the same pad
+    sharp = _m(6.5, 21.5, 60.0, 1e-9)
+    for kw in ({}, dict(smooth=True, beta=2.0)):
+        r = orc.forward(dict({"op": kind, "child": S, "mask": sharp, "pad": pad, "pad_value": pv}, **kw),
+                        sig1(u))[0]
+        ri = orc.forward(dict({"op": kind, "child": S, "a": 7, "b": 21, "pad": pad, "pad_value": pv}, **kw),
+                         sig1(u))[0]
+        assert np.abs(r - ri).max() <= (1e-9 if kw else 0.0)
+
+
+def test_fd_mask_pad_gradients(orc):
+    rng = np.random.default_rng(37)
+    x = np.cumsum(rng.normal(size=(2, 45, 2)) * 0.2, axis=1)
+    G = rng.normal(size=(2, 45))
+    for pad in ("last", "const"):
+        spec = {"op": "always", "smooth": True, "beta": 3.0, "mask": _m("a", "b", 0.8), "pad": pad,
+                "pad_value": -0.2, "child": {"op": "linear", "w": [1.0, 0.5], "c": 0.1}}
+        _fd_check(orc, spec, x, G, params={"a": 12.3, "b": 38.6}, names=("a", "b"))
