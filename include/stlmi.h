@@ -27,7 +27,12 @@
  *    w_k = max(sig(c(k-a)) - sig(c(k-b)) - eps, 0), k = offset >= 0, with
  *    a, b, c, eps read from the device parameter buffer at run time (so they
  *    can be learned or annealed without recompiling the plan).  Their hard
- *    variant takes max/min over the support {k : w_k > 0}.
+ *    variant takes max/min over the support {k : w_k > 0}.  On Until the
+ *    mask weights the Until index i (the psi index) in the outer smooth max;
+ *    the running min of phi over [0, i] is unweighted.  On a bounded mask,
+ *    STL_PAD_LAST / STL_PAD_CONST give every support offset past the end one
+ *    pad copy weighted by w_k (offsets more than 65536 past the end are not
+ *    visited; w_k is below eps there unless c is tiny).
  *  - Hard min/max break ties toward the lowest time index (and the lowest
  *    child index for n-ary And/Or; the phi side inside Until's min).
  *
@@ -101,7 +106,7 @@ typedef struct {
     int32_t mask_unbounded;  /* smooth mask with b = +inf (params[mask_param+1] ignored) */
     int32_t beta_param;      /* smooth nodes: index of beta in params; ignored when hard */
     int32_t pred;            /* PRED_*: index into the predicate array */
-    int32_t pad;             /* stl_pad (integer-interval EVENTUALLY / ALWAYS only) */
+    int32_t pad;             /* stl_pad (EVENTUALLY / ALWAYS; ignored by unbounded windows) */
     float pad_value;         /* STL_PAD_CONST value */
 } stl_node;
 

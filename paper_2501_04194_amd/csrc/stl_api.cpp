@@ -214,6 +214,10 @@ stl_status emit(Builder& B, int id, int depth, int* out)
             I.mslot = (int8_t)B.mask_params.size();
             B.mask_params.push_back(n.mask_param);
             if (n.mask_unbounded) I.flags |= F_MASK_UNB;
+            // pads apply to bounded masks (an unbounded one reaches the end)
+            if (n.pad < 0 || n.pad > 2) return fail(STL_E_ARG, "node %d: bad pad policy", id);
+            I.pad = (int8_t)(n.mask_unbounded ? STL_PAD_NEUTRAL : n.pad);
+            std::memcpy(&I.a, &n.pad_value, sizeof(float));
         } else {
             I.kind = K_WIN;
             if (n.a < 0 || (n.b >= 0 && n.b < n.a) || n.b < -1)
@@ -229,13 +233,27 @@ stl_status emit(Builder& B, int id, int depth, int* out)
         break;
     case STL_UNTIL:
         I.kind = K_UNTIL;
-        if (n.mask_param >= 0) return fail(STL_E_UNSUPPORTED, "node %d: smooth masks on Until are not supported", id);
+        B.has_until = true;
+        if (n.mask_param >= 0) {
+            // smooth mask on the Until index: the kernels walk its support,
+            // which can reach the end of the trajectory
+            if (n.mask_param + 3 >= B.n_params) return fail(STL_E_ARG, "node %d: mask_param + 3 >= n_params", id);
+            if ((int)B.mask_params.size() >= MAX_MASKS) return fail(STL_E_UNSUPPORTED, "too many smooth masks");
+            I.mask = (int8_t)n.mask_param;
+            I.mslot = (int8_t)B.mask_params.size();
+            B.mask_params.push_back(n.mask_param);
+            if (n.mask_unbounded) I.flags |= F_MASK_UNB;
+            I.a = 0;
+            I.b = -1;
+            I.flags |= F_UNB;
+            B.max_until_b = 1 << 30;
+            break;
+        }
         if (n.a < 0 || (n.b >= 0 && n.b < n.a) || n.b < -1)
             return fail(STL_E_FORMULA, "node %d: bad interval [%d, %d]", id, n.a, n.b);
         I.a = n.a;
         I.b = n.b;
         if (n.b < 0) I.flags |= F_UNB;
-        B.has_until = true;
         B.max_until_b = std::max(B.max_until_b, n.b < 0 ? (1 << 30) : n.b);
         break;
     default:
@@ -327,6 +345,9 @@ extern "C" stl_status stl_compile(const stl_node* nodes, int32_t n_nodes, const 
     if (s != STL_OK) return s;
     const int n = (int)B.ins.size();
     if (n > MAX_INSTR) return fail(STL_E_UNSUPPORTED, "plan has %d instructions (max %d)", n, MAX_INSTR);
+    if ((int)B.coef.size() > MAX_COEF)
+        return fail(STL_E_UNSUPPORTED, "predicate and pad coefficients need %d floats (max %d)", (int)B.coef.size(),
+                    MAX_COEF);
 
     // consumers
     std::vector<int> parent(n, -1);
@@ -400,7 +421,7 @@ extern "C" stl_status stl_compile(const stl_node* nodes, int32_t n_nodes, const 
     {
         auto is_fmask = [&](int k) {
             const Instr& I = B.ins[k];
-            return I.kind == K_MASK && (I.flags & F_SMOOTH) && B.kids[k].size() == 1 &&
+            return I.kind == K_MASK && (I.flags & F_SMOOTH) && I.pad == STL_PAD_NEUTRAL && B.kids[k].size() == 1 &&
                    B.ins[B.kids[k][0]].kind == K_LIN;
         };
         FusedDesc& F = dp.fused;

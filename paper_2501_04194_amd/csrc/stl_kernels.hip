@@ -681,19 +681,121 @@ DEV MaskInfo mask_info(const float* params, const Instr& I, int L, SH& sh, float
     return mi;
 }
 
+// pad value of a smooth-mask node (carried in the instruction: kernels read
+// it without indexing the plan's coefficient table)
+DEV float mask_padv(const Instr& I) { return __int_as_float(I.a); }
+
 DEV MaskInfo mask_weights(const Env& e, const Instr& I, float* w, float* dwa, float* dwb)
 {
     return mask_info(e.params, I, e.L, *e.sh, w, dwa, dwb);
+}
+
+// deterministic work-group sum of one double per thread
+DEV double wg_sum_d(double v, Shared& sh)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    sh.scan[tid] = v;
+    __syncthreads();
+    for (int s = nt >> 1; s > 0; s >>= 1) {
+        if (tid < s) sh.scan[tid] += sh.scan[tid + s];
+        __syncthreads();
+    }
+    const double r = sh.scan[0];
+    __syncthreads();
+    return r;
+}
+
+// Offsets past the signal end, for the LAST / CONST pads of a bounded smooth
+// mask: each offset k >= L of the support contributes one pad copy with
+// weight w_k.  Past b, w_k <= sig(-c(k - b)) < e^{-c(k - b)}, which is below
+// eps (and w_k clamps to 0) from k = b + ln(1/eps)/c on; in fp32 the sigmoid
+// itself is 0 once c(k - b) > 89.  The walk stops there, and never runs more
+// than MASK_TAIL_MAX offsets past the end.
+constexpr int MASK_TAIL_MAX = 65536;
+
+struct MaskTail {
+    int lo, hi;          // support offsets >= L (lo > hi: none)
+    double s, sa, sb;    // sums of w_k, d w_k/da, d w_k/db over them
+};
+
+DEV MaskTail mask_tail(const Env& e, const Instr& I, bool grads)
+{
+    const int L = e.L;
+    const MaskP mp = mask_params(e.params + I.mask, false);
+    int kend = -1;
+    if (mp.c > 0.f && mp.b == mp.b) {
+        const float span = fminf(logf(1.f / fmaxf(mp.eps, 1e-38f)), 89.f) / mp.c + 2.f;
+        const float ke = fminf(mp.b + span, (float)L + (float)MASK_TAIL_MAX);
+        kend = ke >= (float)L ? (int)ke : -1;
+    }
+    int* si = e.sh->ints;
+    if (threadIdx.x == 0) { si[5] = INT_MAX; si[6] = -1; }
+    __syncthreads();
+    int lo = INT_MAX, hi = -1;
+    double s = 0.0, sa = 0.0, sb = 0.0;
+    for (int k = L + (int)threadIdx.x; k <= kend; k += blockDim.x) {
+        float da = 0.f, db = 0.f;
+        const float wk = mask_wk(mp, k, grads ? &da : nullptr, &db);
+        if (wk > 0.f) {
+            lo = min(lo, k);
+            hi = max(hi, k);
+            s += wk;
+            sa += da;
+            sb += db;
+        }
+    }
+    atomicMin(&si[5], lo);
+    atomicMax(&si[6], hi);
+    __syncthreads();
+    MaskTail mt;
+    mt.lo = si[5];
+    mt.hi = si[6];
+    mt.s = wg_sum_d(s, *e.sh);
+    mt.sa = grads ? wg_sum_d(sa, *e.sh) : 0.0;
+    mt.sb = grads ? wg_sum_d(sb, *e.sh) : 0.0;
+    return mt;
+}
+
+// out[t] = tail + sum_{k=L-t}^{L-1} v[k] for t in [0, L): the part of an
+// offset table v (zero outside the mask support) that lies past the signal
+// end for the output at t, plus the tail beyond the table.  fp64 sums: one
+// contiguous chunk per thread, an exclusive suffix scan over the lanes and
+// the totals of the later waves.
+DEV void tail_weights(const float* v, float* out, int L, double tail, Shared& sh)
+{
+    const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nw = (nt + 63) >> 6;
+    const int ch = (L + nt - 1) / nt;
+    const int k0 = min(L, tid * ch), k1 = min(L, k0 + ch);
+    double c = 0.0;
+    for (int k = k0; k < k1; ++k) c += (double)v[k];
+    double r = c;                               // inclusive suffix over the lanes
+    for (int d = 1; d < 64; d <<= 1) {
+        const double o = __shfl_down(r, d);
+        if (lane + d < 64) r += o;
+    }
+    double ex = __shfl_down(r, 1);              // lanes after this one
+    if (lane == 63) ex = 0.0;
+    if (lane == 0) sh.scan[wv] = r;
+    __syncthreads();
+    double acc = tail + ex;
+    for (int q = wv + 1; q < nw; ++q) acc += sh.scan[q];
+    for (int k = k1 - 1; k >= k0; --k) {
+        acc += (double)v[k];
+        if (k >= 1) out[L - k] = (float)acc;
+    }
+    if (tid == 0) out[0] = (float)tail;
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ until
 
 // Hard Until, one thread per output t: running min of phi over [t, t+i],
 // max over i in [a, b] of min(running min, psi_{t+i}); phi wins ties.
-DEV void until_hard(const Env& e, const Instr& I, const float* phi, const float* psi, float* out,
+DEV void until_hard(const Env& e, int a, int b, const float* phi, const float* psi, float* out,
                     const float* g, float* gphi, float* gpsi)
 {
-    const int L = e.L, a = I.a, b = I.b;
+    const int L = e.L;
     const float rho_pad = e.P->rho_pad;
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
@@ -725,12 +827,13 @@ DEV void until_hard(const Env& e, const Instr& I, const float* phi, const float*
 // Smooth Until forward, one thread per output t:
 //   P_i = sum_{k<=i} 2^{-z_phi(t+k)}   (running scaled sum: smooth min of phi)
 //   Y_i = 1 / (P_i + 2^{-z_psi(t+i)})  (= exp(beta * smin(R_i, psi_{t+i})))
-//   out = log2(sum_{i in [a,b]} Y_i) / (beta log2 e)
-// Ephi / Epsi hold the leaves 2^{-z}.  Returns Z (scaled) through Zout when given.
-DEV void until_smooth_fwd(const Env& e, const Instr& I, const SP* Ephi, const SP* Epsi, float* out,
-                          float bl)
+//   out = log2(sum_{i in [a,b]} w_i Y_i) / (beta log2 e)
+// Ephi / Epsi hold the leaves 2^{-z}; w (smooth mask weights by offset i,
+// Sec. VI) is null for the 0/1 interval.
+DEV void until_smooth_fwd(const Env& e, int a, int b, const float* w, const SP* Ephi, const SP* Epsi,
+                          float* out, float bl)
 {
-    const int L = e.L, a = I.a, b = I.b;
+    const int L = e.L;
     const float rho_pad = e.P->rho_pad;
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
@@ -740,7 +843,7 @@ DEV void until_smooth_fwd(const Env& e, const Instr& I, const SP* Ephi, const SP
             P = sp_add(P, Ephi[t + i]);
             if (i >= a) {
                 SP Dn = sp_add(P, Epsi[t + i]);
-                Z = sp_add(Z, SP{1.f / Dn.s, -Dn.r});
+                Z = sp_add(Z, SP{(w ? w[i] : 1.f) / Dn.s, -Dn.r});
             }
         }
         out[t] = sp_log2(Z) / bl;
@@ -748,17 +851,20 @@ DEV void until_smooth_fwd(const Env& e, const Instr& I, const SP* Ephi, const SP
 }
 
 constexpr int UCK = 16;   // checkpoint spacing of the smooth Until adjoint
+constexpr int UCK_UNIT = 7;   // scratch unit where its checkpoints start (units 4-6: mask tables)
 
 // Smooth Until adjoint (checkpointed reverse sweep per output t):
-//   d out / d psi_{t+i} = Y_i^2 Q_i / Z,  Q_i = 2^{-z_psi(t+i)}
-//   d out / d phi_{t+k} = e_k / Z * sum_{i >= max(k,a)} Y_i^2,  e_k = 2^{-z_phi(t+k)}
+//   d out / d psi_{t+i} = w_i Y_i^2 Q_i / Z,  Q_i = 2^{-z_psi(t+i)}
+//   d out / d phi_{t+k} = e_k / Z * sum_{i >= max(k,a)} w_i Y_i^2,  e_k = 2^{-z_phi(t+k)}
+//   d out / d w_i = Y_i / (beta Z)   (summed against d w/da, d w/db into pa, pb)
 // Pass 1 recomputes Z and stores P every UCK steps; pass 2 walks the
 // checkpoint blocks backward, recomputing P inside each block, and adds the
 // contributions to the adjoint slots with LDS atomics.
-DEV void until_smooth_adj(const Env& e, const Instr& I, const SP* Ephi, const SP* Epsi, const float* g,
-                          float* gphi, float* gpsi, SP* ck, int ncks)
+DEV void until_smooth_adj(const Env& e, int a, int b, const float* w, const float* dwa, const float* dwb,
+                          const SP* Ephi, const SP* Epsi, const float* g, float* gphi, float* gpsi, SP* ck,
+                          int ncks, float& pa, float& pb)
 {
-    const int L = e.L, a = I.a, b = I.b;
+    const int L = e.L;
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
         const float gt = g[t];
@@ -770,11 +876,11 @@ DEV void until_smooth_adj(const Env& e, const Instr& I, const SP* Ephi, const SP
             P = sp_add(P, Ephi[t + i]);
             if (i >= a) {
                 SP Dn = sp_add(P, Epsi[t + i]);
-                Z = sp_add(Z, SP{1.f / Dn.s, -Dn.r});
+                Z = sp_add(Z, SP{(w ? w[i] : 1.f) / Dn.s, -Dn.r});
             }
         }
         const float gz = gt / Z.s;          // G / Z = gz * 2^{-Z.r}
-        SP A = sp_zero();                   // suffix sum of Y_i^2
+        SP A = sp_zero();                   // suffix sum of w_i Y_i^2
         for (int blk = imax / UCK; blk >= 0; --blk) {
             const int i0 = blk * UCK, i1 = min(imax, i0 + UCK - 1);
             SP Ps[UCK];
@@ -792,10 +898,15 @@ DEV void until_smooth_adj(const Env& e, const Instr& I, const SP* Ephi, const SP
                     const SP Q = Epsi[t + i];
                     const SP Dn = sp_add(Ps[q], Q);
                     const float y = 1.f / Dn.s;       // Y = y * 2^{-Dn.r}
-                    const SP Y2{y * y, -2 * Dn.r};
+                    const SP Y2{(w ? w[i] : 1.f) * y * y, -2 * Dn.r};
                     A = sp_add(A, Y2);
-                    // psi: gz * Y^2 * Q  (exponent -Z.r - 2 Dn.r + Q.r)
+                    // psi: gz * w Y^2 * Q  (exponent -Z.r - 2 Dn.r + Q.r)
                     atomicAdd(&gpsi[t + i], ldexpf(gz * Y2.s * Q.s, clampe((long long)Y2.r + Q.r - Z.r)));
+                    if (w) {
+                        const int ex = clampe(-(long long)Dn.r - Z.r);
+                        pa += ldexpf(gz * dwa[i] * y, ex);
+                        pb += ldexpf(gz * dwb[i] * y, ex);
+                    }
                 }
                 const SP E = Ephi[t + i];
                 atomicAdd(&gphi[t + i], ldexpf(gz * A.s * E.s, clampe((long long)A.r + E.r - Z.r)));
@@ -886,8 +997,8 @@ DEV bool in_lds(const void* p)
 // Z = sum_{i=a}^{imax} 1 / (P_i + q_i), P_i = sum_{k<=i} p_k, over the terms of
 // one output.  The terms are read eight at a time (independent loads ahead of
 // the dependent sums); the additions keep the plain sequential order.
-template <class DP>
-DEV double until_z(DP ep, DP eq, int a, int imax)
+template <bool MW, class DP>
+DEV double until_z(DP ep, DP eq, int a, int imax, const float* w)
 {
     double P = 0.0, Z = 0.0;
     int i = 0;
@@ -909,27 +1020,29 @@ DEV double until_z(DP ep, DP eq, int a, int imax)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             P += v[k];
-            Z += rcpd(P + q[k]);
+            const double y = rcpd(P + q[k]);
+            Z += MW ? (double)w[i + k] * y : y;
         }
     }
     for (; i <= imax; ++i) {
         P += ep[i];
-        Z += rcpd(P + eq[i]);
+        const double y = rcpd(P + eq[i]);
+        Z += MW ? (double)w[i] * y : y;
     }
     return Z;
 }
 
 // Forward on the fp64 terms: the same sums as until_smooth_fwd, with
 // Y_i = 2^{-M} / (P_i + Q_i) in true units, so log2 Z_true = log2 Z - M.
-template <class DP>
-DEV void until_fwd_d(const Env& e, const Instr& I, DP Ep, DP Eq, float* out, float bl, int M)
+template <bool MW, class DP>
+DEV void until_fwd_d(const Env& e, int a, int b, const float* w, DP Ep, DP Eq, float* out, float bl, int M)
 {
-    const int L = e.L, a = I.a, b = I.b;
+    const int L = e.L;
     const float rho_pad = e.P->rho_pad;
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
         if (a > imax) { out[t] = -rho_pad; continue; }
-        const double Z = until_z(Ep + t, Eq + t, a, imax);
+        const double Z = until_z<MW>(Ep + t, Eq + t, a, imax, w);
         out[t] = (float)(log2_minus(Z, M) / (double)bl);
     }
 }
@@ -950,11 +1063,14 @@ DEV float lane_shr1(float v)
 // accumulator per lane for these positions and moves them up one lane per
 // step.  The position leaving lane 63 is complete for this wave and is added
 // to the adjoint slot (one lane, one atomic); the rest are added at the end.
-template <class DP, class CP, class FP>
-DEV void until_adj_d(const Env& e, const Instr& I, DP Ep, DP Eq, const float* g, FP gphi, FP gpsi, CP ck,
-                     int ncks)
+// With smooth mask weights (MW) each term carries w_i: Z = sum w_i Y_i, A
+// sums w_i Y_i^2, and d out / d w_i = Y_i / (beta Z) is summed against
+// d w/da, d w/db into pa, pb (per thread, before the division by beta).
+template <bool MW, class DP, class CP, class FP>
+DEV void until_adj_d(const Env& e, int a, int b, const float* w, const float* dwa, const float* dwb, DP Ep,
+                     DP Eq, const float* g, FP gphi, FP gpsi, CP ck, int ncks, float& pa, float& pb)
 {
-    const int L = e.L, a = I.a, b = I.b;
+    const int L = e.L;
     const int lane = threadIdx.x & 63;
     for (int tb = (int)threadIdx.x - lane; tb < L; tb += blockDim.x) {
         const int t = tb + lane;
@@ -982,12 +1098,18 @@ DEV void until_adj_d(const Env& e, const Instr& I, DP Ep, DP Eq, const float* g,
 #pragma unroll
                     for (int k = 0; k < UCK; ++k) {
                         P += v[k];
-                        if (i0 + k >= a) Z += rcpd(P + q[k]);
+                        if (i0 + k >= a) {
+                            const double y = rcpd(P + q[k]);
+                            Z += MW ? (double)w[i0 + k] * y : y;
+                        }
                     }
                 } else {
                     for (int i = i0; i <= imax; ++i) {
                         P += ep[i];
-                        if (i >= a) Z += rcpd(P + eq[i]);
+                        if (i >= a) {
+                            const double y = rcpd(P + eq[i]);
+                            Z += MW ? (double)w[i] * y : y;
+                        }
                     }
                 }
             }
@@ -996,7 +1118,8 @@ DEV void until_adj_d(const Env& e, const Instr& I, DP Ep, DP Eq, const float* g,
         int wblk = nblk;
         for (int d = 32; d > 0; d >>= 1) wblk = max(wblk, __shfl_xor(wblk, d));
         float accp = 0.f, accq = 0.f;
-        double A = 0.0;                     // suffix sum of Y_i^2
+        double A = 0.0;                     // suffix sum of w_i Y_i^2
+        double da = 0.0, db = 0.0;          // sum of dw_i Y_i (MW)
         for (int blk = wblk - 1; blk >= 0; --blk) {
             const int i0 = blk * UCK;
             const int n = blk < nblk ? min(UCK, imax - i0 + 1) : 0;
@@ -1018,9 +1141,13 @@ DEV void until_adj_d(const Env& e, const Instr& I, DP Ep, DP Eq, const float* g,
                 if (k < n) {
                     if (i >= a) {
                         const double y = rcpd(Ps[k] + q[k]);
-                        const double y2 = y * y;
+                        const double y2 = (MW ? (double)w[i] * y : y) * y;
                         A += y2;
                         accq += (float)(wz * y2 * q[k]);
+                        if (MW) {
+                            da += (double)dwa[i] * y;
+                            db += (double)dwb[i] * y;
+                        }
                     }
                     accp += (float)(wz * A * v[k]);
                 }
@@ -1040,25 +1167,46 @@ DEV void until_adj_d(const Env& e, const Instr& I, DP Ep, DP Eq, const float* g,
             __hip_atomic_fetch_add(gphi + t, accp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_fetch_add(gpsi + t, accq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        if (MW) {
+            pa += (float)(wz * da);
+            pb += (float)(wz * db);
+        }
     }
 }
 
-DEV void until_smooth_fwd_d(const Env& e, const Instr& I, double* Ep, double* Eq, float* out, float bl, int M)
+DEV void until_smooth_fwd_d(const Env& e, int a, int b, const float* w, double* Ep, double* Eq, float* out,
+                            float bl, int M)
 {
-    if (in_lds(Ep))
-        until_fwd_d(e, I, (const lds_double*)Ep, (const lds_double*)Eq, out, bl, M);
-    else
-        until_fwd_d(e, I, (const double*)Ep, (const double*)Eq, out, bl, M);
+    if (w) {
+        if (in_lds(Ep))
+            until_fwd_d<true>(e, a, b, w, (const lds_double*)Ep, (const lds_double*)Eq, out, bl, M);
+        else
+            until_fwd_d<true>(e, a, b, w, (const double*)Ep, (const double*)Eq, out, bl, M);
+    } else if (in_lds(Ep)) {
+        until_fwd_d<false>(e, a, b, w, (const lds_double*)Ep, (const lds_double*)Eq, out, bl, M);
+    } else {
+        until_fwd_d<false>(e, a, b, w, (const double*)Ep, (const double*)Eq, out, bl, M);
+    }
 }
 
-DEV void until_smooth_adj_d(const Env& e, const Instr& I, double* Ep, double* Eq, const float* g, float* gphi,
-                            float* gpsi, double* ck, int ncks)
+DEV void until_smooth_adj_d(const Env& e, int a, int b, const float* w, const float* dwa, const float* dwb,
+                            double* Ep, double* Eq, const float* g, float* gphi, float* gpsi, double* ck, int ncks,
+                            float& pa, float& pb)
 {
-    if (in_lds(Ep))
-        until_adj_d(e, I, (const lds_double*)Ep, (const lds_double*)Eq, g, (lds_float*)gphi, (lds_float*)gpsi,
-                    (lds_double*)ck, ncks);
-    else
-        until_adj_d(e, I, (const double*)Ep, (const double*)Eq, g, gphi, gpsi, ck, ncks);
+    if (w) {
+        if (in_lds(Ep))
+            until_adj_d<true>(e, a, b, w, dwa, dwb, (const lds_double*)Ep, (const lds_double*)Eq, g,
+                              (lds_float*)gphi, (lds_float*)gpsi, (lds_double*)ck, ncks, pa, pb);
+        else
+            until_adj_d<true>(e, a, b, w, dwa, dwb, (const double*)Ep, (const double*)Eq, g, gphi, gpsi, ck,
+                              ncks, pa, pb);
+    } else if (in_lds(Ep)) {
+        until_adj_d<false>(e, a, b, w, dwa, dwb, (const lds_double*)Ep, (const lds_double*)Eq, g,
+                           (lds_float*)gphi, (lds_float*)gpsi, (lds_double*)ck, ncks, pa, pb);
+    } else {
+        until_adj_d<false>(e, a, b, w, dwa, dwb, (const double*)Ep, (const double*)Eq, g, gphi, gpsi, ck, ncks,
+                           pa, pb);
+    }
 }
 
 // ------------------------------------------------------------------ instructions
@@ -1121,26 +1269,37 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
         const float* u = slot(e, i0);
         float* w = S(e, 6);
         MaskInfo mi = mask_weights(e, I, w, nullptr, nullptr);
+        // LAST / CONST pads of a bounded mask: support offsets past the end
+        const bool padm = I.pad != PAD_NEUTRAL && !(I.flags & F_MASK_UNB);
+        MaskTail mt{INT_MAX, -1, 0.0, 0.0, 0.0};
+        if (padm) mt = mask_tail(e, I, false);
+        const int klo = mi.any ? mi.klo : mt.lo;             // whole support
+        const int khi = mt.hi >= 0 ? mt.hi : mi.khi;
+        const bool anyk = mi.any || mt.hi >= 0;
+        const float padv = mask_padv(I);
         if (!is_smooth(I)) {
-            if (!mi.any) {
+            if (!anyk) {
                 for (int t = threadIdx.x; t < L; t += blockDim.x) out[t] = -sg * e.P->rho_pad;
             } else {
-                const int khi = ((I.flags & F_MASK_UNB) && mi.khi == L - 1) ? -1 : mi.khi;
-                win_hard(e, u, out, nullptr, sg, mi.klo, khi, PAD_NEUTRAL, 0.f, (VI*)S(e, 0), (VI*)S(e, 2));
+                const int kh = ((I.flags & F_MASK_UNB) && khi == L - 1) ? -1 : khi;
+                win_hard(e, u, out, nullptr, sg, klo, kh, padm ? I.pad : PAD_NEUTRAL, padv, (VI*)S(e, 0),
+                         (VI*)S(e, 2));
             }
             break;
         }
         const float bl = pbeta(e, I) * LOG2E;
         SP* acc = (SP*)S(e, 4);
         SP* E = (SP*)S(e, 8);
+        float* TW = S(e, 7);
         const bool core = mi.clo <= mi.chi;
         if (core) {
-            const int khi = ((I.flags & F_MASK_UNB) && mi.chi == L - 1) ? -1 : mi.chi;
-            win_smooth_sum(e, u, acc, sg * bl, mi.clo, khi, PAD_NEUTRAL, 0.f, (SP*)S(e, 0), (SP*)S(e, 2));
+            const int kh = ((I.flags & F_MASK_UNB) && mi.chi == L - 1) ? -1 : mi.chi;
+            win_smooth_sum(e, u, acc, sg * bl, mi.clo, kh, PAD_NEUTRAL, 0.f, (SP*)S(e, 0), (SP*)S(e, 2));
         }
         for (int j = threadIdx.x; j < L; j += blockDim.x) E[j] = sp_leaf(sg * bl * u[j]);
+        if (padm) tail_weights(w, TW, L, mt.s, *e.sh);
         __syncthreads();
-        const float lwc = core ? log2f(mi.wc) : 0.f;
+        const SP Ev = sp_leaf(sg * bl * (I.pad == PAD_LAST ? u[L - 1] : padv));
         for (int t = threadIdx.x; t < L; t += blockDim.x) {
             // band terms are summed one by one (up to a few hundred of them):
             // accumulate with a double mantissa so the error does not grow with the count
@@ -1151,17 +1310,33 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
             if (core)
                 for (int k = mi.chi + 1; k <= mi.khi && t + k < L; ++k)
                     a = spd_add(a, SP{w[k] * E[t + k].s, E[t + k].r});
-            const bool any = mi.any && t + mi.klo <= L - 1;
+            const bool pt = padm && anyk && t + khi > L - 1;   // pad copies for this output
+            if (pt) a = spd_add(a, SP{TW[t] * Ev.s, Ev.r});
+            const bool any = (mi.any && t + mi.klo <= L - 1) || pt;
             out[t] = any ? sg * sp_log2(spd_to_sp(a)) / bl : -sg * e.P->rho_pad;
         }
-        (void)lwc;
         break;
     }
     case K_UNTIL: {
         const float* phi = slot(e, i0);
         const float* psi = slot(e, i1);
+        // outer index range [ua, ub]; a smooth mask (Sec. VI) replaces it by
+        // its support {w > 0} and weights the terms
+        int ua = I.a, ub = I.b;
+        const float* w = nullptr;
+        if (I.mask >= 0) {
+            float* wt = S(e, 4);
+            const MaskInfo mi = mask_weights(e, I, wt, nullptr, nullptr);
+            if (!mi.any) {
+                for (int t = threadIdx.x; t < L; t += blockDim.x) out[t] = -e.P->rho_pad;
+                break;
+            }
+            ua = mi.klo;
+            ub = mi.khi;
+            w = wt;
+        }
         if (!is_smooth(I)) {
-            until_hard(e, I, phi, psi, out, nullptr, nullptr, nullptr);
+            until_hard(e, ua, ub, phi, psi, out, nullptr, nullptr, nullptr);
         } else {
             const float bl = pbeta(e, I) * LOG2E;
             int M;
@@ -1169,7 +1344,7 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
                 double* Ep = (double*)S(e, 0);
                 double* Eq = (double*)S(e, 2);
                 until_terms(phi, psi, L, bl, M, Ep, Eq);
-                until_smooth_fwd_d(e, I, Ep, Eq, out, bl, M);
+                until_smooth_fwd_d(e, ua, ub, w, Ep, Eq, out, bl, M);
                 break;
             }
             SP* Ephi = (SP*)S(e, 0);
@@ -1179,7 +1354,7 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
                 Epsi[j] = sp_leaf(-bl * psi[j]);
             }
             __syncthreads();
-            until_smooth_fwd(e, I, Ephi, Epsi, out, bl);
+            until_smooth_fwd(e, ua, ub, w, Ephi, Epsi, out, bl);
         }
         break;
     }
@@ -1291,13 +1466,20 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
         float* dwa = S(e, 7);
         float* dwb = S(e, 8);
         MaskInfo mi = mask_weights(e, I, w, dwa, dwb);
-        if (!is_smooth(I) || !mi.any) {
-            if (!mi.any) {
+        const bool padm = I.pad != PAD_NEUTRAL && !(I.flags & F_MASK_UNB);
+        MaskTail mt{INT_MAX, -1, 0.0, 0.0, 0.0};
+        if (padm) mt = mask_tail(e, I, true);
+        const int kall = mi.any ? mi.klo : mt.lo;            // whole support
+        const int khi_all = mt.hi >= 0 ? mt.hi : mi.khi;
+        const bool anyk = mi.any || mt.hi >= 0;
+        if (!is_smooth(I) || !anyk) {
+            if (!anyk) {
                 for (int j = threadIdx.x; j < L; j += blockDim.x) gu[j] = 0.f;
             } else {
-                const int khi = ((I.flags & F_MASK_UNB) && mi.khi == L - 1) ? -1 : mi.khi;
+                const int khi = ((I.flags & F_MASK_UNB) && khi_all == L - 1) ? -1 : khi_all;
                 int* js = (int*)S(e, 4);
-                win_hard(e, u, S(e, 5), js, sg, mi.klo, khi, PAD_NEUTRAL, 0.f, (VI*)S(e, 0), (VI*)S(e, 2));
+                win_hard(e, u, S(e, 5), js, sg, kall, khi, padm ? I.pad : PAD_NEUTRAL, mask_padv(I),
+                         (VI*)S(e, 0), (VI*)S(e, 2));
                 win_hard_adj(e, g, gu, js, (double*)S(e, 10));
             }
             if (I.mslot >= 0 && threadIdx.x == 0) { mask_part[2 * I.mslot] = 0.f; mask_part[2 * I.mslot + 1] = 0.f; }
@@ -1309,8 +1491,31 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
         SP* h = (SP*)S(e, 0);
         SP* hb = (SP*)S(e, 9);      // band copy of h (the scans consume h)
         SP* E = (SP*)S(e, 11);
-        const int nvalid = L - mi.klo;
+        const int nvalid = mi.any ? L - mi.klo : 0;
         float pa = 0.f, pb = 0.f;
+        float lastpad = 0.f;
+        if (padm) {
+            // pad copies: out_t gains TW_t 2^{z_v}; its share of the sum is
+            // f_t = TW_t 2^{z_v - O_t}, giving d/du_{L-1} (LAST) = f_t and
+            // d/da = TWa_t / TW_t * f_t / beta (d/db alike)
+            float* TW = S(e, 13);
+            float* TWa = S(e, 14);
+            float* TWb = S(e, 15);
+            tail_weights(w, TW, L, mt.s, *e.sh);
+            tail_weights(dwa, TWa, L, mt.sa, *e.sh);
+            tail_weights(dwb, TWb, L, mt.sb, *e.sh);
+            const float zv = sg * bl * (I.pad == PAD_LAST ? u[L - 1] : mask_padv(I));
+            const float ib0 = sg / pbeta(e, I);
+            for (int t = threadIdx.x; t < L; t += blockDim.x) {
+                if (t + khi_all <= L - 1 || !(TW[t] > 0.f)) continue;
+                const float f = exp2f(zv - sg * bl * out[t] + log2f(TW[t]));
+                const float gf = g[t] * f;
+                pa += ib0 * gf * (TWa[t] / TW[t]);
+                pb += ib0 * gf * (TWb[t] / TW[t]);
+                lastpad += gf;
+            }
+            if (I.pad == PAD_LAST) lastpad = wg_sum(lastpad, *e.sh);
+        }
         for (int t = threadIdx.x; t < L; t += blockDim.x) {
             E[t] = sp_leaf(sg * bl * u[t]);
             SP hv = sp_zero();
@@ -1358,7 +1563,9 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
             if (core)
                 for (int k = mi.chi + 1; k <= mi.khi && j - k >= 0; ++k)
                     a = spd_add(a, SP{w[k] * hb[j - k].s, hb[j - k].r});
-            gu[j] = sp_times_exp2(spd_to_sp(a), sg * bl * u[j]);
+            float v = sp_times_exp2(spd_to_sp(a), sg * bl * u[j]);
+            if (padm && I.pad == PAD_LAST && j == L - 1) v += lastpad;
+            gu[j] = v;
         }
         break;
     }
@@ -1369,17 +1576,36 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
         float* gpsi = slot(e, I.g_in1);
         for (int t = threadIdx.x; t < L; t += blockDim.x) { gphi[t] = 0.f; gpsi[t] = 0.f; }
         __syncthreads();
-        if (!is_smooth(I)) {
-            until_hard(e, I, phi, psi, nullptr, g, gphi, gpsi);
+        int ua = I.a, ub = I.b;
+        const float *w = nullptr, *dwa = nullptr, *dwb = nullptr;
+        bool none = false;
+        if (I.mask >= 0) {
+            float* wt = S(e, 4);
+            float* wa = S(e, 5);
+            float* wb = S(e, 6);
+            const MaskInfo mi = mask_weights(e, I, wt, wa, wb);
+            none = !mi.any;
+            ua = mi.klo;
+            ub = mi.khi;
+            w = wt;
+            dwa = wa;
+            dwb = wb;
+        }
+        float pa = 0.f, pb = 0.f;
+        if (none) {
+            // empty support: constant output
+        } else if (!is_smooth(I)) {
+            until_hard(e, ua, ub, phi, psi, nullptr, g, gphi, gpsi);
         } else {
             const float bl = pbeta(e, I) * LOG2E;
-            const int bmax = I.b < 0 ? L - 1 : min(I.b, L - 1);
+            const int bmax = ub < 0 ? L - 1 : min(ub, L - 1);
             int M;
             if (until_ref(phi, psi, L, bl, *e.sh, M)) {
                 double* Ep = (double*)S(e, 0);
                 double* Eq = (double*)S(e, 2);
                 until_terms(phi, psi, L, bl, M, Ep, Eq);
-                until_smooth_adj_d(e, I, Ep, Eq, g, gphi, gpsi, (double*)S(e, 4), bmax / UCK + 1);
+                until_smooth_adj_d(e, ua, ub, w, dwa, dwb, Ep, Eq, g, gphi, gpsi, (double*)S(e, UCK_UNIT),
+                                   bmax / UCK + 1, pa, pb);
             } else {
                 SP* Ephi = (SP*)S(e, 0);
                 SP* Epsi = (SP*)S(e, 2);
@@ -1388,8 +1614,16 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
                     Epsi[j] = sp_leaf(-bl * psi[j]);
                 }
                 __syncthreads();
-                until_smooth_adj(e, I, Ephi, Epsi, g, gphi, gpsi, (SP*)S(e, 4), bmax / UCK + 1);
+                until_smooth_adj(e, ua, ub, w, dwa, dwb, Ephi, Epsi, g, gphi, gpsi, (SP*)S(e, UCK_UNIT),
+                                 bmax / UCK + 1, pa, pb);
             }
+        }
+        if (I.mslot >= 0) {
+            // d out / d w_i = Y_i / (beta Z); zero for the hard form
+            const float ib = is_smooth(I) ? 1.f / pbeta(e, I) : 0.f;
+            const float sa = wg_sum(pa * ib, *e.sh);
+            const float sb = wg_sum(pb * ib, *e.sh);
+            if (threadIdx.x == 0) { mask_part[2 * I.mslot] = sa; mask_part[2 * I.mslot + 1] = sb; }
         }
         // d phi / d psi are sums of scaled terms: convert the scaled psi/phi sums in place
         break;
@@ -1423,7 +1657,12 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
 {
     extern __shared__ float smem[];
     __shared__ Shared sh;
-    const DevPlan* P = &plan;
+    // The plan is the first kernel argument, at offset 0 of the kernarg
+    // segment: read it there.  (Taking the address of the by-value parameter
+    // lets the compiler copy all of it into per-lane private memory, which it
+    // does once the kernel body grows past some size.)
+    const DevPlan* P = (const DevPlan*)__builtin_amdgcn_kernarg_segment_ptr();
+    (void)plan;
     float* arena = ka.garena ? ka.garena + (size_t)blockIdx.x * ka.arena_floats : smem;
     const int nslots = BWD ? P->n_slots_bwd : P->n_slots_fwd;
     const int Lc = bt.Lcap;
@@ -1541,9 +1780,9 @@ namespace stlmi {
 size_t scratch_floats(int Lc, int nt, int max_until_b)
 {
     size_t s = (size_t)SCR_UNITS * Lc + 64;
-    // smooth Until checkpoints: nt * (b/UCK + 1) scaled pairs, placed at unit 4
+    // smooth Until checkpoints: nt * (b/UCK + 1) scaled pairs, placed at unit UCK_UNIT
     size_t ck = (size_t)nt * (size_t)(max_until_b / UCK + 1) * 2;
-    if ((size_t)4 * Lc + ck + 64 > s) s = (size_t)4 * Lc + ck + 64;
+    if ((size_t)UCK_UNIT * Lc + ck + 64 > s) s = (size_t)UCK_UNIT * Lc + ck + 64;
     return s;
 }
 

@@ -52,7 +52,8 @@ struct Instr {                  // 40 bytes
     int8_t f_ch[MAX_NCH], b_ch[MAX_NCH], g_ch[MAX_NCH];
     int16_t node;                           // caller's node index (trace output), -1
     int16_t coef;                           // predicate / pad-value offset into coef[]
-    int32_t a, b;                           // integer interval (b < 0: unbounded)
+    int32_t a, b;                           // integer interval (b < 0: unbounded); K_MASK:
+                                            // a = bits of the pad value (no interval)
 };
 static_assert(sizeof(Instr) == 40, "Instr layout");
 

@@ -123,6 +123,15 @@ class _Emitter:
         self.slots.append((v, None) if isinstance(v, str) else (None, float(v)))
         return len(self.slots) - 1
 
+    def mask(self, nd, m):
+        """Smooth time-interval mask (Sec. VI): (a, b, c, eps) in four
+        consecutive parameter slots."""
+        nd.mask_param = self.slot(m["a"])
+        self.slot(0.0 if m.get("b") is None else m["b"])
+        self.slot(m["c"])
+        self.slot(m.get("eps", 1e-6))
+        nd.mask_unbounded = 1 if m.get("b") is None else 0
+
     def emit(self, f):
         op = f["op"]
         nd = Node()
@@ -167,22 +176,20 @@ class _Emitter:
             nd.op = STL_EVENTUALLY if op == "eventually" else STL_ALWAYS
             kids = [self.emit(f["child"])]
             if "mask" in f:
-                m = f["mask"]
-                nd.mask_param = self.slot(m["a"])
-                self.slot(0.0 if m.get("b") is None else m["b"])
-                self.slot(m["c"])
-                self.slot(m.get("eps", 1e-6))
-                nd.mask_unbounded = 1 if m.get("b") is None else 0
+                self.mask(nd, f["mask"])
             else:
                 nd.a = int(f.get("a", 0))
                 nd.b = -1 if f.get("b") is None else int(f["b"])
-                nd.pad = PADS[f.get("pad", "neutral")]
-                nd.pad_value = float(f.get("pad_value", 0.0))
+            nd.pad = PADS[f.get("pad", "neutral")]
+            nd.pad_value = float(f.get("pad_value", 0.0))
         elif op == "until":
             nd.op = STL_UNTIL
             kids = [self.emit(f["left"]), self.emit(f["right"])]
-            nd.a = int(f.get("a", 0))
-            nd.b = -1 if f.get("b") is None else int(f["b"])
+            if "mask" in f:
+                self.mask(nd, f["mask"])
+            else:
+                nd.a = int(f.get("a", 0))
+                nd.b = -1 if f.get("b") is None else int(f["b"])
         else:
             raise ValueError("unknown op %r" % op)
         sm = f.get("smooth", False)

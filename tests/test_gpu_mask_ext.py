@@ -1,0 +1,178 @@
+"""GPU parity of the smooth time mask (Sec. VI) on Until and of the LAST /
+CONST pads on smooth-mask Eventually / Always, against the FP64 oracle.
+
+Until: the mask weights the Until index i (the psi index the interval
+constrains) inside the outer smooth max; the hard form takes the max over the
+mask support.  Pads: every support offset past the signal end contributes one
+pad copy with its weight.  Calls go through the C ABI; tolerances are those of
+``gpu_util`` (hard selections bit-exact).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import Gpu, assert_close, check_formula
+
+pytestmark = pytest.mark.gpu
+
+S1 = {"op": "linear", "w": [1.0], "c": 0.0}
+PHI = {"op": "linear", "w": [1.0, 0.0], "c": -0.5}
+PSI = {"op": "linear", "w": [0.0, 1.0], "c": 0.1}
+
+
+def walk(rng, B, L, D=1, s=0.1):
+    return np.cumsum(rng.normal(size=(B, L, D)) * s, axis=1).astype(np.float32)
+
+
+def mask(a, b, c, eps):
+    return {"a": "a", "b": None if b is None else "b", "c": c, "eps": eps}
+
+
+def mparams(a, b):
+    return {"a": a} if b is None else {"a": a, "b": b}
+
+
+def until(m, smooth=True, left=PHI, right=PSI):
+    kw = {"smooth": True, "beta": 10.0} if smooth else {}
+    return dict({"op": "until", "left": left, "right": right, "mask": mask(*m)}, **kw)
+
+
+# --------------------------------------------------------------------------- smooth mask on Until
+
+UNTIL_MASKS = [
+    (5.3, 60.7, 1.0, 1e-6),       # bands at both ends, interior core
+    (0.0, 30.0, 1.0, 1e-6),       # sigmoid tail clipped at offset 0
+    (40.0, None, 2.0, 1e-6),      # unbounded mask: walks to the end
+    (20.0, 24.0, 0.3, 1e-4),      # wide bands, no flat part
+    (380.0, 450.0, 1.0, 1e-6),    # support running past the end for most t
+]
+
+
+@pytest.mark.parametrize("m", UNTIL_MASKS)
+def test_masked_until_smooth(m):
+    rng = np.random.default_rng(41)
+    x = walk(rng, 3, 420, D=2, s=0.1)
+    check_formula(until(m), x, params=mparams(m[0], m[1]), what="masked until %s" % (m,))
+
+
+def test_masked_until_sparse_gradient_and_ragged():
+    rng = np.random.default_rng(42)
+    m = (7.2, 90.4, 1.5, 1e-6)
+    x = walk(rng, 2, 700, D=2, s=0.1)
+    G = rng.normal(size=(2, 700)).astype(np.float32)
+    G[rng.random(G.shape) < 0.8] = 0.0
+    check_formula(until(m), x, params=mparams(7.2, 90.4), G=G, what="sparse-G masked until")
+    off = np.array([0, 130, 131, 500, 777], dtype=np.int64)
+    xp = walk(rng, 1, 777, D=2, s=0.1)[0]
+    check_formula(until(m), xp, params=mparams(7.2, 90.4), offsets=off, T=369, what="ragged masked until")
+
+
+def test_masked_until_hard_bitexact():
+    # predicate constants exact in float32, so both sides select on identical values
+    rng = np.random.default_rng(43)
+    x = walk(rng, 3, 333, D=2, s=0.1)
+    psi = {"op": "linear", "w": [0.0, 1.0], "c": 0.25}
+    for m in [(5.3, 60.7, 1.0, 1e-6), (12.0, None, 2.0, 1e-6), (300.0, 400.0, 1.0, 1e-6)]:
+        check_formula(until(m, smooth=False, right=psi), x, params=mparams(m[0], m[1]), bitexact_root=True,
+                      what="hard masked until %s" % (m,))
+
+
+def test_masked_until_wide_range_and_true_left():
+    """Exponent ranges beyond the fp64 form take the scaled-pair path; with
+    phi = True the masked Until equals the masked Eventually of psi."""
+    rng = np.random.default_rng(44)
+    x = walk(rng, 2, 300, D=2, s=0.1) * np.float32(60.0)
+    check_formula(until((3.5, 44.5, 1.0, 1e-6)), x, params=mparams(3.5, 44.5), what="wide masked until")
+    x = walk(rng, 2, 260, D=2, s=0.1)
+    m = (4.3, 37.8, 1.5, 1e-6)
+    check_formula(until(m, left={"op": "true"}), x, params=mparams(4.3, 37.8), what="true masked until")
+
+
+def test_masked_until_empty_support():
+    """A mask whose support lies past every trajectory: constant -rho_pad,
+    zero gradients."""
+    rng = np.random.default_rng(45)
+    x = walk(rng, 2, 120, D=2, s=0.1)
+    g = Gpu(until((500.0, 600.0, 1.0, 1e-6)), 2, mparams(500.0, 600.0))
+    r = g.fwd(x)
+    assert np.all(r == np.float32(-1e6))
+    dx, dp = g.bwd(x, rng.normal(size=(2, 120)).astype(np.float32))
+    assert np.all(dx == 0) and dp["a"] == 0 and dp["b"] == 0
+
+
+def test_masked_until_in_formula():
+    """A masked Until below an And with a masked Always: both masks learn."""
+    rng = np.random.default_rng(46)
+    x = walk(rng, 3, 500, D=2, s=0.08)
+    spec = {"op": "and", "smooth": True, "beta": 5.0, "children": [
+        {"op": "until", "smooth": True, "beta": 8.0, "left": PHI, "right": PSI,
+         "mask": {"a": "ua", "b": "ub", "c": 1.0, "eps": 1e-6}},
+        {"op": "always", "smooth": True, "beta": 8.0, "child": PSI,
+         "mask": {"a": "wa", "b": "wb", "c": 0.7, "eps": 1e-6}}]}
+    check_formula(spec, x, params={"ua": 10.2, "ub": 70.9, "wa": 3.1, "wb": 25.6}, what="until+always masks")
+
+
+# --------------------------------------------------------------------------- pads on smooth masks
+
+PAD_MASKS = [
+    (100.0, 400.0, 1.0, 1e-6),    # headline shape: pads for the last ~413 outputs
+    (10.3, 40.7, 1.0, 1e-6),
+    (20.0, 24.0, 0.3, 1e-4),      # no flat part
+    (600.0, 900.0, 1.0, 1e-6),    # support running past the end for every t
+    (800.0, 900.0, 1.0, 1e-6),    # support entirely past the end: pads only
+    (10.0, 40.0, 1.0, 0.0),       # eps = 0: the tail runs until the weights underflow
+]
+
+
+@pytest.mark.parametrize("m", PAD_MASKS)
+@pytest.mark.parametrize("pad", ["last", "const"])
+@pytest.mark.parametrize("kind", ["eventually", "always"])
+def test_mask_pads_smooth(m, pad, kind):
+    rng = np.random.default_rng(47)
+    x = walk(rng, 3, 700, s=0.05)
+    spec = {"op": kind, "smooth": True, "beta": 10.0, "child": S1, "mask": mask(*m), "pad": pad,
+            "pad_value": 0.3}
+    check_formula(spec, x, params=mparams(m[0], m[1]), what="mask pad %s %s %s" % (m, pad, kind))
+
+
+@pytest.mark.parametrize("pad", ["last", "const"])
+def test_mask_pads_hard_bitexact(pad):
+    rng = np.random.default_rng(48)
+    x = (rng.normal(size=(2, 500, 1))).astype(np.float32)
+    for m in [(9.5, 130.5, 3.0, 1e-6), (450.0, 520.0, 1.0, 1e-6), (600.0, 700.0, 1.0, 1e-6)]:
+        for kind in ("eventually", "always"):
+            spec = {"op": kind, "child": S1, "mask": mask(*m), "pad": pad, "pad_value": 0.25}
+            check_formula(spec, x, params=mparams(m[0], m[1]), bitexact_root=True,
+                          what="hard mask pad %s %s %s" % (m, pad, kind))
+
+
+def test_mask_pads_unbounded_mask_ignores_pad():
+    """An unbounded mask already reaches the end: its pad policy has no effect."""
+    rng = np.random.default_rng(49)
+    x = walk(rng, 2, 300, s=0.05)
+    m = (20.0, None, 1.0, 1e-6)
+    base = {"op": "eventually", "smooth": True, "beta": 10.0, "child": S1, "mask": mask(*m)}
+    r0 = Gpu(base, 1, mparams(20.0, None)).fwd(x)
+    r1 = Gpu(dict(base, pad="last"), 1, mparams(20.0, None)).fwd(x)
+    assert np.array_equal(r0, r1)
+    check_formula(dict(base, pad="const", pad_value=5.0), x, params=mparams(20.0, None), what="unbounded+pad")
+
+
+def test_mask_pads_on_the_fused_shape():
+    """The smooth And of two masked windows on linear predicates normally takes
+    the fused kernel; with a pad it runs on the generic executor and still
+    matches the oracle."""
+    rng = np.random.default_rng(50)
+    x = walk(rng, 4, 900, D=2, s=0.05)
+    spec = {"op": "and", "smooth": True, "beta": 10.0, "children": [
+        {"op": "eventually", "smooth": True, "beta": 10.0, "child": PHI, "pad": "last",
+         "mask": {"a": "ea", "b": "eb", "c": 1.0, "eps": 1e-6}},
+        {"op": "always", "smooth": True, "beta": 10.0, "child": PSI,
+         "mask": {"a": "la", "b": "lb", "c": 1.0, "eps": 1e-6}}]}
+    check_formula(spec, x, params={"ea": 100.0, "eb": 400.0, "la": 50.0, "lb": 200.0}, what="fused shape + pad")
+    ref = oracle.forward(dict(spec, children=[dict(spec["children"][0], pad="neutral"), spec["children"][1]]), x,
+                         params={"ea": 100.0, "eb": 400.0, "la": 50.0, "lb": 200.0})
+    got = Gpu(spec, 2, {"ea": 100.0, "eb": 400.0, "la": 50.0, "lb": 200.0}).fwd(x)
+    # the pad changes the outputs whose Eventually window reaches past the end
+    assert np.abs(got[:, -300:] - ref[:, -300:]).max() > 1e-4
+    assert_close(got[:, :400], ref[:, :400], what="outputs away from the end")

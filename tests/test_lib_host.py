@@ -108,10 +108,16 @@ def test_compile_error_paths():
     assert _compile_raw([lin], [], 0, [_lin()], D=0)[0] == E_UNSUP
     assert _compile_raw([lin], [], 3, [_lin()])[0] == E_ARG
     assert _compile_raw([_node(42)], [], 0)[0] == E_FORMULA
-    # Until with a smooth mask is outside the library's scope
+    # Until with a smooth mask compiles; its parameter block must fit
     st, msg = _compile_raw([lin, _node(stl.STL_PRED_LINEAR, pred=0), _node(stl.STL_UNTIL, 2, 0, mask=0)], [0, 1], 2,
                            [_lin()], n_params=4)
-    assert st == E_UNSUP
+    assert st == 0
+    st, msg = _compile_raw([lin, _node(stl.STL_PRED_LINEAR, pred=0), _node(stl.STL_UNTIL, 2, 0, mask=1)], [0, 1], 2,
+                           [_lin()], n_params=4)
+    assert st == E_ARG
+    # pad policy out of range on a smooth-mask node
+    st, msg = _compile_raw([lin, _node(stl.STL_EVENTUALLY, 1, 0, mask=0, pad=5)], [0], 1, [_lin()], n_params=4)
+    assert st == E_ARG and "pad" in msg
 
 
 def test_nary_more_than_four_children_compiles():
