@@ -689,3 +689,36 @@ def test_fd_mask_pad_gradients(orc):
         spec = {"op": "always", "smooth": True, "beta": 3.0, "mask": _m("a", "b", 0.8), "pad": pad,
                 "pad_value": -0.2, "child": {"op": "linear", "w": [1.0, 0.5], "c": 0.1}}
         _fd_check(orc, spec, x, G, params={"a": 12.3, "b": 38.6}, names=("a", "b"))
+
+
+@pytest.mark.parametrize("pad", ["last", "const"])
+def test_softmax_window_pads(orc, pad):
+    """LAST / CONST on a softmax-weighted window: the output equals the NEUTRAL
+    window on the signal extended by K copies of its last sample (or of the
+    pad value), the last sample's adjoint collects those of its copies, and
+    the gradients match central differences."""
+    rng = np.random.default_rng(38)
+    L, K = 30, 12
+    u = rng.normal(size=L)
+    pv = -0.4
+    ue = np.concatenate([u, np.full(K, u[-1] if pad == "last" else pv)])
+    G = rng.normal(size=L)
+    Ge = np.concatenate([G, np.zeros(K)])
+    for kind in ("eventually", "always"):
+        for (a, b) in [(0, 5), (3, 11), (2, 2)]:
+            sp = {"op": kind, "a": a, "b": b, "child": S, "smooth": "softmax", "beta": 2.5, "pad": pad,
+                  "pad_value": pv}
+            sn = dict(sp, pad="neutral")
+            r = orc.forward(sp, sig1(u))[0]
+            re = orc.forward(sn, sig1(ue))[0][:L]
+            assert np.abs(r - re).max() <= 1e-13
+            d, _ = orc.backward(sp, sig1(u), G.reshape(1, L))
+            de, _ = orc.backward(sn, sig1(ue), Ge.reshape(1, -1))
+            de = de.reshape(-1)
+            want = de[:L].copy()
+            if pad == "last":
+                want[L - 1] += de[L:].sum()
+            assert np.abs(d.reshape(-1) - want).max() <= 1e-12
+    x = np.cumsum(rng.normal(size=(2, 40, 1)) * 0.3, axis=1)
+    _fd_check(orc, {"op": "always", "a": 2, "b": 9, "child": S, "smooth": "softmax", "beta": 3.0, "pad": pad,
+                    "pad_value": pv}, x, rng.normal(size=(2, 40)))
