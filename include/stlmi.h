@@ -99,8 +99,8 @@ typedef struct {
     int32_t child_off;
     int32_t smooth;          /* 0: hard min/max, 1: logsumexp, 2: softmax-weighted mean
                                 sum v e^{beta v} / sum e^{beta v} (Sec. III-C): And/Or with
-                                up to 4 children and unmasked Eventually/Always with the
-                                NEUTRAL pad only (else STL_E_UNSUPPORTED) */
+                                up to 4 children and unmasked Eventually/Always only
+                                (else STL_E_UNSUPPORTED) */
     int32_t a, b;            /* integer interval (temporal nodes); b = -1: unbounded */
     int32_t mask_param;      /* -1: integer interval; else params[mask_param + 0..3] = (a, b, c, eps) */
     int32_t mask_unbounded;  /* smooth mask with b = +inf (params[mask_param+1] ignored) */

@@ -145,14 +145,13 @@ stl_status emit(Builder& B, int id, int depth, int* out)
     }
     if (n.smooth == 2) {
         // softmax-weighted form: And/Or with at most MAX_NCH children (it is not
-        // associative, so no regrouping) and unmasked windows with the NEUTRAL pad
-        const bool win = (n.op == STL_EVENTUALLY || n.op == STL_ALWAYS) && n.mask_param < 0 &&
-                         (n.b < 0 || n.pad == STL_PAD_NEUTRAL);
+        // associative, so no regrouping) and unmasked windows
+        const bool win = (n.op == STL_EVENTUALLY || n.op == STL_ALWAYS) && n.mask_param < 0;
         const bool nary = (n.op == STL_AND || n.op == STL_OR) && n.n_child <= MAX_NCH;
         if (!win && !nary)
             return fail(STL_E_UNSUPPORTED,
                         "node %d: the softmax-weighted form applies to And/Or with up to %d children and to "
-                        "unmasked Eventually/Always with the NEUTRAL pad",
+                        "unmasked Eventually/Always",
                         id, MAX_NCH);
         I.flags |= F_SOFT;
     }

@@ -1245,14 +1245,25 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
         if (!is_smooth(I)) {
             win_hard(e, u, out, nullptr, sg, I.a, khi, I.pad, padv, (VI*)S(e, 0), (VI*)S(e, 2));
         } else if (I.flags & F_SOFT) {
-            // softmax-weighted mean over the window (NEUTRAL pad): out = sum u 2^{z} / sum 2^{z}
+            // softmax-weighted mean over the window: out = sum u 2^{z} / sum 2^{z};
+            // LAST / CONST add np copies of the pad value v to both sums
             const float bl = pbeta(e, I) * LOG2E;
             SP* den = (SP*)S(e, 4);
             SP* num = (SP*)S(e, 6);
-            win_smooth_sum(e, u, den, sg * bl, I.a, khi, PAD_NEUTRAL, 0.f, (SP*)S(e, 0), (SP*)S(e, 2));
+            win_smooth_sum(e, u, den, sg * bl, I.a, khi, I.pad, padv, (SP*)S(e, 0), (SP*)S(e, 2));
             win_smooth_sum_w(e, u, num, sg * bl, I.a, khi, (SP*)S(e, 0), (SP*)S(e, 2));
-            for (int t = threadIdx.x; t < L; t += blockDim.x)
-                out[t] = t + I.a <= L - 1 ? sp_ratio(num[t], den[t]) : -sg * e.P->rho_pad;
+            const float v = I.pad == PAD_LAST ? u[L - 1] : padv;
+            for (int t = threadIdx.x; t < L; t += blockDim.x) {
+                SP nm = num[t];
+                const bool padded = khi >= 0 && I.pad != PAD_NEUTRAL && t + khi > L - 1;
+                if (padded) {
+                    const int np = min(khi - I.a + 1, t + khi - (L - 1));
+                    SP pv = sp_leaf(sg * bl * v);
+                    pv.s *= (float)np * v;
+                    nm = sp_add(nm, pv);
+                }
+                out[t] = (t + I.a <= L - 1 || padded) ? sp_ratio(nm, den[t]) : -sg * e.P->rho_pad;
+            }
         } else {
             const float bl = pbeta(e, I) * LOG2E;
             SP* acc = (SP*)S(e, 4);
@@ -1399,13 +1410,16 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
             // d out_t / d u_j = p_j(t) (1 + k (u_j - out_t)), p_j(t) = 2^{z_j} / S0(t), k = sg beta:
             // gu_j = 2^{z_j} [(1 + k u_j) sum_t G_t / S0(t) - k sum_t G_t out_t / S0(t)]
             // over the t whose window holds j (transposed window sums)
+            // A LAST pad adds, per output, np copies of u_{L-1}: p_v(t) np (1 + k (u_{L-1} - out_t)).
             const float bl = pbeta(e, I) * LOG2E, kap = sg * bl / LOG2E;
             const float* out = slot(e, I.b_out);
             const int n = L - I.a;
             SP* den = (SP*)S(e, 6);
-            win_smooth_sum(e, u, den, sg * bl, I.a, khi, PAD_NEUTRAL, 0.f, (SP*)S(e, 0), (SP*)S(e, 2));
+            win_smooth_sum(e, u, den, sg * bl, I.a, khi, I.pad, padv, (SP*)S(e, 0), (SP*)S(e, 2));
             SP* h = (SP*)S(e, 0);
             SP* h2 = (SP*)S(e, 8);
+            float lastpad = 0.f;
+            const SP zv = sp_leaf(sg * bl * u[L - 1]);
             for (int t = threadIdx.x; t < L; t += blockDim.x) {
                 SP a = sp_zero(), b2 = sp_zero();
                 if (t < n) {
@@ -1415,7 +1429,13 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
                 }
                 h[t] = a;
                 h2[t] = b2;
+                if (khi >= 0 && I.pad == PAD_LAST && t + khi > L - 1) {
+                    const int np = min(khi - I.a + 1, t + khi - (L - 1));
+                    const float pv = sp_ratio(zv, den[t]);
+                    lastpad += g[t] * (float)np * pv * (1.f + kap * (u[L - 1] - out[t]));
+                }
             }
+            if (I.pad == PAD_LAST) lastpad = wg_sum(lastpad, *e.sh);
             __syncthreads();
             SP* res = (SP*)S(e, 4);
             SP* res2 = (SP*)S(e, 10);
@@ -1424,7 +1444,9 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
             for (int j = threadIdx.x; j < L; j += blockDim.x) {
                 const SP r1 = res[j], r2 = res2[j];
                 const SP c = sp_add(SP{r1.s * (1.f + kap * u[j]), r1.r}, SP{-kap * r2.s, r2.r});
-                gu[j] = sp_times_exp2(c, sg * bl * u[j]);
+                float vj = sp_times_exp2(c, sg * bl * u[j]);
+                if (j == L - 1) vj += lastpad;
+                gu[j] = vj;
             }
             break;
         }

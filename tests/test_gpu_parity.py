@@ -379,6 +379,19 @@ def test_softmax_windows(ab, kind):
     check_formula(spec, x, what="softmax %s%s" % (kind, ab))
 
 
+@pytest.mark.parametrize("ab", [(0, 0), (0, 7), (3, 40), (200, 600)])
+@pytest.mark.parametrize("pad", ["last", "const"])
+@pytest.mark.parametrize("kind", ["eventually", "always"])
+def test_softmax_window_pads(ab, pad, kind):
+    """Softmax-weighted windows with LAST / CONST pads: the pad copies enter
+    both sums; with LAST their adjoint reaches the last sample."""
+    rng = np.random.default_rng(23)
+    x = walk(rng, 3, 517, s=0.1)
+    spec = dict({"op": kind, "a": ab[0], "b": ab[1], "child": S1, "smooth": "softmax", "beta": 6.0, "pad": pad,
+                 "pad_value": -0.35})
+    check_formula(spec, x, what="softmax pad %s %s%s" % (pad, kind, ab))
+
+
 def test_softmax_nary_and_nesting():
     rng = np.random.default_rng(22)
     x = walk(rng, 3, 300, D=3, s=0.1)
@@ -396,6 +409,7 @@ def test_softmax_nary_and_nesting():
 def test_softmax_unsupported_forms():
     from paper_2501_04194_amd import stl
     with pytest.raises(stl.StlError, match="softmax"):
-        stl.Plan(ev(S1, 0, 5, smooth="softmax", beta=1.0, pad="last"), 1)
+        stl.Plan({"op": "eventually", "child": S1, "smooth": "softmax", "beta": 1.0,
+                  "mask": {"a": 1.0, "b": 5.0, "c": 1.0, "eps": 1e-6}}, 1)
     with pytest.raises(stl.StlError, match="softmax"):
         stl.Plan({"op": "until", "a": 0, "b": 3, "smooth": "softmax", "beta": 1.0, "left": S1, "right": S1}, 1)
