@@ -1124,7 +1124,7 @@ DEV void until_adj_d(const Env& e, int a, int b, const float* w, const float* dw
         for (int d = 32; d > 0; d >>= 1) wblk = max(wblk, __shfl_xor(wblk, d));
         float accp = 0.f, accq = 0.f;
         float stp = 0.f, stq = 0.f;         // staged finished sums (see the shift below)
-        double A = 0.0;                     // suffix sum of w_i Y_i^2
+        double A = 0.0;                     // G/Z times the suffix sum of w_i Y_i^2
         double da = 0.0, db = 0.0;          // sum of dw_i Y_i (MW)
         for (int blk = wblk - 1; blk >= 0; --blk) {
             const int i0 = blk * UCK;
@@ -1147,15 +1147,15 @@ DEV void until_adj_d(const Env& e, int a, int b, const float* w, const float* dw
                 if (k < n) {
                     if (i >= a) {
                         const double y = rcpd(Ps[k] + q[k]);
-                        const double y2 = (MW ? (double)w[i] * y : y) * y;
+                        const double y2 = (MW ? wz * (double)w[i] : wz) * y * y;   // G/Z w_i Y_i^2
                         A += y2;
-                        accq += (float)(wz * y2 * q[k]);
+                        accq += (float)(y2 * q[k]);
                         if (MW) {
                             da += (double)dwa[i] * y;
                             db += (double)dwb[i] * y;
                         }
                     }
-                    accp += (float)(wz * A * v[k]);
+                    accp += (float)(A * v[k]);
                 }
                 if (i > 0) {
                     // lane 63 holds the finished sum of position tb + 64 + s, s = i - 1:
