@@ -397,13 +397,25 @@ extern "C" stl_status stl_compile(const stl_node* nodes, int32_t n_nodes, const 
             if (ch.size() > 1) { I.f_in1 = (int8_t)fslot[ch[1]]; I.b_in1 = (int8_t)ch[1]; I.g_in1 = (int8_t)(nval + gslot[ch[1]]); }
         }
     }
+    // each smooth Until gets a slot pair in the backward map where the
+    // recompute keeps its fp64 outer sums Z_t for the adjoint (index in I.coef)
+    int nbwd = nval + nadj;
+    for (int k = 0; k < n; ++k) {
+        Instr& I = B.ins[k];
+        if (I.kind != K_UNTIL) continue;
+        I.coef = -1;
+        if (I.flags & F_SMOOTH) {
+            I.coef = (int16_t)nbwd;
+            nbwd += 2;
+        }
+    }
     stl_plan* p = new (std::nothrow) stl_plan();
     if (!p) return fail(STL_E_ARG, "out of host memory");
     DevPlan& dp = p->dev;
     std::memset(&dp, 0, sizeof dp);
     dp.n_ins = n;
     dp.n_slots_fwd = (int)fa.free_at.size();
-    dp.n_slots_bwd = nval + nadj;
+    dp.n_slots_bwd = nbwd;
     dp.D = D;
     dp.n_masks = (int)B.mask_params.size();
     dp.n_params = n_params;

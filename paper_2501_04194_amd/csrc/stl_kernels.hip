@@ -1039,7 +1039,8 @@ DEV double until_z(DP ep, DP eq, int a, int imax, const float* w)
 // Forward on the fp64 terms: the same sums as until_smooth_fwd, with
 // Y_i = 2^{-M} / (P_i + Q_i) in true units, so log2 Z_true = log2 Z - M.
 template <bool MW, class DP>
-DEV void until_fwd_d(const Env& e, int a, int b, const float* w, DP Ep, DP Eq, float* out, float bl, int M)
+DEV void until_fwd_d(const Env& e, int a, int b, const float* w, DP Ep, DP Eq, float* out, double* zs, float bl,
+                     int M)
 {
     const int L = e.L;
     const float rho_pad = e.P->rho_pad;
@@ -1048,6 +1049,7 @@ DEV void until_fwd_d(const Env& e, int a, int b, const float* w, DP Ep, DP Eq, f
         if (a > imax) { out[t] = -rho_pad; continue; }
         const double Z = until_z<MW>(Ep + t, Eq + t, a, imax, w);
         out[t] = (float)(log2_minus(Z, M) / (double)bl);
+        if (zs) zs[t] = Z;
     }
 }
 
@@ -1058,9 +1060,9 @@ DEV float lane_shr1(float v)
 }
 
 // Adjoint on the fp64 terms (the derivatives are ratios of terms, so the
-// reference cancels).  A forward sweep keeps P every UCK steps; the reverse
-// sweep rebuilds each block's P from its checkpoint and carries the suffix
-// sum A of Y_i^2:
+// reference cancels).  Z_t comes from the forward recompute (zs); a forward
+// sweep of additions keeps P every UCK steps; the reverse sweep rebuilds each
+// block's P from its checkpoint and carries the suffix sum A of Y_i^2:
 //   d out / d psi_{t+i} = Y_i^2 q_i / Z,  d out / d phi_{t+k} = p_k A_k / Z.
 // The lanes of a wave hold consecutive t and walk i downwards in step, so at
 // each step lane l adds to position t_0 + l + i: the wave keeps one register
@@ -1073,7 +1075,8 @@ DEV float lane_shr1(float v)
 // d w/da, d w/db into pa, pb (per thread, before the division by beta).
 template <bool MW, class DP, class CP, class FP>
 DEV void until_adj_d(const Env& e, int a, int b, const float* w, const float* dwa, const float* dwb, DP Ep,
-                     DP Eq, const float* g, FP gphi, FP gpsi, CP ck, int ncks, float& pa, float& pb)
+                     DP Eq, const double* zs, const float* g, FP gphi, FP gpsi, CP ck, int ncks, float& pa,
+                     float& pb)
 {
     const int L = e.L;
     const int lane = threadIdx.x & 63;
@@ -1088,34 +1091,18 @@ DEV void until_adj_d(const Env& e, int a, int b, const float* w, const float* dw
         const CP myck = ck + (size_t)threadIdx.x * ncks;
         double Z = 1.0;
         if (act) {
+            // Z comes from the forward recompute: only the block-start prefixes of P
+            Z = zs[t];
             double P = 0.0;
-            Z = 0.0;
             for (int blk = 0; blk < nblk; ++blk) {
-                const int i0 = blk * UCK;
                 myck[blk] = P;
-                if (i0 + UCK <= imax + 1) {
-                    double v[UCK], q[UCK];
+                if (blk + 1 < nblk) {                  // blocks before the last are full
+                    const int i0 = blk * UCK;
+                    double v[UCK];
 #pragma unroll
-                    for (int k = 0; k < UCK; ++k) {
-                        v[k] = ep[i0 + k];
-                        q[k] = eq[i0 + k];
-                    }
+                    for (int k = 0; k < UCK; ++k) v[k] = ep[i0 + k];
 #pragma unroll
-                    for (int k = 0; k < UCK; ++k) {
-                        P += v[k];
-                        if (i0 + k >= a) {
-                            const double y = rcpd(P + q[k]);
-                            Z += MW ? (double)w[i0 + k] * y : y;
-                        }
-                    }
-                } else {
-                    for (int i = i0; i <= imax; ++i) {
-                        P += ep[i];
-                        if (i >= a) {
-                            const double y = rcpd(P + eq[i]);
-                            Z += MW ? (double)w[i] * y : y;
-                        }
-                    }
+                    for (int k = 0; k < UCK; ++k) P += v[k];
                 }
             }
         }
@@ -1194,36 +1181,36 @@ DEV void until_adj_d(const Env& e, int a, int b, const float* w, const float* dw
 }
 
 DEV void until_smooth_fwd_d(const Env& e, int a, int b, const float* w, double* Ep, double* Eq, float* out,
-                            float bl, int M)
+                            double* zs, float bl, int M)
 {
     if (w) {
         if (in_lds(Ep))
-            until_fwd_d<true>(e, a, b, w, (const lds_double*)Ep, (const lds_double*)Eq, out, bl, M);
+            until_fwd_d<true>(e, a, b, w, (const lds_double*)Ep, (const lds_double*)Eq, out, zs, bl, M);
         else
-            until_fwd_d<true>(e, a, b, w, (const double*)Ep, (const double*)Eq, out, bl, M);
+            until_fwd_d<true>(e, a, b, w, (const double*)Ep, (const double*)Eq, out, zs, bl, M);
     } else if (in_lds(Ep)) {
-        until_fwd_d<false>(e, a, b, w, (const lds_double*)Ep, (const lds_double*)Eq, out, bl, M);
+        until_fwd_d<false>(e, a, b, w, (const lds_double*)Ep, (const lds_double*)Eq, out, zs, bl, M);
     } else {
-        until_fwd_d<false>(e, a, b, w, (const double*)Ep, (const double*)Eq, out, bl, M);
+        until_fwd_d<false>(e, a, b, w, (const double*)Ep, (const double*)Eq, out, zs, bl, M);
     }
 }
 
 DEV void until_smooth_adj_d(const Env& e, int a, int b, const float* w, const float* dwa, const float* dwb,
-                            double* Ep, double* Eq, const float* g, float* gphi, float* gpsi, double* ck, int ncks,
-                            float& pa, float& pb)
+                            double* Ep, double* Eq, const double* zs, const float* g, float* gphi, float* gpsi,
+                            double* ck, int ncks, float& pa, float& pb)
 {
     if (w) {
         if (in_lds(Ep))
-            until_adj_d<true>(e, a, b, w, dwa, dwb, (const lds_double*)Ep, (const lds_double*)Eq, g,
+            until_adj_d<true>(e, a, b, w, dwa, dwb, (const lds_double*)Ep, (const lds_double*)Eq, zs, g,
                               (lds_float*)gphi, (lds_float*)gpsi, (lds_double*)ck, ncks, pa, pb);
         else
-            until_adj_d<true>(e, a, b, w, dwa, dwb, (const double*)Ep, (const double*)Eq, g, gphi, gpsi, ck,
+            until_adj_d<true>(e, a, b, w, dwa, dwb, (const double*)Ep, (const double*)Eq, zs, g, gphi, gpsi, ck,
                               ncks, pa, pb);
     } else if (in_lds(Ep)) {
-        until_adj_d<false>(e, a, b, w, dwa, dwb, (const lds_double*)Ep, (const lds_double*)Eq, g,
+        until_adj_d<false>(e, a, b, w, dwa, dwb, (const lds_double*)Ep, (const lds_double*)Eq, zs, g,
                            (lds_float*)gphi, (lds_float*)gpsi, (lds_double*)ck, ncks, pa, pb);
     } else {
-        until_adj_d<false>(e, a, b, w, dwa, dwb, (const double*)Ep, (const double*)Eq, g, gphi, gpsi, ck, ncks,
+        until_adj_d<false>(e, a, b, w, dwa, dwb, (const double*)Ep, (const double*)Eq, zs, g, gphi, gpsi, ck, ncks,
                            pa, pb);
     }
 }
@@ -1374,7 +1361,9 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
                 double* Ep = (double*)S(e, 0);
                 double* Eq = (double*)S(e, 2);
                 until_terms(phi, psi, L, bl, M, Ep, Eq);
-                until_smooth_fwd_d(e, ua, ub, w, Ep, Eq, out, bl, M);
+                // the backward's recompute keeps Z in the instruction's slot pair for the adjoint
+                double* zs = bwdmap ? (double*)slot(e, I.coef) : nullptr;
+                until_smooth_fwd_d(e, ua, ub, w, Ep, Eq, out, zs, bl, M);
                 break;
             }
             SP* Ephi = (SP*)S(e, 0);
@@ -1645,7 +1634,8 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
                 double* Ep = (double*)S(e, 0);
                 double* Eq = (double*)S(e, 2);
                 until_terms(phi, psi, L, bl, M, Ep, Eq);
-                until_smooth_adj_d(e, ua, ub, w, dwa, dwb, Ep, Eq, g, gphi, gpsi, (double*)S(e, UCK_UNIT),
+                const double* zs = (const double*)slot(e, I.coef);
+                until_smooth_adj_d(e, ua, ub, w, dwa, dwb, Ep, Eq, zs, g, gphi, gpsi, (double*)S(e, UCK_UNIT),
                                    bmax / UCK + 1, pa, pb);
             } else {
                 SP* Ephi = (SP*)S(e, 0);
