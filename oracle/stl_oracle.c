@@ -89,25 +89,38 @@ static double sigm(double z)
     return e / (1.0 + e);
 }
 
-/* Smooth mask weight of Sec. VI for offset k (timesteps). */
+/* Smooth mask weight of Sec. VI for offset k (timesteps):
+ * sig(x) - sig(y) - eps with x = c(k-a), y = c(k-b).  The difference is
+ * evaluated through the identity sig(x) - sig(y) = sig(x) sig(-y) (1 - e^{y-x})
+ * (put the two fractions over one denominator), which has no cancellation:
+ * where both sigmoids round to 1 the literal difference is 0 in fp64 while
+ * the weight is e^{-y}-small but positive, and with eps = 0 such weights can
+ * still carry a large exponential term. */
 static double mask_weight(const onode *nd, int k)
 {
-    double s1 = sigm(nd->mc * ((double)k - nd->ma));
-    double s2 = nd->mb_inf ? 0.0 : sigm(nd->mc * ((double)k - nd->mb));
-    double w = s1 - s2 - nd->meps;
+    double x = nd->mc * ((double)k - nd->ma);
+    double d;
+    if (nd->mb_inf) {
+        d = sigm(x);
+    } else {
+        double y = nd->mc * ((double)k - nd->mb);
+        d = sigm(x) * sigm(-y) * -expm1(y - x);
+    }
+    double w = d - nd->meps;
     return w > 0 ? w : 0.0;
 }
 
-/* d w_k / d a and d w_k / d b (zero where the max(.,0) clamp is active). */
+/* d w_k / d a = -c sig'(x) and d w_k / d b = c sig'(y), sig' = sig(.) sig(-.)
+ * (no 1 - sig cancellation), zero where the max(.,0) clamp is active. */
 static void mask_weight_grad(const onode *nd, int k, double *dwa, double *dwb)
 {
     double w = mask_weight(nd, k);
     if (w <= 0) { *dwa = 0; *dwb = 0; return; }
-    double s1 = sigm(nd->mc * ((double)k - nd->ma));
-    *dwa = -nd->mc * s1 * (1.0 - s1);
+    double x = nd->mc * ((double)k - nd->ma);
+    *dwa = -nd->mc * sigm(x) * sigm(-x);
     if (nd->mb_inf) { *dwb = 0; return; }
-    double s2 = sigm(nd->mc * ((double)k - nd->mb));
-    *dwb = nd->mc * s2 * (1.0 - s2);
+    double y = nd->mc * ((double)k - nd->mb);
+    *dwb = nd->mc * sigm(y) * sigm(-y);
 }
 
 /* Orientation: +1 for max-type operators (or, eventually), -1 for min-type.

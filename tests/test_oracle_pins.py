@@ -722,3 +722,33 @@ def test_softmax_window_pads(orc, pad):
     x = np.cumsum(rng.normal(size=(2, 40, 1)) * 0.3, axis=1)
     _fd_check(orc, {"op": "always", "a": 2, "b": 9, "child": S, "smooth": "softmax", "beta": 3.0, "pad": pad,
                     "pad_value": pv}, x, rng.normal(size=(2, 40)))
+
+
+def test_mask_weights_against_high_precision(orc):
+    """The mask weight and its derivatives against the literal Sec. VI
+    expressions evaluated with 200 significant digits (decimal), including
+    offsets far past b where both sigmoids round to 1 in fp64 and the weight
+    (eps = 0) is only e^{-c(k-b)}-small."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 200
+    one = Decimal(1)
+
+    def sig(z):
+        return one / (one + (-z).exp())
+
+    for (a, b, c) in [(10.0, 40.0, 1.0), (3.5, 9.25, 2.0), (20.0, 24.0, 0.3)]:
+        L = int(b + 300 / c)
+        w, da, db = orc.mask_weights(a, b, c, 0.0, L)
+        for k in range(L):
+            x = Decimal(c) * (Decimal(k) - Decimal(a))
+            y = Decimal(c) * (Decimal(k) - Decimal(b))
+            ref = sig(x) - sig(y)
+            # fp64 rounds the exponents c(k-a), c(k-b) themselves: a relative
+            # error of about (|x| + |y|) 2^-53 is the conditioning of the weight
+            tol = Decimal((4 + abs(float(x)) + abs(float(y))) * 2.0 ** -52)
+            assert w[k] > 0
+            assert abs(Decimal(w[k]) - ref) <= tol * ref, (a, b, c, k)
+            rda = -Decimal(c) * sig(x) * (one - sig(x))
+            rdb = Decimal(c) * sig(y) * (one - sig(y))
+            assert abs(Decimal(da[k]) - rda) <= tol * abs(rda)
+            assert abs(Decimal(db[k]) - rdb) <= tol * abs(rdb)
