@@ -203,6 +203,15 @@ def bench_intervals(args):
            "roofline": {"bound": "alu", "kernel": "stl_interval_kernel", "achieved": achieved,
                         "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                         "traffic": None, "terms": terms}}
+    if B >= 16:
+        # batched: three [B, T] x [T, N] products on the matrix cores; the
+        # binding roofline is HBM, for the 12 B written per (signal, interval)
+        nbytes = B * N * 12 + B * T * 4 + N * 8
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        mf = 2 * 3 * B * N * (4 * ((T + 3) // 4)) / (ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "hbm", "kernel": "stl_interval_mfma_kernel", "achieved": gbs,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "bytes_per_launch": nbytes, "mfma_fp32_tflops": mf}
     if not args.no_cpu_baseline:
         import oracle
         oracle.build()

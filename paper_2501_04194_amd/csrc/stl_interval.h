@@ -196,6 +196,113 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_kernel(IntervalArgs A)
     }
 }
 
+// ------------------------------------------------------------------ batched sweep on the matrix cores
+
+// For many trajectories the smooth sweep is a dense contraction: with
+// E_bk = 2^{z_bk - R_b} (z = +-beta log2(e) u, R_b the trajectory's largest
+// exponent), S_bn = sum_k w_nk E_bk and the same sums with dw/da, dw/db are
+// three products of the [B, T] term matrix with the [T, N] weight matrices,
+// which v_mfma_f32_16x16x4f32 computes 16 x 16 outputs at a time (K = 4 per
+// instruction).  A wave owns 16 intervals: it evaluates their weights once,
+// as B operands (lane l: interval n0 + l%16, offsets 4s + l/16), then walks
+// tiles of 16 trajectories, whose terms are the A operands (lane l:
+// trajectory b0 + l%16, offsets 4s + l/16).  Result lane l, register q holds
+// trajectory b0 + 4(l/16) + q, interval n0 + l%16.  The terms are fp32 in
+// (0, 1]; an output whose sum falls below 2^-100 (its support only reaches
+// terms near or under the fp32 range) is redone by iv_own_ref from the
+// predicate trace kept in LDS.
+constexpr int IVM_MAXT = 64;
+
+typedef float iv_f4 __attribute__((ext_vector_type(4)));
+
+template <int KS>
+__global__ void __launch_bounds__(IV_NT) stl_interval_mfma_kernel(IntervalArgs A)
+{
+    __shared__ float Ush[IV_NT / 64][16 * IVM_MAXT];   // per wave: 16 predicate traces
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, row4 = lane >> 4;
+    const int T = A.T, D = A.D;
+    const float bl = A.beta * LOG2E, sg = (float)A.op_sg;
+    const int64_t n = ((int64_t)blockIdx.x * (IV_NT / 64) + wv) * 16 + col;
+    const bool nok = n < A.N;
+    MaskP mp;
+    mp.a = nok ? A.a[n] : 0.f;
+    mp.b = nok ? A.b[n] : 1.f;
+    mp.c = A.mc;
+    mp.eps = A.meps;
+    mp.unb = false;
+    mp.band = 1.f - expf(-mp.c * (mp.b - mp.a));
+    float W[KS], Wa[KS], Wb[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + row4;
+        float da = 0.f, db = 0.f, w = 0.f;
+        if (nok && k < T) w = mask_wk(mp, k, &da, &db);
+        W[s] = w;
+        Wa[s] = da;
+        Wb[s] = db;
+    }
+    int lo, hi;
+    iv_range(mp.a, mp.b, mp.c, mp.eps, T, lo, hi);
+    float* Uw = Ush[wv];
+    const float ib = sg / A.beta;
+    for (int64_t b0 = (int64_t)blockIdx.y * 16; b0 < A.B; b0 += (int64_t)gridDim.y * 16) {
+        const int64_t bt = b0 + col;                  // this lane's A-operand trajectory
+        const bool bok = bt < A.B;
+        const float* xb = A.x + (bok ? bt : 0) * (int64_t)T * D;
+        float z[KS];
+        int zm = INT_MIN;
+        __syncthreads();                              // the previous tile's traces are no longer read
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + row4;
+            float u = 0.f;
+            if (bok && k < T) {
+                for (int d = 0; d < D; ++d) u = fmaf(A.w[d], xb[(int64_t)k * D + d], u);
+                u -= A.c;
+                zm = max(zm, (int)ceilf(fminf(fmaxf(sg * bl * u, -1e9f), 1e9f)));
+            }
+            z[s] = sg * bl * u;
+            Uw[col * IVM_MAXT + k] = u;               // k < 4 KS <= IVM_MAXT
+        }
+        zm = max(zm, __shfl_xor(zm, 16));
+        zm = max(zm, __shfl_xor(zm, 32));
+        iv_f4 s0 = {0.f, 0.f, 0.f, 0.f}, sa = s0, sb = s0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + row4;
+            const float e = (bok && k < T) ? exp2f(z[s] - (float)zm) : 0.f;
+            s0 = __builtin_amdgcn_mfma_f32_16x16x4f32(e, W[s], s0, 0, 0, 0);
+            sa = __builtin_amdgcn_mfma_f32_16x16x4f32(e, Wa[s], sa, 0, 0, 0);
+            sb = __builtin_amdgcn_mfma_f32_16x16x4f32(e, Wb[s], sb, 0, 0, 0);
+        }
+        __syncthreads();                              // traces visible to every lane of the wave
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * row4 + q;               // trajectory b0 + r
+            const int Rb = __shfl(zm, r);
+            const int64_t b = b0 + r;
+            if (b >= A.B || !nok) continue;
+            float rho = -sg * A.rho_pad, ga = 0.f, gb = 0.f;
+            const float S = s0[q];
+            if (S >= 0x1p-100f) {
+                rho = sg * ((float)Rb + log2f(S)) / bl;
+                const float iS = 1.f / S;
+                ga = ib * (sa[q] * iS);
+                gb = ib * (sb[q] * iS);
+            } else {
+                iv_own_ref(mp, Uw + r * IVM_MAXT, lo, hi, sg, bl, A.beta, rho, ga, gb);
+            }
+            const int64_t o = b * A.N + n;
+            A.rho[o] = rho;
+            if (A.ga) {
+                A.ga[o] = ga;
+                A.gb[o] = gb;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ pSTL descent
 
 // Gradient descent on the parametric-STL mining loss (Sec. VII-B)
@@ -374,6 +481,20 @@ hipError_t launch_interval_sweep(int op_sg, int smooth, float beta, float mc, fl
     A.c = c;
     A.rho_pad = rho_pad;
     for (int d = 0; d < 16; ++d) A.w[d] = d < D ? w[d] : 0.f;
+    if (smooth && T <= IVM_MAXT && B >= 16) {
+        // batched smooth sweep: matrix cores, 64 intervals per work-group; enough
+        // trajectory-tile groups for about 8192 work-groups
+        const int64_t nx = (N + 63) / 64, tiles = (B + 15) / 16;
+        const int64_t ny = std::max<int64_t>(1, std::min<int64_t>(tiles, std::min<int64_t>(65535, (8192 + nx - 1) / nx)));
+        const dim3 g((unsigned)nx, (unsigned)ny), blk(IV_NT);
+        if (T <= 20)
+            hipLaunchKernelGGL(stl_interval_mfma_kernel<5>, g, blk, 0, s, A);
+        else if (T <= 32)
+            hipLaunchKernelGGL(stl_interval_mfma_kernel<8>, g, blk, 0, s, A);
+        else
+            hipLaunchKernelGGL(stl_interval_mfma_kernel<16>, g, blk, 0, s, A);
+        return hipGetLastError();
+    }
     const int64_t groups = (B + A.tb - 1) / A.tb;
     const dim3 grid((unsigned)((N + IV_NT - 1) / IV_NT), (unsigned)std::min<int64_t>(groups, 65535)), block(IV_NT);
     if (group)

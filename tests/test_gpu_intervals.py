@@ -105,3 +105,41 @@ def test_interval_sweep_edges():
         stl.interval_sweep(xd, one, one, [1.0], mask_c=0.0)
     with pytest.raises(stl.StlError, match="T must be"):
         stl.interval_sweep(torch.zeros((1, 5000, 1), device="cuda"), one, one, [1.0])
+
+
+@pytest.mark.parametrize("T,B,N", [(20, 37, 500), (17, 16, 300), (32, 21, 200), (61, 18, 150)])
+@pytest.mark.parametrize("op", ["always", "eventually"])
+def test_interval_sweep_batched_matrix_cores(T, B, N, op):
+    """Batches of 16 or more trajectories with T <= 64 take the matrix-core
+    path (16 x 16 tiles of trajectories x intervals): ragged tiles on both
+    sides, T not a multiple of 4, every K-step count."""
+    rng = np.random.default_rng(100 + T)
+    x = walk(rng, B, T, D=2, s=0.2)
+    a, b = intervals(rng, N, T)
+    kw = dict(c=0.1, op=op, smooth=True, beta=10.0, mask_c=1.5, mask_eps=1e-6)
+    rho, ga, gb = run(x, a, b, [1.0, -0.5], **kw)
+    r0, ga0, gb0 = oracle.interval_sweep(x, a.astype(np.float64), b.astype(np.float64), [1.0, -0.5], **kw)
+    assert_close(rho, r0, what="batched sweep rho %s T=%d" % (op, T))
+    sc = 1.5 / (4 * 10.0)
+    assert_close(ga, ga0, scale=sc, what="batched sweep d/da")
+    assert_close(gb, gb0, scale=sc, what="batched sweep d/db")
+
+
+def test_interval_sweep_batched_range_fallback_and_eps0():
+    """Traces whose exponent range exceeds fp32 against the trajectory's
+    largest term: intervals whose support only sees terms far below it are
+    redone against their own reference.  eps = 0 keeps every offset; it is
+    checked on a trace of moderate range: the kernels' fp32 weights end near
+    e^-87 (the oracle's fp64 ones near e^-745), and a weight past that point
+    could only matter against a term more than e^87 above the others."""
+    rng = np.random.default_rng(9)
+    B, T = 20, 40
+    for s, eps in ((2.0, 1e-6), (0.3, 0.0)):   # s = 2: beta log2(e) |du| reaches well past 126
+        x = walk(rng, B, T, s=s)
+        a, b = intervals(rng, 300, T)
+        kw = dict(op="eventually", smooth=True, beta=10.0, mask_c=2.0, mask_eps=eps)
+        rho, ga, gb = run(x, a, b, [1.0], **kw)
+        r0, ga0, gb0 = oracle.interval_sweep(x, a.astype(np.float64), b.astype(np.float64), [1.0], **kw)
+        assert_close(rho, r0, what="range sweep rho eps=%g" % eps)
+        assert_close(ga, ga0, scale=2.0 / 40, what="range sweep d/da")
+        assert_close(gb, gb0, scale=2.0 / 40, what="range sweep d/db")
