@@ -159,10 +159,12 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_kernel(IntervalArgs A)
             double S[TB], Sa[TB], Sb[TB];
 #pragma unroll
             for (int t = 0; t < TB; ++t) S[t] = Sa[t] = Sb[t] = 0.0;
+            bool pos = false;                 // some offset has a positive weight
             for (int k = lo; k <= hi; ++k) {
                 float da, db;
                 const float w = mask_wk(mp, k, &da, &db);
                 if (!(w > 0.f)) continue;
+                pos = true;
 #pragma unroll
                 for (int t = 0; t < TB; ++t) {
                     const double e = t < nb ? E[t * T + k] : 0.0;
@@ -178,7 +180,7 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_kernel(IntervalArgs A)
                     rho[t] = sg * ((float)R[t] + log2d(S[t])) / bl;
                     ga[t] = (float)((double)(sg / A.beta) * (Sa[t] / S[t]));
                     gb[t] = (float)((double)(sg / A.beta) * (Sb[t] / S[t]));
-                } else {
+                } else if (pos) {
                     iv_own_ref(mp, U + t * T, lo, hi, sg, bl, A.beta, rho[t], ga[t], gb[t]);
                 }
             }
@@ -233,6 +235,7 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_mfma_kernel(IntervalArgs A
     mp.unb = false;
     mp.band = 1.f - expf(-mp.c * (mp.b - mp.a));
     float W[KS], Wa[KS], Wb[KS];
+    int pos = 0;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
         const int k = 4 * s + row4;
@@ -241,7 +244,12 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_mfma_kernel(IntervalArgs A
         W[s] = w;
         Wa[s] = da;
         Wb[s] = db;
+        pos |= w > 0.f;
     }
+    // an interval whose support misses [0, T) has the empty-window value on
+    // every trajectory: no sum and no fallback for it
+    pos |= __shfl_xor(pos, 16);
+    pos |= __shfl_xor(pos, 32);
     int lo, hi;
     iv_range(mp.a, mp.b, mp.c, mp.eps, T, lo, hi);
     float* Uw = Ush[wv];
@@ -290,7 +298,7 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_mfma_kernel(IntervalArgs A
                 const float iS = 1.f / S;
                 ga = ib * (sa[q] * iS);
                 gb = ib * (sb[q] * iS);
-            } else {
+            } else if (pos) {
                 iv_own_ref(mp, Uw + r * IVM_MAXT, lo, hi, sg, bl, A.beta, rho, ga, gb);
             }
             const int64_t o = b * A.N + n;
