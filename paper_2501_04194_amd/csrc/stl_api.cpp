@@ -572,6 +572,18 @@ stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch*
     size_t arena = (size_t)nslots * Lc + scratch_floats(Lc, nt, ub);
     size_t lds = arena * sizeof(float);
     bool global = (cfg && cfg->global_slots) || lds > di.lds_max;
+    if (!(cfg && cfg->threads) && bt->B < di.cus) {
+        // fewer trajectories than compute units (one work-group each): 512
+        // threads per work-group put more of the GPU to work, unless the
+        // larger Until checkpoint area would push the arena out of LDS
+        const size_t a2 = (size_t)nslots * Lc + scratch_floats(Lc, 512, ub);
+        const bool g2 = (cfg && cfg->global_slots) || a2 * sizeof(float) > di.lds_max;
+        if (g2 == global) {
+            nt = 512;
+            arena = a2;
+            lds = a2 * sizeof(float);
+        }
+    }
     int persistent = cfg ? (cfg->wg_per_cu > 0) : 0;
     int grid;
     if (global) {
