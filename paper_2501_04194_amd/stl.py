@@ -50,13 +50,14 @@ class Launch(ctypes.Structure):
                 ("flags", ctypes.c_int32)]
 
 
-_lib = None
 class IntervalDesc(ctypes.Structure):
     """stl_interval_desc"""
     _fields_ = [("op", ctypes.c_int32), ("smooth", ctypes.c_int32), ("beta", ctypes.c_float),
                 ("mask_c", ctypes.c_float), ("mask_eps", ctypes.c_float), ("D", ctypes.c_int32),
                 ("w", ctypes.c_float * 16), ("c", ctypes.c_float), ("rho_pad", ctypes.c_float)]
 
+
+_lib = None
 
 EXPORTS = ["stl_compile", "stl_plan_destroy", "stl_plan_info", "stl_workspace_size", "stl_forward",
            "stl_backward", "stl_saved_size", "stl_forward_saving", "stl_backward_saved", "stl_last_error",

@@ -5,7 +5,7 @@ its hand-off of trajectories it cannot take to the generic executor."""
 import numpy as np
 import pytest
 
-from gpu_util import Gpu, assert_close, check_formula, f32params
+from gpu_util import Gpu, assert_close, check_formula
 from paper_2501_04194_amd import stl, workloads as W
 
 pytestmark = pytest.mark.gpu

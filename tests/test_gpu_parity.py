@@ -310,7 +310,6 @@ def test_edge_cases():
     g = Gpu(ev(S1, 0, 5), 1)
     assert g.fwd(np.zeros((0, 10, 1), np.float32)).shape == (0, 10)
     # ragged batch with an empty trajectory
-    from paper_2501_04194_amd import workloads
     xp = sig(rng, 1, 30)[0]
     off = np.array([0, 10, 10, 30], dtype=np.int64)
     check_formula(ev(S1, 1, 4, smooth=True, beta=10.0), xp, offsets=off, T=20, what="ragged-empty")

@@ -2,7 +2,6 @@
 stabilization, strict ordering, sequenced visits, sequenced visit +
 stabilization, regions in any order) with synthetic linear predicates, hard
 and smooth, against the FP64 oracle, through the C ABI."""
-import numpy as np
 import pytest
 
 from gpu_util import check_formula

@@ -6,7 +6,6 @@ Sec. IV (built separately in numpy), brute force on tiny inputs, closed
 forms, the Boolean semantics (Sec. III-B), duality, associativity of
 logsumexp (Sec. IV-D) and central finite differences for every gradient.
 """
-import itertools
 import json
 import os
 
