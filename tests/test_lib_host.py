@@ -140,3 +140,17 @@ def test_param_vector_layout():
     assert v[names.index("ev_a")] == 100.0 and v[names.index("al_b")] == 400.0
     g = p.param_grads(np.arange(p.n_params, dtype=np.float32))
     assert g["ev_a"] == names.index("ev_a")
+
+
+def test_compile_coefficient_budget():
+    """Predicate coefficients and per-window pad values share one table in the
+    plan: a formula that overflows it is rejected, one that fits compiles."""
+    D = 16
+    lin = lambda k: {"op": "linear", "w": [1.0 if d == k else 0.0 for d in range(D)], "c": 0.1 * k}
+    win = lambda k: {"op": "eventually", "a": 0, "b": 3, "pad": "const", "pad_value": 0.5, "child": lin(k)}
+    # 9 predicates use 9 * (1 + D) = 153 floats; 8 windows add one pad value each
+    over = {"op": "and", "children": [lin(8), {"op": "and", "children": [win(k) for k in range(8)]}]}
+    with pytest.raises(stl.StlError, match="coefficients"):
+        stl.Plan(over, D)
+    fits = {"op": "and", "children": [lin(8), {"op": "and", "children": [win(k) for k in range(7)]}]}
+    assert stl.Plan(fits, D).n_nodes == 17
