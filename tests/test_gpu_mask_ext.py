@@ -176,3 +176,28 @@ def test_mask_pads_on_the_fused_shape():
     # the pad changes the outputs whose Eventually window reaches past the end
     assert np.abs(got[:, -300:] - ref[:, -300:]).max() > 1e-4
     assert_close(got[:, :400], ref[:, :400], what="outputs away from the end")
+
+
+def test_masked_until_and_pads_in_global_arenas():
+    """The same operators with the slot arena in global memory (forced by the
+    launch configuration, and by a trajectory too long for LDS): the Until
+    sums and the pad tables then live behind global pointers."""
+    from paper_2501_04194_amd import stl
+    rng = np.random.default_rng(51)
+    glob = stl.Launch(256, 2, 1, 0)
+    x = walk(rng, 3, 420, D=2, s=0.1)
+    m = (5.3, 60.7, 1.0, 1e-6)
+    check_formula(until(m), x, params=mparams(m[0], m[1]), launch=glob, what="global masked until")
+    check_formula(until(m, smooth=False, right={"op": "linear", "w": [0.0, 1.0], "c": 0.25}), x,
+                  params=mparams(m[0], m[1]), launch=glob, bitexact_root=True, what="global hard masked until")
+    xs = walk(rng, 3, 700, s=0.05)
+    for pad in ("last", "const"):
+        spec = {"op": "always", "smooth": True, "beta": 10.0, "child": S1, "mask": mask(100.0, 400.0, 1.0, 1e-6),
+                "pad": pad, "pad_value": 0.3}
+        check_formula(spec, xs, params=mparams(100.0, 400.0), launch=glob, what="global mask pad %s" % pad)
+    # long trajectories: the arena does not fit in LDS at this length
+    xl = walk(rng, 2, 2600, D=2, s=0.05)
+    check_formula(until((12.5, 140.5, 1.0, 1e-6)), xl, params=mparams(12.5, 140.5), what="long masked until")
+    spec = {"op": "eventually", "smooth": True, "beta": 10.0, "child": PHI, "mask": mask(2400.0, 2900.0, 1.0, 1e-6),
+            "pad": "last"}
+    check_formula(spec, xl, params=mparams(2400.0, 2900.0), what="long mask pad")
