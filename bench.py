@@ -83,7 +83,7 @@ def bench_graph(args):
         offsets = None
         n_steps = B * T
         bpstep = (4 * D + 4) + (4 * D + 4 + 4 * D)     # fwd (x + root) + bwd (x + G + dx)
-        cfg = {"workload": W.CONFIGS[1]["name"], "B": B, "T": T, "D": D, "beta": 10.0}
+        cfg = {"workload": W.WORKLOADS[1]["name"], "B": B, "T": T, "D": D, "beta": 10.0}
     else:
         spec, params, x, offsets = W.ragged_workload()
         B = len(offsets) - 1
@@ -91,7 +91,7 @@ def bench_graph(args):
         T = int(np.max(np.diff(offsets)))
         n_steps = int(offsets[-1])
         bpstep = (4 * D + 4) + (4 * D + 4 + 4 * D)
-        cfg = {"workload": W.CONFIGS[3]["name"], "trajectories": B, "total_steps": n_steps, "D": D,
+        cfg = {"workload": W.WORKLOADS[3]["name"], "trajectories": B, "total_steps": n_steps, "D": D,
                "max_len": T, "beta": 10.0}
     plan = stl.Plan(spec, D, params)
     pv = torch.from_numpy(plan.param_vector()).to(dev)
@@ -360,7 +360,7 @@ def main():
     ap.add_argument("--interval-batch", type=int, default=1, help="signals per interval sweep (--workload intervals)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (trajectories shard with no "
+        print("bench.py measures one GPU: the library has no multi-GPU path (trajectories shard with no "
               "communication; see the design notes).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:

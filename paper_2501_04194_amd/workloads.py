@@ -135,7 +135,7 @@ def cfg2_params():
             "al_a": 100.0, "al_b": 400.0, "al_c": 1.0, "al_eps": 1e-6}
 
 
-CONFIGS = {
+WORKLOADS = {
     0: dict(name="hard_B16_T100_D2", B=16, T=100, D=2, sigma=0.1, seed=0),
     1: dict(name="smooth_until_B1024_T1000_D4", B=1024, T=1000, D=4, sigma=0.05, seed=1),
     2: dict(name="smooth_mask_B4096_T2048_D2", B=4096, T=2048, D=2, sigma=0.05, seed=2),
@@ -146,7 +146,7 @@ CONFIGS = {
 
 def workload(k: int, B: int | None = None, T: int | None = None):
     """(formula, params, x) for benchmark workload k (0, 1 or 2); B/T may shrink it."""
-    c = CONFIGS[k]
+    c = WORKLOADS[k]
     B = c["B"] if B is None else B
     T = c["T"] if T is None else T
     x = random_walks(c["seed"], B, T, c["D"], c["sigma"])
@@ -161,7 +161,7 @@ def workload(k: int, B: int | None = None, T: int | None = None):
 
 def ragged_workload(n: int | None = None, seed: int | None = None):
     """(formula, params, x_packed, offsets) for the ragged workload."""
-    c = CONFIGS[3]
+    c = WORKLOADS[3]
     x, off = ragged_walks(c["seed"] if seed is None else seed, c["N"] if n is None else n,
                           c["lmin"], c["lmax"], c["D"], c["sigma"])
     return cfg1_formula(c["D"]), {}, x, off
