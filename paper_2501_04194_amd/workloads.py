@@ -19,9 +19,13 @@ the formula; named entries are the learnable (or annealable) scalars.
    "smooth": bool, "beta": num, "pad": "neutral" | "last" | "const",
    "pad_value": float}
   {"op": "eventually" | "always", "child": f, "mask": {"a": num, "b": num | None,
-   "c": num, "eps": num}, "smooth": bool, "beta": num}
+   "c": num, "eps": num}, "smooth": bool, "beta": num, "pad": ..., "pad_value": float}
   {"op": "until", "left": f, "right": f, "a": int, "b": int | None,
    "smooth": bool, "beta": num}
+  {"op": "until", "left": f, "right": f, "mask": {...}, "smooth": bool, "beta": num}
+
+A smooth mask replaces the integer interval; on Until it weights the Until
+index (the right operand's offset).
 
 ``"smooth": "softmax"`` selects the softmax-weighted smooth max/min of
 Sec. III-C (sum v exp(beta v) / sum exp(beta v)) on and/or and on unmasked
