@@ -573,15 +573,19 @@ stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch*
     size_t lds = arena * sizeof(float);
     bool global = (cfg && cfg->global_slots) || lds > di.lds_max;
     if (!(cfg && cfg->threads) && bt->B < di.cus) {
-        // fewer trajectories than compute units (one work-group each): 512
-        // threads per work-group put more of the GPU to work, unless the
-        // larger Until checkpoint area would push the arena out of LDS
-        const size_t a2 = (size_t)nslots * Lc + scratch_floats(Lc, 512, ub);
+        // fewer trajectories than compute units (one work-group each): size
+        // the work-group to the trajectory (measured on MI355X: 64 threads
+        // for T <= 64, 128 up to 128, 256 up to 256, 512 beyond), but keep
+        // 256 where the larger Until checkpoint area of 512 threads would
+        // push the arena out of LDS
+        const int want = bt->T <= 64 ? 64 : bt->T <= 128 ? 128 : bt->T <= 256 ? 256 : 512;
+        const size_t a2 = (size_t)nslots * Lc + scratch_floats(Lc, want, ub);
         const bool g2 = (cfg && cfg->global_slots) || a2 * sizeof(float) > di.lds_max;
-        if (g2 == global) {
-            nt = 512;
+        if (want < 256 || g2 == global) {
+            nt = want;
             arena = a2;
             lds = a2 * sizeof(float);
+            global = g2;
         }
     }
     int persistent = cfg ? (cfg->wg_per_cu > 0) : 0;
