@@ -143,3 +143,27 @@ def test_interval_sweep_batched_range_fallback_and_eps0():
         assert_close(rho, r0, what="range sweep rho eps=%g" % eps)
         assert_close(ga, ga0, scale=2.0 / 40, what="range sweep d/da")
         assert_close(gb, gb0, scale=2.0 / 40, what="range sweep d/db")
+
+
+@pytest.mark.parametrize("B", [1, 3])
+def test_interval_sweep_maximum_length(B):
+    """T = 4096, the sweep's maximum: the whole trace's terms fill the LDS
+    array of one work-group; intervals near both ends and past the end."""
+    rng = np.random.default_rng(40 + B)
+    x = walk(rng, B, 4096, s=0.05)
+    a = np.array([0.0, 100.0, 1999.5, 3000.5, 4090.0, 4200.0, -50.0, 10.0, 2047.0, 4000.0, 512.0, 3500.0],
+                 dtype=np.float32)
+    b = np.array([5.0, 1500.0, 2010.5, 4200.0, 5000.0, 4300.0, 30.0, 4095.0, 2049.0, 4095.5, 1024.0, 3400.0],
+                 dtype=np.float32)
+    for op in ("eventually", "always"):
+        kw = dict(op=op, smooth=True, beta=10.0, mask_c=1.0, mask_eps=1e-6)
+        rho, ga, gb = run(x, a, b, [1.0], **kw)
+        r0, ga0, gb0 = oracle.interval_sweep(x, a.astype(np.float64), b.astype(np.float64), [1.0], **kw)
+        assert_close(rho, r0, what="T=4096 sweep rho %s" % op)
+        assert_close(ga, ga0, scale=1.0 / 40, what="T=4096 d/da")
+        assert_close(gb, gb0, scale=1.0 / 40, what="T=4096 d/db")
+    kw = dict(op="always", smooth=False, mask_c=50.0, mask_eps=1e-6)
+    rho, _, _ = run(x, np.floor(a) - 0.5, np.floor(b) + 0.5, [1.0], **kw)
+    r0, _, _ = oracle.interval_sweep(x, (np.floor(a) - 0.5).astype(np.float64), (np.floor(b) + 0.5).astype(np.float64),
+                                     [1.0], **kw)
+    assert np.array_equal(rho.astype(np.float32), r0.astype(np.float32))
