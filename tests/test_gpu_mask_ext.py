@@ -201,3 +201,24 @@ def test_masked_until_and_pads_in_global_arenas():
     spec = {"op": "eventually", "smooth": True, "beta": 10.0, "child": PHI, "mask": mask(2400.0, 2900.0, 1.0, 1e-6),
             "pad": "last"}
     check_formula(spec, xl, params=mparams(2400.0, 2900.0), what="long mask pad")
+
+
+def test_mask_ext_length_one_and_two():
+    """Trajectories of one and two samples: masks whose support starts past
+    the end, pads that supply every term, and a masked Until with i = 0 only."""
+    rng = np.random.default_rng(52)
+    for L in (1, 2):
+        x1 = walk(rng, 3, L, s=0.3)
+        x2 = walk(rng, 3, L, D=2, s=0.3)
+        cases = [
+            ({"op": "eventually", "smooth": True, "beta": 10.0, "child": S1, "mask": mask(3.0, 9.0, 1.0, 1e-6),
+              "pad": "last"}, x1, mparams(3.0, 9.0)),
+            ({"op": "always", "smooth": True, "beta": 10.0, "child": S1, "mask": mask(0.0, 4.0, 2.0, 1e-6),
+              "pad": "const", "pad_value": -0.2}, x1, mparams(0.0, 4.0)),
+            ({"op": "eventually", "smooth": "softmax", "beta": 4.0, "child": S1, "a": 0, "b": 5, "pad": "last"},
+             x1, {}),
+            (until((0.0, 3.0, 2.0, 1e-6)), x2, mparams(0.0, 3.0)),
+            (until((-3.0, 0.4, 3.0, 1e-6)), x2, mparams(-3.0, 0.4)),
+        ]
+        for spec, x, params in cases:
+            check_formula(spec, x, params=params, what="L=%d %s" % (L, spec["op"]))
