@@ -222,3 +222,34 @@ def test_mask_ext_length_one_and_two():
         ]
         for spec, x, params in cases:
             check_formula(spec, x, params=params, what="L=%d %s" % (L, spec["op"]))
+
+
+def test_graph_replay_masked_until_and_pads():
+    """A formula with a masked Until and a padded smooth mask captured in a
+    HIP graph: every replay matches the eager calls (to the rounding of the
+    Until adjoint's cross-wave atomic sums), with eager work between replays."""
+    import torch
+    from paper_2501_04194_amd import stl
+    rng = np.random.default_rng(53)
+    x = walk(rng, 6, 500, D=2, s=0.08)
+    spec = {"op": "and", "smooth": True, "beta": 5.0, "children": [
+        {"op": "until", "smooth": True, "beta": 8.0, "left": PHI, "right": PSI,
+         "mask": {"a": "ua", "b": "ub", "c": 1.0, "eps": 1e-6}},
+        {"op": "always", "smooth": True, "beta": 8.0, "child": PSI, "pad": "last",
+         "mask": {"a": "wa", "b": "wb", "c": 0.7, "eps": 1e-6}}]}
+    g = Gpu(spec, 2, {"ua": 10.2, "ub": 70.9, "wa": 300.1, "wb": 525.6})
+    xt = torch.from_numpy(x).cuda()
+    G = torch.randn(x.shape[:2], device="cuda")
+    r_e = g.plan.forward(xt, g.pv)
+    d_e, p_e = g.plan.backward(xt, G, g.pv)
+    gr = stl.Graph(g.plan, xt, g.pv, G)
+    for rep in range(3):
+        gr.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(gr.root.view_as(r_e), r_e)
+        assert torch.allclose(gr.dx, d_e, rtol=1e-5, atol=1e-6 * float(d_e.abs().max()))
+        assert torch.allclose(gr.gp, p_e, rtol=1e-5, atol=1e-6 * float(p_e.abs().max()))
+        xt.add_(0.01)
+        r_e = g.plan.forward(xt, g.pv)
+        d_e, p_e = g.plan.backward(xt, G, g.pv)
+        torch.cuda.synchronize()
