@@ -253,3 +253,18 @@ def test_graph_replay_masked_until_and_pads():
         r_e = g.plan.forward(xt, g.pv)
         d_e, p_e = g.plan.backward(xt, G, g.pv)
         torch.cuda.synchronize()
+
+
+def test_mask_pads_ragged():
+    """Pads on a smooth mask in a ragged batch: the tail past each trajectory's
+    own end depends on its length (lengths 1, 37, 400, 0 and 901)."""
+    rng = np.random.default_rng(54)
+    off = np.array([0, 1, 38, 438, 438, 1339], dtype=np.int64)
+    xp = walk(rng, 1, 1339, s=0.05)[0]
+    for pad, kind in (("last", "eventually"), ("const", "always")):
+        spec = {"op": kind, "smooth": True, "beta": 10.0, "child": S1, "mask": mask(20.0, 150.0, 1.0, 1e-6),
+                "pad": pad, "pad_value": -0.1}
+        check_formula(spec, xp, params=mparams(20.0, 150.0), offsets=off, T=901, what="ragged mask pad %s" % pad)
+    spec = until((15.5, 90.5, 1.0, 1e-6))
+    xp2 = walk(rng, 1, 1339, D=2, s=0.05)[0]
+    check_formula(spec, xp2, params=mparams(15.5, 90.5), offsets=off, T=901, what="ragged masked until")
