@@ -268,3 +268,32 @@ def test_mask_pads_ragged():
     spec = until((15.5, 90.5, 1.0, 1e-6))
     xp2 = walk(rng, 1, 1339, D=2, s=0.05)[0]
     check_formula(spec, xp2, params=mparams(15.5, 90.5), offsets=off, T=901, what="ragged masked until")
+
+
+def test_saved_traces_with_a_padded_mask():
+    """The saved-trace pair on the fused formula shape with a padded mask: the
+    forward does not take the fused path, marks its saved rows invalid, and the
+    backward recomputes, matching the plain pair bit for bit."""
+    rng = np.random.default_rng(55)
+    x = walk(rng, 4, 900, D=2, s=0.05)
+    spec = {"op": "and", "smooth": True, "beta": 10.0, "children": [
+        {"op": "eventually", "smooth": True, "beta": 10.0, "child": PHI, "pad": "const", "pad_value": 0.2,
+         "mask": {"a": "ea", "b": "eb", "c": 1.0, "eps": 1e-6}},
+        {"op": "always", "smooth": True, "beta": 10.0, "child": PSI,
+         "mask": {"a": "la", "b": "lb", "c": 1.0, "eps": 1e-6}}]}
+    g = Gpu(spec, 2, {"ea": 100.0, "eb": 400.0, "la": 50.0, "lb": 200.0})
+    G = rng.normal(size=(4, 900)).astype(np.float32)
+    r0 = g.fwd(x)
+    d0, p0 = g.bwd(x, G)
+    t = g.torch
+    xd = t.from_numpy(x).cuda()
+    sv = g.plan.saved_buffer(xd)
+    sv.fill_(0xAB)
+    r1 = g.plan.forward(xd, g.pv, saved=sv)
+    d1, gp1 = g.plan.backward(xd, t.from_numpy(G).cuda(), g.pv, saved=sv)
+    t.cuda.synchronize()
+    assert np.array_equal(r0, r1.cpu().numpy())
+    assert np.array_equal(d0, d1.cpu().numpy())
+    p1 = g.plan.param_grads(gp1.cpu().numpy())
+    for k in p0:
+        assert p0[k] == p1[k], k
