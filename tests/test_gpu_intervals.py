@@ -167,3 +167,19 @@ def test_interval_sweep_maximum_length(B):
     r0, _, _ = oracle.interval_sweep(x, (np.floor(a) - 0.5).astype(np.float64), (np.floor(b) + 0.5).astype(np.float64),
                                      [1.0], **kw)
     assert np.array_equal(rho.astype(np.float32), r0.astype(np.float32))
+
+
+def test_interval_sweep_batched_wide_state():
+    """The matrix-core path with the widest state (D = 16): each lane's
+    predicate reads 16 strided coefficients per offset."""
+    rng = np.random.default_rng(12)
+    B, T, D = 19, 24, 16
+    x = walk(rng, B, T, D=D, s=0.05)
+    w = list(rng.normal(size=D) * 0.3)
+    a, b = intervals(rng, 130, T)
+    kw = dict(c=-0.05, op="always", smooth=True, beta=10.0, mask_c=1.2, mask_eps=1e-6)
+    rho, ga, gb = run(x, a, b, w, **kw)
+    r0, ga0, gb0 = oracle.interval_sweep(x, a.astype(np.float64), b.astype(np.float64), w, **kw)
+    assert_close(rho, r0, what="D=16 batched sweep rho")
+    assert_close(ga, ga0, scale=1.2 / 40, what="D=16 d/da")
+    assert_close(gb, gb0, scale=1.2 / 40, what="D=16 d/db")
