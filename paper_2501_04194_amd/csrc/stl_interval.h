@@ -205,15 +205,17 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_kernel(IntervalArgs A)
 // exponent), S_bn = sum_k w_nk E_bk and the same sums with dw/da, dw/db are
 // three products of the [B, T] term matrix with the [T, N] weight matrices,
 // which v_mfma_f32_16x16x4f32 computes 16 x 16 outputs at a time (K = 4 per
-// instruction).  A wave owns 16 intervals: it evaluates their weights once,
-// as B operands (lane l: interval n0 + l%16, offsets 4s + l/16), then walks
-// tiles of 16 trajectories, whose terms are the A operands (lane l:
-// trajectory b0 + l%16, offsets 4s + l/16).  Result lane l, register q holds
-// trajectory b0 + 4(l/16) + q, interval n0 + l%16.  The terms are fp32 in
+// instruction).  A wave owns IVM_NT tiles of 16 intervals: it evaluates their
+// weights once, as B operands (lane l: interval n0 + 16j + l%16, offsets
+// 4s + l/16), then walks tiles of 16 trajectories, whose terms are the A
+// operands (lane l: trajectory b0 + l%16, offsets 4s + l/16) shared by all
+// its interval tiles.  Result lane l, register q of tile j holds trajectory
+// b0 + 4(l/16) + q, interval n0 + 16j + l%16.  The terms are fp32 in
 // (0, 1]; an output whose sum falls below 2^-100 (its support only reaches
 // terms near or under the fp32 range) is redone by iv_own_ref from the
 // predicate trace kept in LDS.
 constexpr int IVM_MAXT = 64;
+constexpr int IVM_NT = 2;          // 16-interval tiles per wave (the terms of a trajectory tile serve them all)
 
 typedef float iv_f4 __attribute__((ext_vector_type(4)));
 
@@ -225,33 +227,40 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_mfma_kernel(IntervalArgs A
     const int col = lane & 15, row4 = lane >> 4;
     const int T = A.T, D = A.D;
     const float bl = A.beta * LOG2E, sg = (float)A.op_sg;
-    const int64_t n = ((int64_t)blockIdx.x * (IV_NT / 64) + wv) * 16 + col;
-    const bool nok = n < A.N;
-    MaskP mp;
-    mp.a = nok ? A.a[n] : 0.f;
-    mp.b = nok ? A.b[n] : 1.f;
-    mp.c = A.mc;
-    mp.eps = A.meps;
-    mp.unb = false;
-    mp.band = 1.f - expf(-mp.c * (mp.b - mp.a));
-    float W[KS], Wa[KS], Wb[KS];
-    int pos = 0;
+    // this wave's IVM_NT interval tiles: intervals n0 + 16 j + col
+    const int64_t n0 = ((int64_t)blockIdx.x * (IV_NT / 64) + wv) * (16 * IVM_NT);
+    MaskP mp[IVM_NT];
+    bool nok[IVM_NT];
+    int lo[IVM_NT], hi[IVM_NT], pos[IVM_NT];
+    float W[IVM_NT][KS], Wa[IVM_NT][KS], Wb[IVM_NT][KS];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        const int k = 4 * s + row4;
-        float da = 0.f, db = 0.f, w = 0.f;
-        if (nok && k < T) w = mask_wk(mp, k, &da, &db);
-        W[s] = w;
-        Wa[s] = da;
-        Wb[s] = db;
-        pos |= w > 0.f;
+    for (int j = 0; j < IVM_NT; ++j) {
+        const int64_t n = n0 + 16 * j + col;
+        nok[j] = n < A.N;
+        mp[j].a = nok[j] ? A.a[n] : 0.f;
+        mp[j].b = nok[j] ? A.b[n] : 1.f;
+        mp[j].c = A.mc;
+        mp[j].eps = A.meps;
+        mp[j].unb = false;
+        mp[j].band = 1.f - expf(-mp[j].c * (mp[j].b - mp[j].a));
+        int p = 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + row4;
+            float da = 0.f, db = 0.f, w = 0.f;
+            if (nok[j] && k < T) w = mask_wk(mp[j], k, &da, &db);
+            W[j][s] = w;
+            Wa[j][s] = da;
+            Wb[j][s] = db;
+            p |= w > 0.f;
+        }
+        // an interval whose support misses [0, T) has the empty-window value on
+        // every trajectory: no sum and no fallback for it
+        p |= __shfl_xor(p, 16);
+        p |= __shfl_xor(p, 32);
+        pos[j] = p;
+        iv_range(mp[j].a, mp[j].b, mp[j].c, mp[j].eps, T, lo[j], hi[j]);
     }
-    // an interval whose support misses [0, T) has the empty-window value on
-    // every trajectory: no sum and no fallback for it
-    pos |= __shfl_xor(pos, 16);
-    pos |= __shfl_xor(pos, 32);
-    int lo, hi;
-    iv_range(mp.a, mp.b, mp.c, mp.eps, T, lo, hi);
     float* Uw = Ush[wv];
     const float ib = sg / A.beta;
     for (int64_t b0 = (int64_t)blockIdx.y * 16; b0 < A.B; b0 += (int64_t)gridDim.y * 16) {
@@ -275,14 +284,19 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_mfma_kernel(IntervalArgs A
         }
         zm = max(zm, __shfl_xor(zm, 16));
         zm = max(zm, __shfl_xor(zm, 32));
-        iv_f4 s0 = {0.f, 0.f, 0.f, 0.f}, sa = s0, sb = s0;
+        iv_f4 s0[IVM_NT], sa[IVM_NT], sb[IVM_NT];
+#pragma unroll
+        for (int j = 0; j < IVM_NT; ++j) s0[j] = sa[j] = sb[j] = iv_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int k = 4 * s + row4;
             const float e = (bok && k < T) ? exp2f(z[s] - (float)zm) : 0.f;
-            s0 = __builtin_amdgcn_mfma_f32_16x16x4f32(e, W[s], s0, 0, 0, 0);
-            sa = __builtin_amdgcn_mfma_f32_16x16x4f32(e, Wa[s], sa, 0, 0, 0);
-            sb = __builtin_amdgcn_mfma_f32_16x16x4f32(e, Wb[s], sb, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < IVM_NT; ++j) {
+                s0[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, W[j][s], s0[j], 0, 0, 0);
+                sa[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, Wa[j][s], sa[j], 0, 0, 0);
+                sb[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, Wb[j][s], sb[j], 0, 0, 0);
+            }
         }
         __syncthreads();                              // traces visible to every lane of the wave
 #pragma unroll
@@ -290,22 +304,26 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_mfma_kernel(IntervalArgs A
             const int r = 4 * row4 + q;               // trajectory b0 + r
             const int Rb = __shfl(zm, r);
             const int64_t b = b0 + r;
-            if (b >= A.B || !nok) continue;
-            float rho = -sg * A.rho_pad, ga = 0.f, gb = 0.f;
-            const float S = s0[q];
-            if (S >= 0x1p-100f) {
-                rho = sg * ((float)Rb + log2f(S)) / bl;
-                const float iS = 1.f / S;
-                ga = ib * (sa[q] * iS);
-                gb = ib * (sb[q] * iS);
-            } else if (pos) {
-                iv_own_ref(mp, Uw + r * IVM_MAXT, lo, hi, sg, bl, A.beta, rho, ga, gb);
-            }
-            const int64_t o = b * A.N + n;
-            A.rho[o] = rho;
-            if (A.ga) {
-                A.ga[o] = ga;
-                A.gb[o] = gb;
+            if (b >= A.B) continue;
+#pragma unroll
+            for (int j = 0; j < IVM_NT; ++j) {
+                if (!nok[j]) continue;
+                float rho = -sg * A.rho_pad, ga = 0.f, gb = 0.f;
+                const float S = s0[j][q];
+                if (S >= 0x1p-100f) {
+                    rho = sg * ((float)Rb + log2f(S)) / bl;
+                    const float iS = 1.f / S;
+                    ga = ib * (sa[j][q] * iS);
+                    gb = ib * (sb[j][q] * iS);
+                } else if (pos[j]) {
+                    iv_own_ref(mp[j], Uw + r * IVM_MAXT, lo[j], hi[j], sg, bl, A.beta, rho, ga, gb);
+                }
+                const int64_t o = b * A.N + n0 + 16 * j + col;
+                A.rho[o] = rho;
+                if (A.ga) {
+                    A.ga[o] = ga;
+                    A.gb[o] = gb;
+                }
             }
         }
     }
@@ -490,9 +508,9 @@ hipError_t launch_interval_sweep(int op_sg, int smooth, float beta, float mc, fl
     A.rho_pad = rho_pad;
     for (int d = 0; d < 16; ++d) A.w[d] = d < D ? w[d] : 0.f;
     if (smooth && T <= IVM_MAXT && B >= 16) {
-        // batched smooth sweep: matrix cores, 64 intervals per work-group; enough
+        // batched smooth sweep: matrix cores, 64 IVM_NT intervals per work-group; enough
         // trajectory-tile groups for about 8192 work-groups
-        const int64_t nx = (N + 63) / 64, tiles = (B + 15) / 16;
+        const int64_t nx = (N + 64 * IVM_NT - 1) / (64 * IVM_NT), tiles = (B + 15) / 16;
         const int64_t ny = std::max<int64_t>(1, std::min<int64_t>(tiles, std::min<int64_t>(65535, (8192 + nx - 1) / nx)));
         const dim3 g((unsigned)nx, (unsigned)ny), blk(IV_NT);
         if (T <= 20)
