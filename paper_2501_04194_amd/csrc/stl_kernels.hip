@@ -1706,7 +1706,16 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
         const int64_t b = ka.list_mode ? (int64_t)ka.list[item] : (bt.order ? (int64_t)bt.order[item] : item);
         const int64_t off = bt.offsets ? bt.offsets[b] : b * bt.T;
         const int64_t len = bt.offsets ? bt.offsets[b + 1] - off : bt.T;
-        if (len <= 0) continue;
+        if (len <= 0) {
+            // an empty trajectory adds nothing to d/da, d/db: its partials
+            // are still read by the reduction
+            if (BWD && threadIdx.x == 0)
+                for (int m = 0; m < P->n_masks; ++m) {
+                    ka.mask_part[(b * P->n_masks + m) * 2] = 0.f;
+                    ka.mask_part[(b * P->n_masks + m) * 2 + 1] = 0.f;
+                }
+            continue;
+        }
         if (len > Lc) {
             // trajectory longer than the launch's capacity: report NaN
             for (int64_t t = threadIdx.x; t < len; t += blockDim.x) {

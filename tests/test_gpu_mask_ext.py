@@ -297,3 +297,26 @@ def test_saved_traces_with_a_padded_mask():
     p1 = g.plan.param_grads(gp1.cpu().numpy())
     for k in p0:
         assert p0[k] == p1[k], k
+
+
+def test_empty_trajectory_mask_partials_with_poisoned_workspace():
+    """An empty trajectory in a ragged batch writes zero mask-bound partials:
+    the workspace is filled with huge values before the backward, so a
+    partial left unwritten would show in d/da, d/db."""
+    import torch
+    rng = np.random.default_rng(56)
+    off = np.array([0, 40, 40, 300], dtype=np.int64)
+    xp = walk(rng, 1, 300, s=0.05)[0]
+    spec = {"op": "eventually", "smooth": True, "beta": 10.0, "child": S1, "mask": mask(5.0, 30.0, 1.0, 1e-6)}
+    params = mparams(5.0, 30.0)
+    g = Gpu(spec, 1, params)
+    g.fwd(xp, offsets=off, T=260)
+    for ws in g.plan._ws.values():
+        ws.fill_(0x7F)                      # every float reads 3.4e38
+    torch.cuda.synchronize()
+    G = rng.normal(size=300).astype(np.float32)
+    dx, dp = g.bwd(xp, G, offsets=off, T=260)
+    _, dp_ref = oracle.backward(spec, xp, G, params=params, offsets=off)
+    _, dp_abs = oracle.backward(spec, xp, np.abs(G), params=params, offsets=off)
+    for k in dp_ref:
+        assert abs(dp[k] - dp_ref[k]) <= 1e-5 * abs(dp_abs[k]) + 1e-12, (k, dp[k], dp_ref[k])
