@@ -178,8 +178,9 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_kernel(IntervalArgs A)
                 if (t >= nb) continue;
                 if (S[t] > 0.0) {
                     rho[t] = sg * ((float)R[t] + log2d(S[t])) / bl;
-                    ga[t] = (float)((double)(sg / A.beta) * (Sa[t] / S[t]));
-                    gb[t] = (float)((double)(sg / A.beta) * (Sb[t] / S[t]));
+                    const double iS = (double)(sg / A.beta) / S[t];   // one division for both ratios
+                    ga[t] = (float)(iS * Sa[t]);
+                    gb[t] = (float)(iS * Sb[t]);
                 } else if (pos) {
                     iv_own_ref(mp, U + t * T, lo, hi, sg, bl, A.beta, rho[t], ga[t], gb[t]);
                 }
