@@ -200,7 +200,8 @@ def bench_intervals(args):
            "config": {"workload": "interval_sweep_T20_N90000", "signals": B, "T": T, "intervals": N,
                       "grid": "300 x 300 (a, b) fractions, a = a_frac T", "beta": 10.0, "mask_c": 1.0,
                       "mask_eps": 1e-6},
-           "roofline": {"bound": "alu", "kernel": "stl_interval_kernel", "achieved": achieved,
+           "roofline": {"bound": "alu", "kernel": "stl_interval_split_kernel" if B <= 2 else "stl_interval_kernel",
+                        "achieved": achieved,
                         "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                         "traffic": None, "terms": terms}}
     if B >= 16:

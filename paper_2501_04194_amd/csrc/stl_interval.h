@@ -199,6 +199,91 @@ __global__ void __launch_bounds__(IV_NT) stl_interval_kernel(IntervalArgs A)
     }
 }
 
+// Smooth sweep of one or two trajectories: with one thread per interval the
+// launch holds too few waves to cover the latency of each thread's serial
+// walk over its offsets, so IVS_LPI consecutive lanes share an interval (lane
+// r takes offsets lo + r, lo + r + IVS_LPI, ...) and add their partial sums
+// with lane exchanges; the first lane of the group writes the outputs.
+constexpr int IVS_LPI = 4;
+
+__global__ void __launch_bounds__(IV_NT) stl_interval_split_kernel(IntervalArgs A)
+{
+    __shared__ double E[IV_MAXT];
+    __shared__ float U[IV_MAXT];
+    __shared__ int red[IV_NT / 64];
+    const int T = A.T, D = A.D;
+    const float bl = A.beta * LOG2E, sg = (float)A.op_sg;
+    const int64_t gi = (int64_t)blockIdx.x * IV_NT + threadIdx.x;
+    const int64_t n = gi / IVS_LPI;
+    const int r = (int)(gi % IVS_LPI);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool nok = n < A.N;
+    MaskP mp;
+    mp.a = nok ? A.a[n] : 0.f;
+    mp.b = nok ? A.b[n] : 1.f;
+    mp.c = A.mc;
+    mp.eps = A.meps;
+    mp.unb = false;
+    mp.band = 1.f - expf(-mp.c * (mp.b - mp.a));
+    int lo, hi;
+    iv_range(mp.a, mp.b, mp.c, mp.eps, T, lo, hi);
+    for (int64_t b = blockIdx.y; b < A.B; b += gridDim.y) {
+        __syncthreads();                   // the previous trajectory's terms are no longer read
+        const float* xb = A.x + b * (int64_t)T * D;
+        int zmax = INT_MIN;
+        for (int j = threadIdx.x; j < T; j += IV_NT) {
+            float u = 0.f;
+            for (int d = 0; d < D; ++d) u = fmaf(A.w[d], xb[(int64_t)j * D + d], u);
+            u -= A.c;
+            U[j] = u;
+            zmax = max(zmax, (int)ceilf(fminf(fmaxf(sg * bl * u, -1e9f), 1e9f)));
+        }
+        for (int d = 32; d > 0; d >>= 1) zmax = max(zmax, __shfl_xor(zmax, d));
+        if (lane == 0) red[wv] = zmax;
+        __syncthreads();
+        int R = INT_MIN;
+        for (int k = 0; k < IV_NT / 64; ++k) R = max(R, red[k]);
+        for (int j = threadIdx.x; j < T; j += IV_NT) E[j] = exp2d_neg(sg * bl * U[j] - (float)R);
+        __syncthreads();
+        double S = 0.0, Sa = 0.0, Sb = 0.0;
+        int pos = 0;
+        if (nok)
+            for (int k = lo + r; k <= hi; k += IVS_LPI) {
+                float da, db;
+                const float w = mask_wk(mp, k, &da, &db);
+                if (!(w > 0.f)) continue;
+                pos = 1;
+                const double e = E[k];
+                S = fma((double)w, e, S);
+                Sa = fma((double)da, e, Sa);
+                Sb = fma((double)db, e, Sb);
+            }
+#pragma unroll
+        for (int d = 1; d < IVS_LPI; d <<= 1) {
+            S += __shfl_xor(S, d);
+            Sa += __shfl_xor(Sa, d);
+            Sb += __shfl_xor(Sb, d);
+            pos |= __shfl_xor(pos, d);
+        }
+        if (!nok || r != 0) continue;
+        float rho = -sg * A.rho_pad, ga = 0.f, gb = 0.f;
+        if (S > 0.0) {
+            rho = sg * ((float)R + log2d(S)) / bl;
+            const double iS = (double)(sg / A.beta) / S;
+            ga = (float)(iS * Sa);
+            gb = (float)(iS * Sb);
+        } else if (pos) {
+            iv_own_ref(mp, U, lo, hi, sg, bl, A.beta, rho, ga, gb);
+        }
+        const int64_t o = b * A.N + n;
+        A.rho[o] = rho;
+        if (A.ga) {
+            A.ga[o] = ga;
+            A.gb[o] = gb;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ batched sweep on the matrix cores
 
 // For many trajectories the smooth sweep is a dense contraction: with
@@ -520,6 +605,12 @@ hipError_t launch_interval_sweep(int op_sg, int smooth, float beta, float mc, fl
             hipLaunchKernelGGL(stl_interval_mfma_kernel<8>, g, blk, 0, s, A);
         else
             hipLaunchKernelGGL(stl_interval_mfma_kernel<16>, g, blk, 0, s, A);
+        return hipGetLastError();
+    }
+    if (smooth && !group) {
+        const dim3 g((unsigned)((N * IVS_LPI + IV_NT - 1) / IV_NT), (unsigned)std::min<int64_t>(B, 65535)),
+            blk(IV_NT);
+        hipLaunchKernelGGL(stl_interval_split_kernel, g, blk, 0, s, A);
         return hipGetLastError();
     }
     const int64_t groups = (B + A.tb - 1) / A.tb;
