@@ -149,11 +149,15 @@ typedef struct stl_plan stl_plan;
 
 /*
  * Compile a formula (post-order not required; `root` names the top node)
- * into an execution plan.  Host only: validates the node array (op codes,
+ * into an execution plan: the bottom-up composition of the formula graph
+ * (Sec. III-E, Fig. 2), each node an operator of Sec. III-B / III-C, IV-B,
+ * IV-C or VI.  Host only: validates the node array (op codes,
  * child counts and indices, acyclicity, intervals, predicate and parameter
  * indices against n_params), orders nodes topologically, assigns on-chip
  * trace slots by liveness and records the parameter layout.  rho_max is the
  * value of STL_TRUE, rho_pad the magnitude of the empty-window value.
+ * Several smooth-mask nodes may name the same (or overlapping) parameter
+ * slots (tied bounds): their d/da, d/db are summed into the shared entries.
  * Returns STL_OK and *out, or STL_E_ARG / STL_E_FORMULA / STL_E_UNSUPPORTED.
  */
 stl_status stl_compile(const stl_node* nodes, int32_t n_nodes, const int32_t* child_idx,
@@ -183,7 +187,10 @@ stl_status stl_workspace_size(const stl_plan* plan, const stl_batch* batch, cons
  * executor in the same call.  Results agree with the generic executor to
  * float32 rounding.
  *
- * Robustness traces: d_root receives the root trace ([B, T] dense or
+ * Robustness traces (Sec. III-D, Definition 1: value t is the robustness of
+ * the suffix starting at t), evaluated bottom-up over the plan with the
+ * windowed operators of Sec. IV-B / IV-C and the masks of Sec. VI:
+ * d_root receives the root trace ([B, T] dense or
  * [N_total] ragged, float32).  d_node_traces, if not NULL, receives every
  * node's trace as [n_nodes][N_total] in the caller's node numbering (debug and
  * tests).  d_params holds the plan's n_params float32 scalars (beta of smooth
@@ -195,7 +202,10 @@ stl_status stl_forward(const stl_plan* plan, const stl_batch* batch, const float
                        const stl_launch* cfg, void* stream);
 
 /*
- * Gradients of sum_t G_t * root_t: d_grad_x (same layout as x) is
+ * Reverse mode through the same plan (the gradients the paper obtains by
+ * automatic differentiation of Sec. IV-B / IV-C and of the mask of Sec. VI,
+ * here written out per operator): gradients of sum_t G_t * root_t.
+ * d_grad_root has the layout of d_root.  d_grad_x (same layout as x) is
  * overwritten; d_grad_params (n_params floats, may be NULL) is overwritten
  * with d/da and d/db of every smooth-mask bound and 0 elsewhere.  The
  * forward node traces are recomputed on chip, not stored.

@@ -733,18 +733,9 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
     ka.arena_floats = (int64_t)g.arena_floats;
     ka.counter = (int*)wsb;
     ka.persistent = g.persistent;
-    if (nodes) {
-        if (bt->offsets) {
-            // N_total is needed for the [n_nodes][N_total] layout: read it once
-            int64_t nt = 0;
-            if (hipMemcpyAsync(&nt, bt->offsets + bt->B, sizeof nt, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess)
-                return fail(STL_E_HIP, "reading offsets failed");
-            ka.n_total = nt;
-        } else {
-            ka.n_total = bt->B * bt->T;
-        }
-    }
+    // dense node traces are [n_nodes][B*T]; a ragged batch's N_total (offsets[B])
+    // is read by the kernel itself
+    if (nodes && !bt->offsets) ka.n_total = bt->B * bt->T;
     ka.list_count = (int*)wsb + 1;
     ka.list = g.fused ? (int*)(wsb + g.off_list) : nullptr;
     ka.tabs = g.fused ? (const MaskTab*)(wsb + g.off_tabs) : nullptr;

@@ -1748,12 +1748,15 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
                 // needed because the forward map keeps node outputs until
                 // overwritten; the host gives every node its own slot when
                 // traces are requested.
+                // [n_nodes][N_total]: a ragged batch's N_total is offsets[B], read
+                // here on the device so the host never waits for it
+                const int64_t ntot = bt.offsets ? bt.offsets[bt.B] : ka.n_total;
                 for (int k = 0; k < P->n_ins; ++k) {
                     const Instr& I = P->ins[k];
                     if (I.node < 0) continue;
                     const float* s = slot(e, I.f_out);
                     for (int t = threadIdx.x; t < e.L; t += blockDim.x)
-                        ka.nodes[(int64_t)I.node * ka.n_total + off + t] = s[t];
+                        ka.nodes[(int64_t)I.node * ntot + off + t] = s[t];
                 }
             }
             __syncthreads();
@@ -1772,28 +1775,33 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
 // grad_params[mask_param + 0/1] = sum over trajectories (fixed order) of the
 // per-trajectory partials; every other parameter gradient is 0.  One
 // work-group per (mask, bound): block q sums column q.
-__global__ void stl_reduce_params(const float* part, int64_t B, int n_masks, DevPlan plan, float* gp)
+// One work-group per parameter p: d/dp is the sum, over the per-trajectory
+// rows and in a fixed order, of every (mask, bound) column of the partials
+// whose parameter index is p (two mask nodes may share a, b); parameters no
+// mask bound names get 0.  The kernels overwrite gp, they never accumulate.
+__global__ void stl_reduce_params(const float* part, int64_t rows, int n_masks, DevPlan plan, float* gp)
 {
     __shared__ float red[256];
     const int tid = threadIdx.x;
-    const int q = blockIdx.x;
-    if (q == 0) {
-        for (int p = tid; p < plan.n_params; p += blockDim.x) {
-            bool bound = false;
-            for (int m = 0; m < n_masks; ++m) bound |= p == plan.mask_param[m] || p == plan.mask_param[m] + 1;
-            if (!bound) gp[p] = 0.f;
-        }
+    const int p = blockIdx.x;
+    int cols[2 * MAX_MASKS];
+    int nc = 0;
+    for (int q = 0; q < 2 * n_masks; ++q)
+        if (plan.mask_param[q >> 1] + (q & 1) == p) cols[nc++] = q;
+    if (nc == 0) {
+        if (tid == 0) gp[p] = 0.f;
+        return;
     }
-    if (q >= 2 * n_masks) return;
     float s = 0.f;
-    for (int64_t b = tid; b < B; b += blockDim.x) s += part[b * 2 * n_masks + q];
+    for (int64_t r = tid; r < rows; r += blockDim.x)
+        for (int k = 0; k < nc; ++k) s += part[r * 2 * n_masks + cols[k]];
     red[tid] = s;
     __syncthreads();
     for (int k = blockDim.x >> 1; k > 0; k >>= 1) {
         if (tid < k) red[tid] += red[tid + k];
         __syncthreads();
     }
-    if (tid == 0) gp[plan.mask_param[q >> 1] + (q & 1)] = red[0];
+    if (tid == 0) gp[p] = red[0];
 }
 
 __global__ void stl_zero_counter(int* c) { if (threadIdx.x < 2) c[threadIdx.x] = 0; }
@@ -1921,8 +1929,8 @@ hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s)
 
 hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& plan, float* gp, hipStream_t s)
 {
-    hipLaunchKernelGGL(stl_reduce_params, dim3(std::max(1, 2 * plan.n_masks)), dim3(256), 0, s, part, B,
-                       plan.n_masks, plan, gp);
+    if (plan.n_params < 1) return hipSuccess;
+    hipLaunchKernelGGL(stl_reduce_params, dim3(plan.n_params), dim3(256), 0, s, part, B, plan.n_masks, plan, gp);
     return hipGetLastError();
 }
 

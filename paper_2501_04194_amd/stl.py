@@ -119,6 +119,7 @@ class _Emitter:
         self.D = D
         self.nodes, self.child_idx, self.preds = [], [], []
         self.slots = []          # parameter slots: (name or None, literal value or None)
+        self.mask_groups = {}    # (a, b, c, eps) names -> first slot of their group
 
     def slot(self, v):
         self.slots.append((v, None) if isinstance(v, str) else (None, float(v)))
@@ -126,12 +127,19 @@ class _Emitter:
 
     def mask(self, nd, m):
         """Smooth time-interval mask (Sec. VI): (a, b, c, eps) in four
-        consecutive parameter slots."""
+        consecutive parameter slots.  Masks whose four entries are the same
+        parameter names (tied bounds) share one group of slots."""
+        key = (m["a"], m.get("b"), m["c"], m.get("eps", 1e-6))
+        nd.mask_unbounded = 1 if m.get("b") is None else 0
+        if all(isinstance(v, str) for v in key) and key in self.mask_groups:
+            nd.mask_param = self.mask_groups[key]
+            return
         nd.mask_param = self.slot(m["a"])
         self.slot(0.0 if m.get("b") is None else m["b"])
         self.slot(m["c"])
         self.slot(m.get("eps", 1e-6))
-        nd.mask_unbounded = 1 if m.get("b") is None else 0
+        if all(isinstance(v, str) for v in key):
+            self.mask_groups[key] = nd.mask_param
 
     def emit(self, f):
         op = f["op"]

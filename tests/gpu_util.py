@@ -12,7 +12,15 @@ Tolerances (written here, used by every parity test):
     terms, not with the (possibly cancelled) result;
   * d/da, d/db (sums over every timestep of the batch):
     |g - r| <= 1e-5 * sum |per-timestep terms| (the oracle's backward on |G|).
-Empty-window sentinels (+-rho_pad) must match exactly.
+Sentinels: a reference value equal to +-1e6 (the empty-window value +-rho_pad,
+or TRUE's rho_max) must match bit for bit.  Other values of sentinel
+magnitude (|r| >= 1e5: what a smooth operator derives from sentinels, e.g. a
+logsumexp over several of them, 1e6 +- log(K)/beta) compare at 1e-5 of their
+own magnitude, and are left out of S (which would otherwise loosen the bound
+of the ordinary values to 10).  A test whose smooth operators take a single
+sentinel as their whole window passes exact_sentinels=False: the float32
+exponent beta log2(e) 1e6 = 1.4e7 carries a rounding of up to half a unit, so
+such a value is 1e6 only to within about 0.04.
 """
 import numpy as np
 
@@ -31,20 +39,25 @@ def f32params(params):
     return {k: float(np.float32(v)) for k, v in (params or {}).items()}
 
 
-def assert_close(got, ref, rel=REL, scale=None, what="", elem_scale=None):
+SENTINEL = 1e6     # rho_pad and rho_max
+
+
+def assert_close(got, ref, rel=REL, scale=None, what="", elem_scale=None, exact_sentinels=True):
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     assert got.shape == ref.shape, (what, got.shape, ref.shape)
-    # values at the magnitude of the empty-window value (rho_pad) and of TRUE
-    # (rho_max), both 1e6: the sentinels themselves and what smooth operators
-    # derive from them (a logsumexp over sentinels, 1e6 - log(K)/beta, whose
-    # FP32 exponent beta log2(e) v carries an absolute error of one FP32 step
-    # at 1.4e7) compare with the stated tolerance at their own scale, S = |r|
     near = np.abs(ref) >= 1e5
     if near.any():
-        e = np.abs(got[near] - ref[near])
-        assert np.all(np.sign(got[near]) == np.sign(ref[near])), "%s: sentinel sign mismatch" % what
-        assert np.all(e <= 2 * rel * np.abs(ref[near])), "%s: sentinel mismatch (worst %g)" % (what, e.max())
+        exact = near & (np.abs(ref) == SENTINEL) if exact_sentinels else np.zeros_like(near)
+        if exact.any():
+            bad = got[exact] != ref[exact]
+            assert not bad.any(), "%s: %d sentinel values not exact (got %r, ref %r)" % (
+                what, bad.sum(), got[exact][bad][:4], ref[exact][bad][:4])
+        rest = near & ~exact
+        if rest.any():
+            e = np.abs(got[rest] - ref[rest])
+            assert np.all(np.sign(got[rest]) == np.sign(ref[rest])), "%s: sentinel sign mismatch" % what
+            assert np.all(e <= rel * np.abs(ref[rest])), "%s: sentinel-scale mismatch (worst %g)" % (what, e.max())
     nz = ~near
     if not nz.any():
         return
@@ -93,7 +106,7 @@ class Gpu:
 
 
 def check_formula(spec, x, params=None, G=None, grads=True, bitexact_root=False, launch=None, what="",
-                  offsets=None, T=None):
+                  offsets=None, T=None, exact_sentinels=True):
     """Forward (and backward) parity of one formula on one batch."""
     params = f32params(params)
     g = Gpu(spec, x.shape[-1], params, launch)
@@ -102,7 +115,7 @@ def check_formula(spec, x, params=None, G=None, grads=True, bitexact_root=False,
     if bitexact_root:
         assert np.array_equal(root.astype(np.float32), ref.astype(np.float32)), what + ": root not bit-exact"
     else:
-        assert_close(root, ref, what=what + " root")
+        assert_close(root, ref, what=what + " root", exact_sentinels=exact_sentinels)
     if not grads:
         return g
     if G is None:

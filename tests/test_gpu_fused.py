@@ -178,3 +178,19 @@ def test_autograd_function_uses_saved_traces():
     gp = g.plan.param_grads(pv.grad.cpu().numpy())
     for k in p0:
         assert gp[k] == p0[k], k
+
+
+@pytest.mark.parametrize("generic", [False, True])
+def test_tied_mask_bounds_share_parameters(generic):
+    """Two mask nodes tied to the same (a, b, c, eps) names share one group of
+    parameter slots in the plan; d/da and d/db sum both nodes' contributions
+    (the oracle sums per name), on the fused path and on the generic executor."""
+    spec = {"op": "and", "smooth": True, "beta": 10.0, "children": [
+        mask("eventually", lin([1, 0]), "a", "b", c="c", eps="eps"),
+        mask("always", lin([0, -1], -0.5), "a", "b", c="c", eps="eps")]}
+    params = {"a": 60.0, "b": 250.0, "c": 1.0, "eps": 1e-6}
+    plan = stl.Plan(spec, 2, params)
+    assert plan.n_params == 7          # one shared mask group + the three beta slots (11 untied)
+    _, _, x = W.workload(2, B=7, T=700)
+    check_formula(spec, x, params=params, launch=GENERIC if generic else None,
+                  what="tied bounds generic=%s" % generic)

@@ -751,3 +751,54 @@ def test_mask_weights_against_high_precision(orc):
             rdb = Decimal(c) * sig(y) * (one - sig(y))
             assert abs(Decimal(da[k]) - rda) <= tol * abs(rda)
             assert abs(Decimal(db[k]) - rdb) <= tol * abs(rdb)
+
+
+# --------------------------------------------------------------------------- norm predicate
+
+def _norm(A, p, r, sign):
+    return {"op": "norm", "A": A, "p": p, "r": r, "sign": sign}
+
+
+def test_norm_predicate_hand_values(orc):
+    """The distance predicate sign * (||A x - p|| - r) (the obstacle and goal
+    disks of the planning problem of Sec. VII-A, written as predicates of
+    Sec. III-A) against values worked by hand: points at known distances from
+    the centre (3-4-5 offsets), a scaling and a three-row A, both signs, and
+    the centre itself.  A +p in place of -p, a dropped sign or a missing
+    square root fails one of these."""
+    p = [0.3, -0.2]
+    # points p + d * (0.6, 0.8): distance d from the centre
+    ds = [0.0, 0.5, 1.0, 2.5]
+    x = np.array([[[p[0] + 0.6 * d, p[1] + 0.8 * d] for d in ds]])
+    out = orc.forward(_norm([[1.0, 0.0], [0.0, 1.0]], p, 0.5, 1.0), x)[0]
+    np.testing.assert_allclose(out, [d - 0.5 for d in ds], rtol=0, atol=1e-12)
+    out = orc.forward(_norm([[1.0, 0.0], [0.0, 1.0]], p, 0.5, -1.0), x)[0]
+    np.testing.assert_allclose(out, [0.5 - d for d in ds], rtol=0, atol=1e-12)
+    # A = diag(2, 3), p = (1, -1), x = (1, 1): A x - p = (1, 4) -> sqrt(17) - r
+    out = orc.forward(_norm([[2.0, 0.0], [0.0, 3.0]], [1.0, -1.0], 0.25, 1.0), np.array([[[1.0, 1.0]]]))[0]
+    assert abs(out[0] - (17 ** 0.5 - 0.25)) < 1e-12
+    # three rows: A = [[1, 2], [3, 4], [0, 1]], p = (1, 2, 3), x = (1, -1):
+    # A x - p = (-1 - 1, -1 - 2, -1 - 3) = (-2, -3, -4) -> sqrt(29)
+    out = orc.forward(_norm([[1.0, 2.0], [3.0, 4.0], [0.0, 1.0]], [1.0, 2.0, 3.0], 1.0, 1.0),
+                      np.array([[[1.0, -1.0]]]))[0]
+    assert abs(out[0] - (29 ** 0.5 - 1.0)) < 1e-12
+    # one row: |a.x - p| - r = |2*0.5 + 1*(-3) - 1| - 0.5 = 3 - 0.5
+    out = orc.forward(_norm([[2.0, 1.0]], [1.0], 0.5, 1.0), np.array([[[0.5, -3.0]]]))[0]
+    assert abs(out[0] - 2.5) < 1e-12
+
+
+def test_norm_predicate_gradient_hand_values(orc):
+    """d/dx of sign * ||x - p|| is sign * (x - p) / ||x - p|| (a unit vector
+    pointing away from the centre), and 0 at the centre itself (the
+    subgradient the oracle defines there)."""
+    p = [0.3, -0.2]
+    x = np.array([[[p[0] + 0.6 * 2.0, p[1] + 0.8 * 2.0], [p[0], p[1]], [p[0] - 0.8, p[1] + 0.6]]])
+    G = np.ones((1, 3))
+    for sign in (1.0, -1.0):
+        dx, _ = orc.backward(_norm([[1.0, 0.0], [0.0, 1.0]], p, 0.5, sign), x, G)
+        np.testing.assert_allclose(dx[0], sign * np.array([[0.6, 0.8], [0.0, 0.0], [-0.8, 0.6]]), rtol=0,
+                                   atol=1e-12)
+    # with A = diag(2, 3): d/dx = A^T (A x - p) / ||A x - p||; A x - p = (1, 4) at x = (1, 1)
+    dx, _ = orc.backward(_norm([[2.0, 0.0], [0.0, 3.0]], [1.0, -1.0], 0.25, 1.0), np.array([[[1.0, 1.0]]]),
+                         np.ones((1, 1)))
+    np.testing.assert_allclose(dx[0, 0], np.array([2.0 * 1.0, 3.0 * 4.0]) / 17 ** 0.5, rtol=0, atol=1e-12)
