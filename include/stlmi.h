@@ -142,7 +142,8 @@ typedef struct {
     int32_t wg_per_cu;       /* persistent grid size per compute unit (0 = one work-group per
                                 trajectory) */
     int32_t global_slots;    /* 1: keep node traces in the workspace instead of LDS */
-    int32_t flags;           /* bit 0: do not use the fused fast path (see stl_forward) */
+    int32_t flags;           /* bit 0: generic executor only (no fused path); bit 1: the fp64 fused
+                                kernels instead of the matrix-core path (see stl_forward) */
 } stl_launch;
 
 typedef struct stl_plan stl_plan;
@@ -178,14 +179,21 @@ stl_status stl_workspace_size(const stl_plan* plan, const stl_batch* batch, cons
                               size_t* fwd_bytes, size_t* bwd_bytes);
 
 /*
- * Fused fast path: when the formula is a smooth And/Or over up to 4
+ * Fused fast paths, for a formula that is a smooth And/Or over up to 4
  * smooth-mask Eventually/Always nodes on linear predicates (or one such
- * node), the batch is dense and T <= 2048, stl_forward and stl_backward run
- * one fused kernel per call (fp64 accumulation, one work-group per
- * trajectory); trajectories it cannot take (signal range beyond fp64
- * exponents, mask bands wider than 512 steps) are recomputed by the generic
- * executor in the same call.  Results agree with the generic executor to
- * float32 rounding.
+ * node) and a dense batch:
+ *  - matrix-core path (one or two bounded masks, D <= 2, any T): the masked
+ *    logsumexp windows of Sec. VI as products of Toeplitz weight tiles and
+ *    the terms 2^{z - R} on the bf16 matrix cores (each factor split into
+ *    two bf16 parts, three products, fp32 accumulation: relative error a few
+ *    2^-18 at worst per window sum, far less on average); trajectories whose
+ *    exponent range over a chunk of outputs exceeds 200 (log2 units), and
+ *    masks wider than the kernel's tiles, go to the generic executor in the
+ *    same call;
+ *  - otherwise fp64 fused kernels (T <= 2048; one work-group per
+ *    trajectory; signal ranges beyond fp64 exponents and mask bands wider
+ *    than 512 steps go to the generic executor).  Results agree with the
+ *    generic executor to float32 rounding.
  *
  * Robustness traces (Sec. III-D, Definition 1: value t is the robustness of
  * the suffix starting at t), evaluated bottom-up over the plan with the
@@ -223,8 +231,11 @@ stl_status stl_backward(const stl_plan* plan, const stl_batch* batch, const floa
  *
  * stl_saved_size: bytes of the caller-owned device buffer `d_saved` for this
  * batch: a header of B int32 validity flags (padded to 256 bytes) followed by
- * [n_mask][B][T] float32 traces when the fused fast path applies (n_mask = the
- * number of smooth-mask children of the root); only the header otherwise.
+ * [n_mask][B][T] float32 traces when a fused fast path applies (n_mask = the
+ * number of smooth-mask children of the root), and for the matrix-core path
+ * the per-chunk exponent ranges of those traces; only the header otherwise.
+ * A flag is 1 (fp64 fused forward) or 2 (matrix-core forward) where the
+ * trajectory's saved data are valid for the backward of the same path.
  *
  * stl_forward_saving: stl_forward that also fills d_saved (saved_bytes must
  * be at least stl_saved_size).  Trajectories the fused kernel does not take

@@ -32,6 +32,12 @@ hipError_t launch_fused(bool bwd, const DevPlan& plan, const struct Batch& bt, c
                         hipStream_t s);
 hipError_t set_max_lds_fused(size_t bytes);
 size_t mask_tab_bytes();
+size_t mx_tab_bytes();
+size_t mx_lds_bytes(int n, int D, bool bwd);
+size_t mx_static_lds();
+hipError_t set_max_lds_mx(size_t bytes);
+hipError_t launch_mx(bool bwd, const DevPlan& plan, const struct Batch& bt, const struct KArgs& ka,
+                     const struct MxArgs& mx, int* table_saved_flag, bool tables, size_t lds, hipStream_t s);
 int interval_max_T();
 int pstl_max_BT();
 hipError_t launch_pstl_descent(const float* x, int B, int T, int D, const float* w, float c, int op_sg, float eps,
@@ -515,6 +521,7 @@ namespace {
 struct DevInfo {
     int cus = 256;
     size_t lds_max = 65536;
+    size_t lds_mx = 0;
     bool lds_set = false;
 };
 
@@ -537,6 +544,10 @@ DevInfo& devinfo()
     di.lds_max = di.lds_max > static_lds ? di.lds_max - static_lds : 0;
     if (set_max_lds(di.lds_max) == hipSuccess) di.lds_set = true;
     (void)set_max_lds_fused(di.lds_max);
+    // the matrix-core kernels' static LDS is small and known: they may use the rest
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+        di.lds_mx = (size_t)v > mx_static_lds() + 1024 ? (size_t)v - mx_static_lds() - 1024 : 0;
+    (void)set_max_lds_mx(di.lds_mx);
     (void)hipGetLastError();
     return g_dev[dev] = di;
 }
@@ -556,7 +567,27 @@ struct Geom {
     size_t fused_lds;
     size_t off_list;        // fused: fix-up list (bytes)
     size_t off_tabs;        // fused: per-mask tables (bytes)
+    // matrix-core path (replaces the fused kernels where it applies)
+    bool mx;
+    size_t mx_lds;
+    size_t off_handed;      // [B] int
+    size_t off_mxtr;        // backward without saved traces: [n][B][T] traces, [B] flags, ranges
+    size_t off_mxflag;
+    size_t off_mxrange;
 };
+
+// The matrix-core path takes dense batches of a root that is a smooth
+// And/Or over one or two bounded smooth-mask nodes on linear predicates (or
+// one such node), D <= 2, unless the launch asks for another path (flags bit
+// 0: generic executor only, bit 1: the fp64 fused kernels).
+static bool mx_applies(const DevPlan& dp, const stl_batch* bt, const stl_launch* cfg, bool trace)
+{
+    if (dp.fused.n < 1 || dp.fused.n > 2 || trace || bt->offsets != nullptr || bt->D > 2) return false;
+    if (cfg && (cfg->flags & 3)) return false;
+    for (int m = 0; m < dp.fused.n; ++m)
+        if (dp.ins[dp.fused.ins[m]].flags & F_MASK_UNB) return false;
+    return true;
+}
 
 stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch* cfg, bool bwd, bool trace,
                     Geom* g)
@@ -607,17 +638,55 @@ stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch*
     g->global = global;
     g->arena_floats = arena;
     g->lds_bytes = global ? 0 : lds;
+    g->mx = false;
+    g->mx_lds = 0;
+    g->off_handed = g->off_mxtr = g->off_mxflag = g->off_mxrange = 0;
+    if (mx_applies(dp, bt, cfg, trace)) {
+        const size_t lds = mx_lds_bytes(dp.fused.n, bt->D, bwd);
+        if (lds <= di.lds_mx) {
+            g->mx = true;
+            g->mx_lds = lds;
+        }
+    }
+    const int64_t prow = 1;     // partial rows per trajectory
     size_t off = 256;   // counter
     g->off_part = off;
-    if (bwd) off += (size_t)bt->B * std::max(dp.n_masks, 1) * 2 * sizeof(float);
+    if (bwd) off += (size_t)bt->B * prow * std::max(dp.n_masks, 1) * 2 * sizeof(float);
     off = (off + 255) / 256 * 256;
     g->off_arena = off;
     g->fused = false;
     g->fused_lds = 0;
     g->off_list = 0;
     g->off_tabs = 0;
-    const bool want_fused = dp.fused.n > 0 && !trace && bt->offsets == nullptr && bt->T <= fused_max_T() &&
-                            !(cfg && (cfg->flags & 1));
+    if (g->mx) {
+        // fix-up grid of the generic executor, list, hand-off flags, tables
+        if (!global) g->persistent = 1;
+        g->grid = (int)std::max<int64_t>(1, std::min<int64_t>(bt->B, di.cus / 4));
+        g->off_list = off;
+        off += (size_t)bt->B * sizeof(int);
+        off = (off + 255) / 256 * 256;
+        g->off_handed = off;
+        off += (size_t)bt->B * sizeof(int);
+        off = (off + 255) / 256 * 256;
+        g->off_tabs = off;
+        off += (size_t)dp.fused.n * mx_tab_bytes();
+        off = (off + 255) / 256 * 256;
+        if (bwd) {
+            // the backward without saved traces first runs the forward into these
+            g->off_mxtr = off;
+            off += (size_t)dp.fused.n * bt->B * bt->T * sizeof(float);
+            off = (off + 255) / 256 * 256;
+            g->off_mxflag = off;
+            off += (size_t)bt->B * sizeof(int);
+            off = (off + 255) / 256 * 256;
+            g->off_mxrange = off;
+            off += (size_t)bt->B * dp.fused.n * 2 * sizeof(int);
+            off = (off + 255) / 256 * 256;
+        }
+        g->off_arena = off;
+    }
+    const bool want_fused = !g->mx && dp.fused.n > 0 && !trace && bt->offsets == nullptr &&
+                            bt->T <= fused_max_T() && !(cfg && (cfg->flags & 1));
     if (want_fused) {
         const size_t fl = fused_lds((int)((bt->T + 3) / 4 * 4), dp.fused.n, bt->D, bwd);
         if (fl <= di.lds_max) {
@@ -673,11 +742,22 @@ extern "C" stl_status stl_workspace_size(const stl_plan* plan, const stl_batch* 
 
 static size_t saved_header(int64_t B) { return ((size_t)B * sizeof(int32_t) + 255) / 256 * 256; }
 
+// saved buffer: B int32 flags (padded to 256 bytes), [n][B][T] float32 mask
+// traces when a fused path applies, and for the matrix-core path the
+// ranges of the traces' exponents ([B][n][2] int32)
+static size_t saved_traces_bytes(const stl_plan* plan, const stl_batch* bt)
+{
+    return (size_t)plan->dev.fused.n * bt->B * bt->T * sizeof(float);
+}
+
 static size_t saved_bytes_needed(const stl_plan* plan, const stl_batch* bt)
 {
     const int n = plan->dev.fused.n;
-    const bool fusable = n > 0 && bt->offsets == nullptr && bt->T <= fused_max_T();
-    return saved_header(bt->B) + (fusable ? (size_t)n * bt->B * bt->T * sizeof(float) : 0);
+    const bool mx = mx_applies(plan->dev, bt, nullptr, false);
+    const bool fusable = n > 0 && bt->offsets == nullptr && (bt->T <= fused_max_T() || mx);
+    size_t s = saved_header(bt->B) + (fusable ? saved_traces_bytes(plan, bt) : 0);
+    if (mx) s += (size_t)bt->B * n * 2 * sizeof(int32_t);
+    return s;
 }
 
 // saved: 0 none, 1 forward writes d_saved, 2 backward reads it
@@ -737,9 +817,61 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
     // is read by the kernel itself
     if (nodes && !bt->offsets) ka.n_total = bt->B * bt->T;
     ka.list_count = (int*)wsb + 1;
-    ka.list = g.fused ? (int*)(wsb + g.off_list) : nullptr;
+    ka.list = (g.fused || g.mx) ? (int*)(wsb + g.off_list) : nullptr;
     ka.tabs = g.fused ? (const MaskTab*)(wsb + g.off_tabs) : nullptr;
     ka.list_mode = 0;
+    ka.part_stride = 1;
+    if (g.mx) {
+        MxArgs mx;
+        mx.tabs = (const MxTab*)(wsb + g.off_tabs);
+        mx.handed = (int*)(wsb + g.off_handed);
+        mx.part = ka.mask_part;
+        mx.ranges = nullptr;
+        hipError_t e;
+        int* traces_flags = nullptr;
+        if (saved) {
+            traces_flags = (int*)d_saved;
+            float* traces = (float*)((char*)d_saved + saved_header(bt->B));
+            ka.saved_flag = traces_flags;
+            mx.ranges = (int*)((char*)traces + saved_traces_bytes(plan, bt));
+            if (saved == 1) ka.saved = traces;
+            else ka.saved_in = traces;
+        }
+        if (!bwd) {
+            e = launch_mx(false, dp, b, ka, mx, saved == 1 ? traces_flags : nullptr, true, g.mx_lds, st);
+        } else if (saved == 2) {
+            e = launch_mx(true, dp, b, ka, mx, nullptr, true, g.mx_lds, st);
+        } else {
+            // no saved traces: the forward fills workspace copies first
+            KArgs kf = ka;
+            MxArgs mf = mx;
+            kf.root = nullptr;
+            kf.saved = (float*)(wsb + g.off_mxtr);
+            kf.saved_flag = (int*)(wsb + g.off_mxflag);
+            mf.ranges = (int*)(wsb + g.off_mxrange);
+            e = launch_mx(false, dp, b, kf, mf, kf.saved_flag, true, g.mx_lds, st);
+            if (e == hipSuccess) {
+                KArgs kb = ka;
+                kb.saved_in = kf.saved;
+                kb.saved_flag = kf.saved_flag;
+                e = launch_mx(true, dp, b, kb, mf, nullptr, false, g.mx_lds, st);
+            }
+        }
+        if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+        // trajectories the matrix-core kernels handed off go through the generic executor
+        KArgs kx = ka;
+        kx.list_mode = 1;
+        kx.persistent = 1;
+        kx.saved = nullptr;
+        kx.saved_in = nullptr;
+        e = launch_exec(bwd, dp, b, kx, g.grid, g.nt, g.lds_bytes, st);
+        if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+        if (bwd && gparams) {
+            e = launch_reduce_params(ka.mask_part, bt->B, dp, gparams, st);
+            if (e != hipSuccess) return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(e));
+        }
+        return STL_OK;
+    }
     if (saved) {
         int* flags = (int*)d_saved;
         float* traces = (float*)((char*)d_saved + saved_header(bt->B));

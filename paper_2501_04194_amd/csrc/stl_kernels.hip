@@ -1709,11 +1709,9 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
         if (len <= 0) {
             // an empty trajectory adds nothing to d/da, d/db: its partials
             // are still read by the reduction
-            if (BWD && threadIdx.x == 0)
-                for (int m = 0; m < P->n_masks; ++m) {
-                    ka.mask_part[(b * P->n_masks + m) * 2] = 0.f;
-                    ka.mask_part[(b * P->n_masks + m) * 2 + 1] = 0.f;
-                }
+            if (BWD)
+                for (int q = threadIdx.x; q < ka.part_stride * P->n_masks * 2; q += blockDim.x)
+                    ka.mask_part[b * ka.part_stride * P->n_masks * 2 + q] = 0.f;
             continue;
         }
         if (len > Lc) {
@@ -1722,11 +1720,9 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
                 if (!BWD) ka.root[off + t] = NAN;
                 else for (int d = 0; d < bt.D; ++d) ka.dx[(off + t) * bt.D + d] = NAN;
             }
-            if (BWD && threadIdx.x == 0)
-                for (int m = 0; m < P->n_masks; ++m) {
-                    ka.mask_part[(b * P->n_masks + m) * 2] = NAN;
-                    ka.mask_part[(b * P->n_masks + m) * 2 + 1] = NAN;
-                }
+            if (BWD)
+                for (int q = threadIdx.x; q < ka.part_stride * P->n_masks * 2; q += blockDim.x)
+                    ka.mask_part[b * ka.part_stride * P->n_masks * 2 + q] = NAN;
             continue;
         }
         Env e;
@@ -1764,7 +1760,11 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
             float* gr = slot(e, P->ins[P->root].g_out);
             for (int t = threadIdx.x; t < e.L; t += blockDim.x) gr[t] = ka.G[off + t];
             __syncthreads();
-            float* mp = ka.mask_part + b * P->n_masks * 2;
+            // one partial row per trajectory; with part_stride > 1 (rows per
+            // chunk of the matrix-core path) the trajectory's other rows are cleared
+            float* mp = ka.mask_part + b * ka.part_stride * P->n_masks * 2;
+            for (int q = threadIdx.x; q < (ka.part_stride - 1) * P->n_masks * 2; q += blockDim.x)
+                mp[P->n_masks * 2 + q] = 0.f;
             for (int k = P->n_ins - 1; k >= 0; --k) exec_adj(e, P->ins[k], mp);
             op_dx(e, ka.dx + off * bt.D);
             __syncthreads();
@@ -1772,16 +1772,14 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
     }
 }
 
-// grad_params[mask_param + 0/1] = sum over trajectories (fixed order) of the
-// per-trajectory partials; every other parameter gradient is 0.  One
-// work-group per (mask, bound): block q sums column q.
 // One work-group per parameter p: d/dp is the sum, over the per-trajectory
 // rows and in a fixed order, of every (mask, bound) column of the partials
 // whose parameter index is p (two mask nodes may share a, b); parameters no
 // mask bound names get 0.  The kernels overwrite gp, they never accumulate.
-__global__ void stl_reduce_params(const float* part, int64_t rows, int n_masks, DevPlan plan, float* gp)
+__global__ void __launch_bounds__(1024) stl_reduce_params(const float* part, int64_t rows, int n_masks, DevPlan plan,
+                                                          float* gp)
 {
-    __shared__ float red[256];
+    __shared__ float red[1024];
     const int tid = threadIdx.x;
     const int p = blockIdx.x;
     int cols[2 * MAX_MASKS];
@@ -1792,10 +1790,18 @@ __global__ void stl_reduce_params(const float* part, int64_t rows, int n_masks, 
         if (tid == 0) gp[p] = 0.f;
         return;
     }
-    float s = 0.f;
-    for (int64_t r = tid; r < rows; r += blockDim.x)
-        for (int k = 0; k < nc; ++k) s += part[r * 2 * n_masks + cols[k]];
-    red[tid] = s;
+    // each thread: rows tid, tid + 1024, ... (four independent sums, added in a fixed order)
+    float s4[4] = {0.f, 0.f, 0.f, 0.f};
+    const int64_t stride = (int64_t)blockDim.x;
+    for (int64_t r0 = tid; r0 < rows; r0 += 4 * stride) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t r = r0 + u * stride;
+            if (r < rows)
+                for (int k = 0; k < nc; ++k) s4[u] += part[r * 2 * n_masks + cols[k]];
+        }
+    }
+    red[tid] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     __syncthreads();
     for (int k = blockDim.x >> 1; k > 0; k >>= 1) {
         if (tid < k) red[tid] += red[tid + k];
@@ -1816,6 +1822,7 @@ __global__ void stl_fill_int(int* p, int64_t n, int v)
 
 #include "stl_fused.h"
 #include "stl_interval.h"
+#include "stl_mx.h"
 
 namespace stlmi {
 
@@ -1930,7 +1937,68 @@ hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s)
 hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& plan, float* gp, hipStream_t s)
 {
     if (plan.n_params < 1) return hipSuccess;
-    hipLaunchKernelGGL(stl_reduce_params, dim3(plan.n_params), dim3(256), 0, s, part, B, plan.n_masks, plan, gp);
+    hipLaunchKernelGGL(stl_reduce_params, dim3(plan.n_params), dim3(1024), 0, s, part, B, plan.n_masks, plan, gp);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ matrix-core path
+
+size_t mx_tab_bytes() { return sizeof(MxTab); }
+
+// dynamic LDS of the matrix-core kernels: the rings (n masks x 16 rows), the
+// exchange area of masks 1 .. n-1 (forward: traces; backward: d/dx), the
+// backward's derivative tiles and the lo weight tiles
+size_t mx_lds_bytes(int n, int D, bool bwd)
+{
+    return (size_t)n * MXG * MXRS + (size_t)(n - 1) * MXG * MXXS * (bwd ? D : 1) * sizeof(float) +
+           (bwd ? (size_t)n * NDMAX * 2 * 64 * 16 : 0) + (size_t)n * NKMAX * 64 * 16;
+}
+size_t mx_static_lds() { return sizeof(MxShared); }
+
+hipError_t set_max_lds_mx(size_t bytes)
+{
+    hipError_t e = hipSuccess;
+#define STLMI_MX_ATTR(KK)                                                                                   \
+    {                                                                                                     \
+        const hipError_t e2 = hipFuncSetAttribute((const void*)KK, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                                  (int)bytes);                                            \
+        if (e2 != hipSuccess) e = e2;                                                                     \
+    }
+    STLMI_MX_ATTR((stl_mx_fwd<1, 2>)) STLMI_MX_ATTR((stl_mx_fwd<1, 1>))
+    STLMI_MX_ATTR((stl_mx_fwd<2, 2>)) STLMI_MX_ATTR((stl_mx_fwd<2, 1>))
+    STLMI_MX_ATTR((stl_mx_bwd<1, 2>)) STLMI_MX_ATTR((stl_mx_bwd<1, 1>))
+    STLMI_MX_ATTR((stl_mx_bwd<2, 2>)) STLMI_MX_ATTR((stl_mx_bwd<2, 1>))
+#undef STLMI_MX_ATTR
+    return e;
+}
+
+// tables (saved_flag: marked valid for a saving forward, else NULL), then
+// the forward or backward kernel over (trajectory groups) x (chunks)
+hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs& ka, const MxArgs& mx,
+                     int* table_saved_flag, bool tables, size_t lds, hipStream_t s)
+{
+    if (tables) {
+        hipLaunchKernelGGL(stl_mx_tables, dim3(NKMAX, plan.fused.n), dim3(256), 0, s, plan, ka.params, (int)bt.T,
+                           (MxTab*)mx.tabs, ka.counter, mx.handed, table_saved_flag, bt.B);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((unsigned)((bt.B + MXG - 1) / MXG)), block(256 * plan.fused.n);
+    const bool d2 = bt.D == 2;
+#define STLMI_MX_CASE(NN)                                                                                 \
+    case NN:                                                                                              \
+        if (bwd && d2) hipLaunchKernelGGL((stl_mx_bwd<NN, 2>), grid, block, lds, s, plan, bt, ka, mx);     \
+        else if (bwd) hipLaunchKernelGGL((stl_mx_bwd<NN, 1>), grid, block, lds, s, plan, bt, ka, mx);      \
+        else if (d2) hipLaunchKernelGGL((stl_mx_fwd<NN, 2>), grid, block, lds, s, plan, bt, ka, mx);       \
+        else hipLaunchKernelGGL((stl_mx_fwd<NN, 1>), grid, block, lds, s, plan, bt, ka, mx);               \
+        break;
+    switch (plan.fused.n) {
+        STLMI_MX_CASE(1)
+        STLMI_MX_CASE(2)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef STLMI_MX_CASE
     return hipGetLastError();
 }
 

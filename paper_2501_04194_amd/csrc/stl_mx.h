@@ -1,0 +1,912 @@
+// Matrix-core path for formulas of the fused shape
+//     root = smooth And/Or over one or two smooth-mask Eventually/Always
+//            nodes with bounded masks, each over a linear predicate,
+// e.g. Eventually~[a,b](x0 > 0) and~ Always~[a,b](x1 < 0.5) with the smooth
+// time mask of arXiv 2501.04194 Sec. VI.  Included by stl_kernels.hip after
+// stl_fused.h.
+//
+// A mask node's trace is out_t = (sg / beta) log sum_k w_k e^{beta sg u_{t+k}}
+// (Sec. III-C logsumexp with the Sec. VI weights inside the sum).  With the
+// terms E_j = 2^{z_j - R}, z = sg beta log2(e) u, the window sums
+// S_t = sum_k w_k E_{t+k} of 16 outputs t and 16 trajectories b are one
+// matrix product S = W E: W[t][j] = w_{j - t} (a Toeplitz tile, the same for
+// every trajectory and every output tile) and E[j][b] the terms.  The
+// product runs on v_mfma_f32_16x16x32_bf16 with each factor split into two
+// bf16 parts (x = hi + lo to 2^-18 relative) and three products
+// (Wh Eh + Wh El + Wl Eh) accumulated in fp32: every sum has positive terms,
+// so its relative error is a few 2^-18 at worst and far smaller on average.
+// The weights are divided by the core weight (core offsets have W = 1).
+//
+// The backward needs, for the adjoint terms H_t = G_m(t) 2^{-O_t - Q}
+// (O_t = sg beta log2(e) out_t, G_m the root's adjoint share of the node),
+// the transposed window sums D_j = sum_t w_{j - t} H_t (for d/dx) and
+// sum_t dw_{j - t} H_t for the band derivative tables (for d/da, d/db): the
+// same products with transposed weight tiles over H.
+//
+// Work decomposition: a work-group takes 16 trajectories from start to end,
+// four waves per mask node.  The terms (or adjoint terms) of each mask
+// stream through an LDS ring of 640 positions per trajectory, 128 positions
+// (one block) at a time: in round k the waves compute outputs
+// [128 k, 128 k + 128) from blocks k .. k+3 while the loads of block k+4 are
+// in flight, then write it over block k-1.  Each wave computes two output
+// tiles t and t + 32, which read the same E blocks one K-step apart, so every
+// E read feeds six products.  The reference R of a trajectory's terms is the
+// midpoint of its exponents over a strided sample; every staged exponent is
+// checked to lie within 100 of it (so that nothing over- or underflows), and
+// a trajectory that fails is handed to the generic executor.  The backward's
+// reference Q comes from the range of O the forward recorded.
+#pragma once
+
+namespace stlmi {
+
+constexpr int MXG = 16;                 // trajectories per work-group (the MFMA N)
+constexpr int MXWPM = 4;                // waves per mask node
+constexpr int NKMAX = 12;               // K-steps (32 offsets each) of a window tile
+constexpr int NDMAX = 4;                // derivative tiles per mask (a K-step with d/da and d/db weights has two)
+constexpr int MXROUND = 128;            // outputs per round (4 pairs of 16-output tiles)
+constexpr int MXBLK = 128;              // positions per staged block
+constexpr int MXNBLK = 5;               // blocks in the ring
+constexpr int MXRING = MXBLK * MXNBLK;  // ring positions per trajectory
+constexpr int MXRS = MXRING / 8 * 32 + 16;   // LDS row stride (bytes): 16 bytes of pad put the 16
+                                             // rows a wave reads at once on distinct bank groups
+constexpr int MXXS = MXROUND + 4;       // exchange row stride (floats per state component): the
+                                        // 16 bytes of pad spread the rows over the banks
+constexpr float MX_HALF = 100.f;       // largest |z - R| (and half the range of O), log2 units
+constexpr int MX_MAXN = 2;              // mask nodes under the root
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float mxf4;
+
+// Per-mask tables, computed once per call by stl_mx_tables.  Tiles are
+// stored in the lane layout of the MFMA A operand (16 rows x 32 columns,
+// lane l holds row l % 16, columns 8 (l / 16) .. + 7), 16 bytes per lane.
+struct MxTab {
+    int ok;                    // 0: the window needs more than NKMAX K-steps
+    int any;                   // the support {w > 0} is non-empty
+    int klo, khi, clo, chi;    // support and constant core (clo > chi: no core)
+    int NK;                    // K-steps of an output tile
+    float lscale;              // log2 of the weight scale (the core weight, or 1)
+    int flo_f[NKMAX];          // tile s of the forward (backward) product has a
+    int flo_b[NKMAX];          //   non-zero lo part
+    int fd[NKMAX];             // backward K-step s has d/da (bit 0) / d/db (bit 1) weights
+    uint4 Wf[NKMAX][2][64];    // forward tiles [s][hi, lo][lane]: row t, column j: w(klo + 32 s + j - t)
+    uint4 Wb[NKMAX][2][64];    // backward tiles: row j, column t: w(khi - 32 s + j - t)
+    uint4 Dt[NKMAX][2][2][64]; // derivative tiles [s][d/da, d/db][hi, lo][lane], backward layout
+};
+
+// round to nearest even float -> bf16 bits (finite inputs)
+DEV unsigned bf16_bits(float f)
+{
+    const unsigned u = __float_as_uint(f);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// hi = bf16(v), lo = bf16(v - hi): v to about 2^-18 relative
+DEV void split2(double v, unsigned& hi, unsigned& lo)
+{
+    const float f = (float)v;
+    hi = bf16_bits(f);
+    lo = bf16_bits((float)(v - (double)__uint_as_float(hi << 16)));
+}
+
+// eight floats -> packed bf16 hi and lo parts (hardware conversion, round to
+// nearest even)
+DEV void split8(const float* e, bf16x8& h, bf16x8& l)
+{
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const __bf16 hh = (__bf16)e[v];
+        h[v] = hh;
+        l[v] = (__bf16)(e[v] - (float)hh);
+    }
+}
+
+DEV mxf4 mfma(const bf16x8& a, const bf16x8& b, mxf4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+DEV bf16x8 ld_bf16x8(const void* p) { return *(const bf16x8*)p; }
+
+DEV bf16x8 tile_ld(const uint4* p)
+{
+    const uint4 u = *p;
+    bf16x8 r;
+    __builtin_memcpy(&r, &u, 16);
+    return r;
+}
+
+// max / min over each 32-lane half of the wave
+DEV float half_max(float v)
+{
+    v = fmaxf(v, __int_as_float(swz_xor<1>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(swz_xor<2>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(swz_xor<4>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(swz_xor<8>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(swz_xor<16>(__float_as_int(v))));
+    return v;
+}
+
+DEV float half_min(float v) { return -half_max(-v); }
+
+// ------------------------------------------------------------------ tables
+
+// One work-group per (K-step s, mask node m): the forward, backward and
+// derivative tiles of step s (work-group s = 0 also writes the support and
+// core).  The work-groups also clear the hand-off flags (and, for a saving
+// forward, mark every trajectory's saved traces valid with the value 2:
+// traces written by this path, with their exponent ranges; the fp64 fused
+// kernels write 1 and no ranges); work-group (0, 0) resets the two counters.
+__global__ void __launch_bounds__(256) stl_mx_tables(DevPlan plan, const float* params, int L, MxTab* tabs,
+                                                     int* counters, int* handed, int* saved_flag, int64_t B)
+{
+    __shared__ TabShared sh;
+    const int tid = threadIdx.x;
+    const int s = blockIdx.x, m = blockIdx.y;
+    const int flat = m * gridDim.x + s, nblk = gridDim.x * gridDim.y;
+    for (int64_t b = (int64_t)flat * blockDim.x + tid; b < B; b += (int64_t)nblk * blockDim.x) {
+        handed[b] = 0;
+        if (saved_flag) saved_flag[b] = 2;
+    }
+    if (flat == 0 && tid < 2) counters[tid] = 0;
+    const Instr& I = plan.ins[plan.fused.ins[m]];
+    MxTab& T = tabs[m];
+    const MaskInfo mi = mask_info(params, I, L, sh, nullptr, nullptr, nullptr);
+    const bool core = mi.any && mi.clo <= mi.chi;
+    const int NK = mi.any ? (16 + mi.khi - mi.klo + 31) / 32 : 0;
+    const double scale = core ? (double)mi.wc : 1.0;
+    const MaskP mp = mask_params(params + I.mask, I.flags & F_MASK_UNB);
+    if (s == 0 && tid == 0) {
+        T.ok = NK <= NKMAX;
+        T.any = mi.any;
+        T.klo = mi.klo;
+        T.khi = mi.khi;
+        T.clo = core ? mi.clo : 1;
+        T.chi = core ? mi.chi : 0;
+        T.NK = NK;
+        T.lscale = (float)log2(scale);
+    }
+    if (NK > NKMAX) return;                      // uniform over the work-group
+    const bool live = s < NK;                    // steps past NK: zero tiles
+    auto in_core = [&](int k) { return core && k >= mi.clo && k <= mi.chi; };
+    // weight of offset k divided by the scale (core offsets: exactly 1)
+    auto wk = [&](int k) -> double {
+        if (!live || k < mi.klo || k > mi.khi) return 0.0;
+        if (in_core(k)) return 1.0;
+        return (double)mask_wk(mp, k) / scale;
+    };
+    bool lf = false, lb = false, nza = false, nzb = false;
+    for (int e = tid; e < 512; e += blockDim.x) {
+        const int l = e >> 3, v = e & 7;
+        const int row = l & 15, col = 8 * (l >> 4) + v;
+        unsigned h, lo;
+        split2(wk(mi.klo + 32 * s + col - row), h, lo);
+        ((unsigned short*)&T.Wf[s][0][l])[v] = (unsigned short)h;
+        ((unsigned short*)&T.Wf[s][1][l])[v] = (unsigned short)lo;
+        lf |= lo != 0;
+        const int k = mi.khi - 32 * s + row - col;
+        split2(wk(k), h, lo);
+        ((unsigned short*)&T.Wb[s][0][l])[v] = (unsigned short)h;
+        ((unsigned short*)&T.Wb[s][1][l])[v] = (unsigned short)lo;
+        lb |= lo != 0;
+        // derivative weights (bands only: the core contributes nothing to
+        // d/da, d/db to fp32 rounding)
+        float da = 0.f, db = 0.f;
+        if (live && k >= mi.klo && k <= mi.khi && !in_core(k)) mask_wk(mp, k, &da, &db);
+        nza |= da != 0.f;
+        nzb |= db != 0.f;
+        split2((double)da, h, lo);
+        ((unsigned short*)&T.Dt[s][0][0][l])[v] = (unsigned short)h;
+        ((unsigned short*)&T.Dt[s][0][1][l])[v] = (unsigned short)lo;
+        split2((double)db, h, lo);
+        ((unsigned short*)&T.Dt[s][1][0][l])[v] = (unsigned short)h;
+        ((unsigned short*)&T.Dt[s][1][1][l])[v] = (unsigned short)lo;
+    }
+    lf = __syncthreads_or(lf);
+    lb = __syncthreads_or(lb);
+    nza = __syncthreads_or(nza);
+    nzb = __syncthreads_or(nzb);
+    if (tid == 0) {
+        T.flo_f[s] = lf;
+        T.flo_b[s] = lb;
+        T.fd[s] = (nza ? 1 : 0) | (nzb ? 2 : 0);
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+
+struct MxShared {
+    float R[MX_MAXN][MXG];       // forward: reference of the terms; backward: Q
+    int frag[MXG];               // trajectory handed to the generic executor
+    int omin[MX_MAXN][MXG];      // forward: floor(min O), ceil(max O) over the trajectory
+    int omax[MX_MAXN][MXG];
+    int dstep[MX_MAXN][NDMAX];   // backward: K-step and kind (0: d/da, 1: d/db) of each derivative tile
+    int dwhich[MX_MAXN][NDMAX];
+    int nd[MX_MAXN];
+    int over;                    // backward: more derivative tiles than NDMAX
+    float pp[MX_MAXN][2][MXWPM][MXG];   // backward: d/da, d/db partials per wave
+};
+
+DEV void mx_handoff(const KArgs& ka, const MxArgs& mx, int64_t b)
+{
+    if (atomicExch(&mx.handed[b], 1) == 0) ka.list[atomicAdd(ka.list_count, 1)] = (int)b;
+    if (ka.saved_flag) ka.saved_flag[b] = 0;
+}
+
+// byte offset in a ring row of the 8-position group starting at position p (p % 8 == 0)
+DEV int ring_off(int p) { return (p % MXRING) / 8 * 32; }
+
+// ring offset of position pbase + d, 0 <= d < 2 MXRING, given pr = pbase % MXRING
+DEV int ring_off2(int pr, int d)
+{
+    int q = pr + d;
+    q = q >= MXRING ? q - MXRING : q;
+    q = q >= MXRING ? q - MXRING : q;
+    return q / 8 * 32;
+}
+
+// the two output tiles (16 outputs each) of wave pair index wq in round k:
+// (t, t + 32) with t = 128 k + 64 (wq / 2) + 16 (wq % 2)
+DEV int mx_pair_t(int k, int wq) { return MXROUND * k + 64 * (wq >> 1) + 16 * (wq & 1); }
+
+// per-mask constants of the linear predicate and the exponent scale, in
+// registers (reading them from the plan inside a loop would put a load and a
+// wait in every iteration)
+template <int DD>
+struct MxMask {
+    float sg, beta, sbl;         // sign (-1 for Always), beta, sg beta log2(e)
+    float c, w[DD];              // predicate w . x - c
+};
+
+template <int DD>
+DEV MxMask<DD> mx_mask(const DevPlan* Pk, const float* params, int m)
+{
+    MxMask<DD> r;
+    const Instr& I = Pk->ins[Pk->fused.ins[m]];
+    r.sg = (I.flags & F_MIN) ? -1.f : 1.f;
+    r.beta = params[I.beta];
+    r.sbl = r.sg * r.beta * LOG2E;
+    const float* cf = &Pk->coef[Pk->ins[Pk->fused.pred[m]].coef];
+    r.c = cf[0];
+#pragma unroll
+    for (int d = 0; d < DD; ++d) r.w[d] = cf[1 + d];
+    return r;
+}
+
+template <int DD>
+DEV float mx_zx(const MxMask<DD>& M, const float* xv)
+{
+    float u = -M.c;
+#pragma unroll
+    for (int d = 0; d < DD; ++d) u = fmaf(M.w[d], xv[d], u);
+    return M.sbl * u;
+}
+
+// the root: the smooth And/Or over the mask traces (the same formula as the
+// fused kernels' fused_root), with its constants in registers
+struct MxRoot {
+    bool nary;
+    float sg, bl, ibl;
+};
+
+DEV MxRoot mx_root_consts(const DevPlan& P, const float* params)
+{
+    MxRoot r;
+    r.nary = P.fused.root_nary != 0 || P.fused.n > 1;
+    r.sg = P.fused.nary_min ? -1.f : 1.f;
+    r.bl = r.nary ? params[P.fused.nary_beta] * LOG2E : 1.f;
+    r.ibl = 1.f / r.bl;
+    return r;
+}
+
+template <int N>
+DEV float mx_root(const MxRoot& R, const float* v, float* wts)
+{
+    if (N == 1 && !R.nary) {
+        if (wts) wts[0] = 1.f;
+        return v[0];
+    }
+    float m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < N; ++k) m = fmaxf(m, R.sg * v[k]);
+    float s = 0.f, ek[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        ek[k] = ex2((R.sg * v[k] - m) * R.bl);
+        s += ek[k];
+    }
+    const float r = R.sg * (m + lg2(s) * R.ibl);
+    if (wts) {
+        const float is = __builtin_amdgcn_rcpf(s);
+#pragma unroll
+        for (int k = 0; k < N; ++k) wts[k] = ek[k] * is;
+    }
+    return r;
+}
+
+// four consecutive floats at p[i0 ..] (fewer when n_valid < 4), vectorised when aligned
+DEV void store4(float* p, int64_t i0, int n_valid, const float* v)
+{
+    if (n_valid >= 4 && (((uintptr_t)(p + i0)) & 15) == 0) {
+        *(float4*)(p + i0) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        for (int r = 0; r < 4 && r < n_valid; ++r) p[i0 + r] = v[r];
+    }
+}
+
+// keep a value in registers across a loop (the compiler may otherwise reload
+// loop-invariant tiles from memory inside it, each load followed by a wait)
+DEV void mx_pin(bf16x8& v) { asm volatile("" : "+v"(v)); }
+
+// x where keep, else 0, without a select: a select of a loaded value lets
+// the compiler turn the load into a conditional one under a branch, followed
+// by a wait for it
+DEV float keep_if(float x, bool keep) { return __int_as_float(__float_as_int(x) & -(int)keep); }
+
+// 8 DD floats of x (positions j .. j+7 of row xb) into v; positions at or
+// past L (all of them when L = 0) read as zero.  The loads themselves are
+// unconditional (clamped addresses, then a select): a load under a branch
+// would be followed by a wait for it.
+template <int DD>
+DEV void mx_load_x8(const float* xb, int j, int L, float* v)
+{
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int jc = min(max(j + q, 0), max(L - 1, 0));
+#pragma unroll
+        for (int d = 0; d < DD; ++d) {
+            v[q * DD + d] = keep_if(xb[(int64_t)jc * DD + d], j + q < L);
+        }
+    }
+}
+
+
+
+template <int N, int DD>
+__global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt, KArgs ka, MxArgs mx)
+{
+    extern __shared__ __align__(16) unsigned char mxs[];
+    __shared__ MxShared sh;
+    const DevPlan& P = plan;
+    // the plan is read from the kernel-argument segment where the mask index
+    // is a run-time value (indexing the by-value argument would copy it to
+    // private memory)
+    const DevPlan* Pk = (const DevPlan*)__builtin_amdgcn_kernarg_segment_ptr();
+    const MxRoot RC = mx_root_consts(P, ka.params);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = wv / MXWPM, wq = wv % MXWPM;
+    const int L = (int)bt.T;
+    const int64_t g0 = (int64_t)blockIdx.x * MXG;
+    bool ok = true;
+#pragma unroll
+    for (int mm = 0; mm < N; ++mm) ok = ok && mx.tabs[mm].ok;
+    if (!ok) {
+        // the masks do not fit the matrix-core path: the generic executor takes every trajectory
+        if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
+        return;
+    }
+    if (tid < MXG) {
+        sh.frag[tid] = 0;
+#pragma unroll
+        for (int mm = 0; mm < N; ++mm) {
+            sh.omin[mm][tid] = INT_MAX;
+            sh.omax[mm][tid] = INT_MIN;
+        }
+    }
+    // ---- references: midpoint of the exponents over a strided sample of each
+    // trajectory (positions i * ceil(L / 32), i < 32, one load per thread for
+    // every mask), reduced over each half-wave
+    {
+        const int hw = tid >> 5, l32 = lane & 31;
+        for (int r = hw; r < MXG; r += 8 * N) {
+            const int64_t b = g0 + r;
+            const int j = min(L - 1, l32 * ((L + 31) / 32));
+            float xv[DD];
+#pragma unroll
+            for (int d = 0; d < DD; ++d) xv[d] = bt.x[((b < bt.B ? b : 0) * L + j) * DD + d];
+#pragma unroll
+            for (int mm = 0; mm < N; ++mm) {
+                const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, mm);
+                const float z = b < bt.B ? mx_zx<DD>(M, xv) : -INFINITY;
+                const float zmax = half_max(z), zmin = half_min(b < bt.B ? z : INFINITY);
+                if (l32 == 0) sh.R[mm][r] = zmax >= zmin ? floorf(0.5f * (zmax + zmin)) : 0.f;
+            }
+        }
+    }
+    __syncthreads();
+    // ---- staging: thread tid owns the 8-position group g of trajectory row sr
+    // of mask sm in every block
+    const int sm = tid >> 8, sr = (tid >> 4) & 15, sg8 = tid & 15;
+    const int64_t sb = g0 + sr;
+    const bool srow = sb < bt.B;
+    const MxTab& TS = mx.tabs[sm];
+    const MxMask<DD> MS = mx_mask<DD>(Pk, ka.params, sm);
+    const int sklo = TS.klo;
+    const bool sany = TS.any;
+    const float* sxb = bt.x + (srow ? sb : 0) * (int64_t)L * DD;
+    unsigned char* srowp = mxs + (sm * MXG + sr) * MXRS;
+    const float sR = sh.R[sm][sr];
+    bool sfrag = false;
+    // terms of block blk from the DD x 8 values xv (positions 128 blk + 8 g ..)
+    auto stage_write = [&](int blk, const float* xv) {
+        const int p0 = MXBLK * blk + 8 * sg8;
+        float e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = p0 + q + sklo;
+            e[q] = 0.f;
+            if (srow && sany && j < L) {
+                const float d = mx_zx<DD>(MS, xv + q * DD) - sR;
+                sfrag |= !(fabsf(d) <= MX_HALF);
+                e[q] = ex2(fminf(fmaxf(d, -MX_HALF), MX_HALF));
+            }
+        }
+        bf16x8 h, l;
+        split8(e, h, l);
+        unsigned char* q = srowp + ring_off(p0);
+        *(bf16x8*)q = h;
+        *(bf16x8*)(q + 16) = l;
+    };
+    {
+        float xv[4][8 * DD];
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) mx_load_x8<DD>(sxb, MXBLK * blk + 8 * sg8 + sklo, srow && sany ? L : 0, xv[blk]);
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) stage_write(blk, xv[blk]);
+    }
+    // ---- this wave's mask: weight tiles, constants
+    const MxTab& T = mx.tabs[m];
+    const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, m);
+    const float ibl = 1.f / (M.beta * LOG2E);
+    const int klo = T.klo;
+    const bool any = T.any;
+    const float lscale = T.lscale;
+    // hi tiles in registers, lo tiles (zero on the core steps) in LDS
+    uint4* wlds = (uint4*)(mxs + N * MXG * MXRS + (size_t)(N - 1) * MXG * MXXS * sizeof(float));
+    for (int e = tid; e < N * NKMAX * 64; e += blockDim.x) {
+        const int mm = e / (NKMAX * 64), st = (e / 64) % NKMAX, l = e & 63;
+        wlds[e] = mx.tabs[mm].Wf[st][1][l];
+    }
+    const uint4* wl_m = wlds + m * NKMAX * 64 + lane;
+    bf16x8 Wh[NKMAX];
+#pragma unroll
+    for (int s = 0; s < NKMAX; ++s) Wh[s] = tile_ld(&T.Wf[s][0][lane]);
+    // (pinned here: the wait for these loads happens once, before the loop)
+#pragma unroll
+    for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
+    const int bc = lane & 15, rq = lane >> 4;
+    const int64_t bo = g0 + bc;
+    const bool bvalid = bo < bt.B;
+    const unsigned char* ebase = mxs + (m * MXG + bc) * MXRS;
+    float* xch = (float*)(mxs + N * MXG * MXRS);     // [N-1][16][MXXS] traces of masks 1..N-1
+    float omin = INFINITY, omax = -INFINITY;
+    const int nround = (L + MXROUND - 1) / MXROUND;
+    __syncthreads();
+    const float Rb = sh.R[m][bc] + lscale;
+    // x of block k+4 is loaded two rounds before it is written (memory latency
+    // under load exceeds one round); the loop is unrolled by two so that the
+    // two prefetch buffers keep static register names
+    float xq0[8 * DD], xq1[8 * DD];
+    mx_load_x8<DD>(sxb, MXBLK * 4 + 8 * sg8 + sklo, srow && sany ? L : 0, xq0);
+    auto round = [&](const int k, const float* xn, float* xnext) {
+        mx_load_x8<DD>(sxb, MXBLK * (k + 5) + 8 * sg8 + sklo, srow && sany ? L : 0, xnext);
+        const int tA = mx_pair_t(k, wq);
+        mxf4 accA = {0.f, 0.f, 0.f, 0.f}, accB = accA;
+        const int pr = (tA + 8 * rq) % MXRING;
+        bf16x8 wlp;
+#pragma unroll
+        for (int s = 0; s <= NKMAX; ++s) {
+            const unsigned char* ep = ebase + ring_off2(pr, 32 * s);
+            const bf16x8 eh = ld_bf16x8(ep), el = ld_bf16x8(ep + 16);
+            if (s < NKMAX) {
+                const bf16x8 wl = ld_bf16x8(wl_m + s * 64);
+                accA = mfma(Wh[s], eh, accA);
+                accA = mfma(Wh[s], el, accA);
+                accA = mfma(wl, eh, accA);
+                if (s >= 1) {
+                    accB = mfma(Wh[s - 1], eh, accB);
+                    accB = mfma(Wh[s - 1], el, accB);
+                    accB = mfma(wlp, eh, accB);
+                }
+                wlp = wl;
+            } else {
+                accB = mfma(Wh[s - 1], eh, accB);
+                accB = mfma(Wh[s - 1], el, accB);
+                accB = mfma(wlp, eh, accB);
+            }
+        }
+        // traces of this lane's outputs t0 + 4 (l / 16) + rr of both tiles
+        float tr[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const mxf4 a = h ? accB : accA;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int t = tA + 32 * h + 4 * rq + rr;
+                float o = -M.sg * P.rho_pad;
+                if (any && t + klo <= L - 1) {
+                    const float O = Rb + lg2(a[rr]);
+                    o = M.sg * O * ibl;
+                    omin = fminf(omin, O);
+                    omax = fmaxf(omax, O);
+                }
+                tr[h][rr] = o;
+            }
+        }
+        if (N > 1 && m > 0) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                *(float4*)&xch[((m - 1) * MXG + bc) * MXXS + (tA - MXROUND * k) + 32 * h + 4 * rq] =
+                    make_float4(tr[h][0], tr[h][1], tr[h][2], tr[h][3]);
+        }
+        if (N > 1) __syncthreads();
+        if (bvalid) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t0 = tA + 32 * h + 4 * rq;
+                const int nv = L - t0;
+                if (nv <= 0) continue;
+                if (m == 0) {
+                    float rt[4];
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        float v[N];
+                        v[0] = tr[h][rr];
+#pragma unroll
+                        for (int mm = 1; mm < N; ++mm)
+                            v[mm] = xch[((mm - 1) * MXG + bc) * MXXS + (t0 - MXROUND * k) + rr];
+                        rt[rr] = mx_root<N>(RC, v, nullptr);
+                    }
+                    if (ka.root) store4(ka.root, bo * (int64_t)L + t0, nv, rt);
+                }
+                if (ka.saved) store4(ka.saved, ((int64_t)m * bt.B + bo) * L + t0, nv, tr[h]);
+            }
+        }
+        stage_write(k + 4, xn);
+#pragma unroll
+        for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
+        __syncthreads();
+    };
+    for (int k = 0; k < nround; k += 2) {
+        round(k, xq0, xq1);
+        if (k + 1 < nround) round(k + 1, xq1, xq0);
+    }
+    // ---- exponent ranges of the traces (for the backward), hand-offs
+    if (any && bvalid && omin <= omax) {
+        atomicMin(&sh.omin[m][bc], (int)floorf(omin));
+        atomicMax(&sh.omax[m][bc], (int)ceilf(omax));
+    }
+    if (sfrag) atomicOr(&sh.frag[sr], 1);
+    __syncthreads();
+    if (mx.ranges && tid < N * MXG) {
+        const int mm = tid / MXG, r = tid % MXG;
+        if (g0 + r < bt.B) {
+            int* rp = mx.ranges + ((g0 + r) * N + mm) * 2;
+            rp[0] = sh.omin[mm][r];
+            rp[1] = sh.omax[mm][r];
+        }
+    }
+    if (tid < MXG && sh.frag[tid] && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
+}
+
+template <int N, int DD>
+__global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt, KArgs ka, MxArgs mx)
+{
+    extern __shared__ __align__(16) unsigned char mxs[];
+    __shared__ MxShared sh;
+    const DevPlan& P = plan;
+    const DevPlan* Pk = (const DevPlan*)__builtin_amdgcn_kernarg_segment_ptr();
+    const MxRoot RC = mx_root_consts(P, ka.params);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = wv / MXWPM, wq = wv % MXWPM;
+    const int L = (int)bt.T;
+    const int64_t g0 = (int64_t)blockIdx.x * MXG;
+    bool ok = true;
+#pragma unroll
+    for (int mm = 0; mm < N; ++mm) ok = ok && mx.tabs[mm].ok;
+    if (!ok) {
+        if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
+        return;
+    }
+    // ---- per mask: the list of derivative tiles (K-step, kind)
+    if (tid == 0) sh.over = 0;
+    if (tid < MXG) sh.frag[tid] = 0;
+    __syncthreads();
+    if (tid < N) {
+        const MxTab& T = mx.tabs[tid];
+        int nd = 0;
+        bool over = false;
+        for (int s = 0; s < T.NK; ++s)
+            for (int w = 0; w < 2; ++w)
+                if ((T.fd[s] >> w) & 1) {
+                    if (nd < NDMAX) {
+                        sh.dstep[tid][nd] = s;
+                        sh.dwhich[tid][nd] = w;
+                        ++nd;
+                    } else {
+                        over = true;
+                    }
+                }
+        sh.nd[tid] = nd;
+        if (over) sh.over = 1;
+    }
+    // ---- per trajectory: saved traces valid, reference Q from the forward's range of O
+    if (tid < N * MXG) {
+        const int mm = tid / MXG, r = tid % MXG;
+        const int64_t b = g0 + r;
+        float Q = 0.f;
+        if (b < bt.B) {
+            bool frag = ka.saved_flag[b] != 2;
+            if (!frag) {
+                const int* rp = mx.ranges + (b * N + mm) * 2;
+                const int lo = rp[0], hi = rp[1];
+                if (lo <= hi) {
+                    if ((float)hi - (float)lo > 2.f * MX_HALF) frag = true;
+                    else Q = -floorf(0.5f * ((float)lo + (float)hi));
+                }
+            }
+            if (frag) atomicOr(&sh.frag[r], 1);
+        }
+        sh.R[mm][r] = Q;
+    }
+    __syncthreads();
+    const bool over = sh.over != 0;
+    // ---- staging: thread tid owns the 8-position group g of trajectory row sr
+    // of mask sm in every block.  Position p of mask m is time t = p - khi_m;
+    // H_m(t) = G(t) wt_m(t) 2^{-O_m(t) - Q} (0 outside the trajectory and where
+    // the window of t is empty)
+    const int sm = tid >> 8, sr = (tid >> 4) & 15, sg8 = tid & 15;
+    const int64_t sb = g0 + sr;
+    const bool srow = sb < bt.B && !sh.frag[sr] && !over;
+    const MxTab& TS = mx.tabs[sm];
+    const MxMask<DD> MS = mx_mask<DD>(Pk, ka.params, sm);
+    const int skhi = TS.khi, sklo = TS.klo;
+    const bool sany = TS.any;
+    const float* sG = ka.G + (srow ? sb : 0) * (int64_t)L;
+    const float* str[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) str[n] = ka.saved_in + ((int64_t)n * bt.B + (srow ? sb : 0)) * L;
+    unsigned char* srowp = mxs + (sm * MXG + sr) * MXRS;
+    const float sQ = sh.R[sm][sr];
+    const bool sact = srow && sany;
+    // G and the saved traces at t .. t+7 (zero outside [0, L))
+    auto stage_load = [&](int blk, float* gv, float (*tv)[8]) {
+        const int t0 = MXBLK * blk + 8 * sg8 - skhi;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int t = t0 + q;
+            const bool in = sact && t >= 0 && t < L;
+            const int tc = min(max(t, 0), L - 1);     // unconditional loads (see mx_load_x8)
+            gv[q] = keep_if(sG[tc], in);
+#pragma unroll
+            for (int n = 0; n < N; ++n) tv[n][q] = keep_if(str[n][tc], in);
+        }
+    };
+    auto stage_write = [&](int blk, const float* gv, float (*tv)[8]) {
+        const int p0 = MXBLK * blk + 8 * sg8, t0 = p0 - skhi;
+        float h[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int t = t0 + q;
+            h[q] = 0.f;
+            if (sact && t >= 0 && t + sklo <= L - 1) {
+                float v[N], wts[N];
+#pragma unroll
+                for (int n = 0; n < N; ++n) v[n] = tv[n][q];
+                mx_root<N>(RC, v, wts);
+                float wm = wts[0], tm = v[0];
+#pragma unroll
+                for (int n = 1; n < N; ++n) {
+                    wm = n == sm ? wts[n] : wm;
+                    tm = n == sm ? v[n] : tm;
+                }
+                // -O - Q lies within [-MX_HALF, MX_HALF] (the forward's range check)
+                h[q] = gv[q] * wm * ex2(fminf(fmaxf(-MS.sbl * tm - sQ, -2.f * MX_HALF), 2.f * MX_HALF));
+            }
+        }
+        bf16x8 hh, hl;
+        split8(h, hh, hl);
+        unsigned char* q = srowp + ring_off(p0);
+        *(bf16x8*)q = hh;
+        *(bf16x8*)(q + 16) = hl;
+    };
+    {
+        float gv[4][8], tv[4][N][8];
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) stage_load(blk, gv[blk], tv[blk]);
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) stage_write(blk, gv[blk], tv[blk]);
+    }
+    // ---- this wave's mask: weight and derivative tiles, constants
+    const MxTab& T = mx.tabs[m];
+    const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, m);
+    const bool any = T.any;
+    // hi tiles in registers, lo tiles in LDS (after the derivative tiles)
+    uint4* wlds = (uint4*)(mxs + N * MXG * MXRS + (size_t)(N - 1) * MXG * MXXS * DD * sizeof(float)) +
+                  N * NDMAX * 128;
+    for (int e = tid; e < N * NKMAX * 64; e += blockDim.x) {
+        const int mm = e / (NKMAX * 64), st = (e / 64) % NKMAX, l = e & 63;
+        wlds[e] = mx.tabs[mm].Wb[st][1][l];
+    }
+    const uint4* wl_m = wlds + m * NKMAX * 64 + lane;
+    bf16x8 Wh[NKMAX];
+#pragma unroll
+    for (int s = 0; s < NKMAX; ++s) Wh[s] = tile_ld(&T.Wb[s][0][lane]);
+#pragma unroll
+    for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
+    // derivative tiles of every mask in LDS ([n][NDMAX][hi, lo][lane], zero
+    // tiles in unused slots)
+    uint4* dlds = (uint4*)(mxs + N * MXG * MXRS + (size_t)(N - 1) * MXG * MXXS * DD * sizeof(float));
+    for (int e = tid; e < N * NDMAX * 2 * 64; e += blockDim.x) {
+        const int mm = e / (NDMAX * 128), d = (e / 128) % NDMAX, hl = (e / 64) & 1, l = e & 63;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (d < sh.nd[mm]) v = mx.tabs[mm].Dt[sh.dstep[mm][d]][sh.dwhich[mm][d]][hl][l];
+        dlds[e] = v;
+    }
+    const int nd = sh.nd[m];
+    int dst[NDMAX];
+    bool isb[NDMAX];
+#pragma unroll
+    for (int d = 0; d < NDMAX; ++d) {
+        const bool use = d < nd;
+        dst[d] = use ? sh.dstep[m][d] : 0;
+        isb[d] = use && sh.dwhich[m][d] != 0;
+    }
+    const uint4* dl_m = dlds + m * NDMAX * 128 + lane;
+    const int bc = lane & 15, rq = lane >> 4;
+    const int64_t bo = g0 + bc;
+    const bool bvalid = bo < bt.B && !sh.frag[bc] && !over;
+    const float* xo = bt.x + (bo < bt.B ? bo : 0) * (int64_t)L * DD;
+    const unsigned char* hbase = mxs + (m * MXG + bc) * MXRS;
+    float* xch = (float*)(mxs + N * MXG * MXRS);     // [N-1][16][MXXS][DD] d/dx of masks 1..N-1
+    const float Qb = sh.R[m][bc];
+    float pam = 0.f, pbm = 0.f;
+    const int nround = (L + MXROUND - 1) / MXROUND;
+    __syncthreads();
+    for (int k = 0; k < nround; ++k) {
+        // loads of block k+4 go out first
+        float gn[8], tn[N][8];
+        stage_load(k + 4, gn, tn);
+        const int tA0 = mx_pair_t(k, wq);
+        // and x at this lane's outputs
+        float xv[2][4 * DD];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int j = tA0 + 32 * h + 4 * rq + rr;
+                const int jc = min(j, L - 1);
+#pragma unroll
+                for (int d = 0; d < DD; ++d) xv[h][rr * DD + d] = keep_if(xo[(int64_t)jc * DD + d], bvalid && j < L);
+            }
+        const int tA = mx_pair_t(k, wq);
+        mxf4 accA = {0.f, 0.f, 0.f, 0.f}, accB = accA;
+        const int pr = (tA + 8 * rq) % MXRING;
+        bf16x8 wlp;
+#pragma unroll
+        for (int s = 0; s <= NKMAX; ++s) {
+            const unsigned char* ep = hbase + ring_off2(pr, 32 * s);
+            const bf16x8 hh = ld_bf16x8(ep), hl = ld_bf16x8(ep + 16);
+            if (s < NKMAX) {
+                const bf16x8 wl = ld_bf16x8(wl_m + s * 64);
+                accA = mfma(Wh[s], hh, accA);
+                accA = mfma(Wh[s], hl, accA);
+                accA = mfma(wl, hh, accA);
+                if (s >= 1) {
+                    accB = mfma(Wh[s - 1], hh, accB);
+                    accB = mfma(Wh[s - 1], hl, accB);
+                    accB = mfma(wlp, hh, accB);
+                }
+                wlp = wl;
+            } else {
+                accB = mfma(Wh[s - 1], hh, accB);
+                accB = mfma(Wh[s - 1], hl, accB);
+                accB = mfma(wlp, hh, accB);
+            }
+        }
+        // 2^{z_j + Q} = f 2^n at this lane's outputs (the products below are
+        // moderate even where the factors are not); f = 0 where j is not an output
+        float fj[2][4];
+        int nj[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int j = tA + 32 * h + 4 * rq + rr;
+                const float e = mx_zx<DD>(M, xv[h] + rr * DD) + Qb;
+                const float fl = floorf(e);
+                fj[h][rr] = (any && bvalid && j < L) ? ex2(e - fl) : 0.f;
+                nj[h][rr] = (int)fminf(fmaxf(fl, -300.f), 300.f);
+            }
+        // d/dx contributions of this mask at the lane's positions
+        float gx[2][4 * DD];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const mxf4 a = h ? accB : accA;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const float gu = ldexpf(a[rr] * fj[h][rr], nj[h][rr]);
+#pragma unroll
+                for (int d = 0; d < DD; ++d) gx[h][rr * DD + d] = M.w[d] * gu;
+            }
+        }
+        // derivative sums (K-step dst[d] of tile A, and of tile B one step
+        // later), added straight into this lane's d/da, d/db partials
+#pragma unroll
+        for (int d = 0; d < NDMAX; ++d) {
+            const bf16x8 Dh = ld_bf16x8(dl_m + d * 128), Dl = ld_bf16x8(dl_m + d * 128 + 64);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const unsigned char* ep = hbase + ring_off2(pr, 32 * (dst[d] + h));
+                const bf16x8 hh = ld_bf16x8(ep), hl = ld_bf16x8(ep + 16);
+                mxf4 a = mfma(Dh, hh, mxf4{0.f, 0.f, 0.f, 0.f});
+                a = mfma(Dh, hl, a);
+                a = mfma(Dl, hh, a);
+                float sum = 0.f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sum += ldexpf(a[q] * fj[h][q], nj[h][q]);
+                pam += isb[d] ? 0.f : sum;
+                pbm += isb[d] ? sum : 0.f;
+            }
+        }
+        if (N > 1 && m > 0) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < 4 * DD; ++q)
+                    xch[(((m - 1) * MXG + bc) * MXXS + (tA - MXROUND * k) + 32 * h + 4 * rq) * DD + q] = gx[h][q];
+        }
+        if (N > 1) __syncthreads();
+        if (m == 0 && bvalid) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j0 = tA + 32 * h + 4 * rq;
+                const int nv = min(4, L - j0);
+                if (nv <= 0) continue;
+#pragma unroll
+                for (int mm = 1; mm < N; ++mm)
+#pragma unroll
+                    for (int q = 0; q < 4 * DD; ++q)
+                        gx[h][q] += xch[(((mm - 1) * MXG + bc) * MXXS + (j0 - MXROUND * k)) * DD + q];
+                float* dp = ka.dx + (bo * (int64_t)L + j0) * DD;
+                if (nv == 4 && (((uintptr_t)dp) & 15) == 0) {
+#pragma unroll
+                    for (int q = 0; q < DD; ++q)
+                        *(float4*)(dp + 4 * q) = make_float4(gx[h][4 * q], gx[h][4 * q + 1], gx[h][4 * q + 2], gx[h][4 * q + 3]);
+                } else {
+                    for (int q = 0; q < nv * DD; ++q) dp[q] = gx[h][q];
+                }
+            }
+        }
+        stage_write(k + 4, gn, tn);
+#pragma unroll
+        for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
+        __syncthreads();
+    }
+    // ---- d/da, d/db partials: lanes of one trajectory (l, l + 16, l + 32,
+    // l + 48), then the mask's waves in order
+    pam *= M.sg / M.beta;
+    pbm *= M.sg / M.beta;
+    pam += __shfl_xor(pam, 16);
+    pbm += __shfl_xor(pbm, 16);
+    pam += __shfl_xor(pam, 32);
+    pbm += __shfl_xor(pbm, 32);
+    if (lane < MXG) {
+        sh.pp[m][0][wq][lane] = pam;
+        sh.pp[m][1][wq][lane] = pbm;
+    }
+    __syncthreads();
+    if (tid < 2 * N * MXG) {
+        const int mm = tid / (2 * MXG), ab = (tid / MXG) & 1, r = tid % MXG;
+        const int64_t bq = g0 + r;
+        if (bq < bt.B && !sh.frag[r] && !over) {
+            float s = 0.f;
+            for (int w = 0; w < MXWPM; ++w) s += sh.pp[mm][ab][w][r];
+            const int slot = Pk->ins[Pk->fused.ins[mm]].mslot;
+            if (slot >= 0) mx.part[(bq * P.n_masks + slot) * 2 + ab] = s;
+        }
+    }
+    if (tid < MXG && (sh.frag[tid] || over) && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
+}
+
+}  // namespace stlmi

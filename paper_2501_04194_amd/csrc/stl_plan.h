@@ -124,6 +124,17 @@ struct KArgs {
     float* saved;          // fused forward: mask-node traces out ([n][B][T]) or NULL
     const float* saved_in; // fused backward: mask-node traces in, or NULL (recompute)
     int* saved_flag;       // [B]: 1 where the saved traces of a trajectory are valid
+    int part_stride;       // rows of mask_part per trajectory (1; a caller with more rows per
+                           // trajectory has the generic executor clear the others)
+};
+
+// Launch arguments of the matrix-core smooth-mask kernels (stl_mx.h).
+struct MxTab;
+struct MxArgs {
+    const MxTab* tabs;
+    int* handed;           // [B] 1 once a trajectory is on the hand-off list
+    int* ranges;           // [B][n][2] floor(min), ceil(max) of O over each trajectory's trace
+    float* part;           // [B][n_masks][2] d/da, d/db partials
 };
 
 }  // namespace stlmi

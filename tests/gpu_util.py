@@ -17,10 +17,12 @@ or TRUE's rho_max) must match bit for bit.  Other values of sentinel
 magnitude (|r| >= 1e5: what a smooth operator derives from sentinels, e.g. a
 logsumexp over several of them, 1e6 +- log(K)/beta) compare at 1e-5 of their
 own magnitude, and are left out of S (which would otherwise loosen the bound
-of the ordinary values to 10).  A test whose smooth operators take a single
-sentinel as their whole window passes exact_sentinels=False: the float32
-exponent beta log2(e) 1e6 = 1.4e7 carries a rounding of up to half a unit, so
-such a value is 1e6 only to within about 0.04.
+of the ordinary values to 10).  A test whose smooth operators take sentinels
+as operands (a logsumexp in which a sentinel dominates, so that the exact
+result rounds to 1e6 in fp64) passes exact_sentinels=False: in float32 such
+a value is 1e6 only to within a few units of its last place (0.0625), as the
+float32 exponent beta log2(e) 1e6 = 1.4e7 carries a rounding of up to half a
+unit.
 """
 import numpy as np
 
