@@ -255,6 +255,23 @@ stl_status stl_backward_saved(const stl_plan* plan, const stl_batch* batch, cons
                               float* d_grad_x, float* d_grad_params, void* d_ws, size_t ws_bytes,
                               const stl_launch* cfg, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): stl_forward
+ * whose workspace is a fixed device array inside the library instead of a
+ * d_ws argument.  The array holds STL_STATIC_WS_BYTES; each GPU the library
+ * runs on keeps its own copy until the process ends.  The call allocates
+ * nothing.  A batch whose forward workspace (stl_workspace_size) exceeds the
+ * array returns STL_E_WORKSPACE before any launch.  Every call on one GPU
+ * shares that GPU's copy, which keeps the previous call's contents (the
+ * kernels reset the counters they need themselves): calls that overlap on
+ * one GPU, from several streams or host threads, race and must be
+ * serialised by the caller.  Results equal stl_forward's bit for bit.
+ */
+#define STL_STATIC_WS_BYTES ((size_t)16 << 20)
+stl_status stl_forward_static(const stl_plan* plan, const stl_batch* batch, const float* d_params, float* d_root,
+                              float* d_node_traces, const stl_launch* cfg, void* stream);
+
 /* Message describing the last non-OK status returned on this thread. */
 const char* stl_last_error(void);
 

@@ -948,6 +948,56 @@ extern "C" stl_status stl_backward_saved(const stl_plan* plan, const stl_batch* 
                cfg, stream, 2, const_cast<void*>(d_saved), saved_bytes);
 }
 
+// ------------------------------------------------------------------ forward with a static workspace
+
+namespace {
+
+// The workspace of stl_forward_static.  In host code `scratch` names a host
+// stand-in, not device memory: kernels get the address that
+// hipGetSymbolAddress returns for the current device (one copy per GPU).
+static __device__ __align__(256) unsigned char scratch[STL_STATIC_WS_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;     // device -> its copy of `scratch`
+
+stl_status scratch_ptr(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(STL_E_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return STL_OK;
+    }
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+        return fail(STL_E_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+    *out = p;
+    return STL_OK;
+}
+
+}  // namespace
+
+extern "C" stl_status stl_forward_static(const stl_plan* plan, const stl_batch* batch, const float* d_params,
+                                         float* d_root, float* d_node_traces, const stl_launch* cfg, void* stream)
+{
+    stl_status s = check_batch(plan, batch);
+    if (s != STL_OK) return s;
+    Geom g;
+    if ((s = geometry(plan, batch, cfg, false, d_node_traces != nullptr, &g)) != STL_OK) return s;
+    if (g.ws_bytes > STL_STATIC_WS_BYTES)
+        return fail(STL_E_WORKSPACE, "stl_forward_static: this batch needs %zu bytes of workspace, more than the "
+                                     "static %zu", g.ws_bytes, (size_t)STL_STATIC_WS_BYTES);
+    void* ws = nullptr;
+    if ((s = scratch_ptr(&ws)) != STL_OK) return s;
+    return run(plan, batch, d_params, false, d_root, d_node_traces, nullptr, nullptr, nullptr, ws,
+               STL_STATIC_WS_BYTES, cfg, stream);
+}
+
 // ------------------------------------------------------------------ autotuner
 
 namespace {

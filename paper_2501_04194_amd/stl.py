@@ -62,7 +62,7 @@ _lib = None
 EXPORTS = ["stl_compile", "stl_plan_destroy", "stl_plan_info", "stl_workspace_size", "stl_forward",
            "stl_backward", "stl_saved_size", "stl_forward_saving", "stl_backward_saved", "stl_last_error",
            "stl_lpt_order", "stl_autotune", "stl_graph_capture", "stl_graph_launch", "stl_graph_destroy",
-           "stl_interval_sweep", "stl_pstl_descent"]
+           "stl_interval_sweep", "stl_pstl_descent", "stl_forward_static"]
 
 
 def lib():
@@ -86,6 +86,7 @@ def lib():
     L.stl_forward_saving.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, sz, vp, sz, ctypes.POINTER(Launch), vp]
     L.stl_backward_saved.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, sz, vp, vp, vp, vp, sz,
                                      ctypes.POINTER(Launch), vp]
+    L.stl_forward_static.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, ctypes.POINTER(Launch), vp]
     L.stl_last_error.restype = ctypes.c_char_p
     L.stl_lpt_order.argtypes = [ctypes.POINTER(i64), i64, ctypes.POINTER(i32)]
     L.stl_autotune.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(Launch),
@@ -333,6 +334,26 @@ class Plan:
         else:
             _check(lib().stl_forward(self._h, ctypes.byref(bt), _ptr(pvec), _ptr(root), _ptr(nodes), _ptr(ws),
                                      ws.numel(), lp, _stream(torch, x.device)))
+        if offsets is None:
+            root = root.view(x.shape[0], x.shape[1])
+            if nodes is not None:
+                nodes = nodes.view(self.n_nodes, x.shape[0], x.shape[1])
+        return (root, nodes) if node_traces else root
+
+    def forward_static(self, x, pvec, offsets=None, order=None, T=None, node_traces=False, launch=None):
+        """``forward`` through ``stl_forward_static``: the library's fixed
+        device workspace instead of one allocated here (the root and node
+        traces are still allocated by the caller, i.e. here)."""
+        import torch
+        _require_gpu(torch, x)
+        x = x.contiguous()
+        bt = self._batch(x, offsets, order, T)
+        N = x.shape[0] * x.shape[1] if offsets is None else x.shape[0]
+        root = torch.empty(N, dtype=torch.float32, device=x.device)
+        nodes = torch.empty((self.n_nodes, N), dtype=torch.float32, device=x.device) if node_traces else None
+        lp = None if launch is None else ctypes.byref(launch)
+        _check(lib().stl_forward_static(self._h, ctypes.byref(bt), _ptr(pvec), _ptr(root), _ptr(nodes), lp,
+                                        _stream(torch, x.device)))
         if offsets is None:
             root = root.view(x.shape[0], x.shape[1])
             if nodes is not None:
