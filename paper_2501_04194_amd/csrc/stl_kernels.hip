@@ -792,8 +792,13 @@ DEV void tail_weights(const float* v, float* out, int L, double tail, Shared& sh
 
 // Hard Until, one thread per output t: running min of phi over [t, t+i],
 // max over i in [a, b] of min(running min, psi_{t+i}); phi wins ties.
+// Adjoint (g != null): every output sends g_t to the one phi or psi sample
+// that decides it.  The target of each t goes to `code` (phi index k as k,
+// psi index k as -k-1, none as INT_MIN); then each position sums the g_t
+// that target it in increasing t, so the result does not depend on the
+// order in which threads finish.
 DEV void until_hard(const Env& e, int a, int b, const float* phi, const float* psi, float* out,
-                    const float* g, float* gphi, float* gpsi)
+                    const float* g, float* gphi, float* gpsi, int* code)
 {
     const int L = e.L;
     const float rho_pad = e.P->rho_pad;
@@ -801,6 +806,7 @@ DEV void until_hard(const Env& e, int a, int b, const float* phi, const float* p
         const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
         if (a > imax) {
             if (out) out[t] = -rho_pad;
+            if (g) code[t] = INT_MIN;
             continue;
         }
         float R = phi[t], best = -INFINITY;
@@ -817,10 +823,19 @@ DEV void until_hard(const Env& e, int a, int b, const float* phi, const float* p
             }
         }
         if (out) out[t] = best;
-        if (g) {
-            const float gt = g[t];
-            if (gt != 0.f) atomicAdd(tphi ? &gphi[tgt] : &gpsi[tgt], gt);
+        if (g) code[t] = tphi ? tgt : -tgt - 1;
+    }
+    if (!g) return;
+    __syncthreads();
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        float sp = 0.f, sq = 0.f;
+        for (int t = b < 0 ? 0 : max(0, j - b); t <= j; ++t) {
+            const int c = code[t];
+            if (c == j) sp += g[t];
+            else if (c == -j - 1) sq += g[t];
         }
+        gphi[j] += sp;
+        gpsi[j] += sq;
     }
 }
 
@@ -858,33 +873,47 @@ constexpr int UCK_UNIT = 7;   // scratch unit where its checkpoints start (units
 //   d out / d phi_{t+k} = e_k / Z * sum_{i >= max(k,a)} w_i Y_i^2,  e_k = 2^{-z_phi(t+k)}
 //   d out / d w_i = Y_i / (beta Z)   (summed against d w/da, d w/db into pa, pb)
 // Pass 1 recomputes Z and stores P every UCK steps; pass 2 walks the
-// checkpoint blocks backward, recomputing P inside each block, and adds the
-// contributions to the adjoint slots with LDS atomics.
+// checkpoint blocks backward, recomputing P inside each block.  The float
+// contributions go through the lane-shifted accumulators of lane_stage
+// (defined below), in the same fixed order as the fp64 adjoint.
+DEV void lane_stage_f(int i, int tb, int lane, int L, float& accp, float& accq, float& stp, float& stq,
+                      float* gphi, float* gpsi);
+
 DEV void until_smooth_adj(const Env& e, int a, int b, const float* w, const float* dwa, const float* dwb,
                           const SP* Ephi, const SP* Epsi, const float* g, float* gphi, float* gpsi, SP* ck,
                           int ncks, float& pa, float& pb)
 {
     const int L = e.L;
-    for (int t = threadIdx.x; t < L; t += blockDim.x) {
-        const int imax = b < 0 ? L - 1 - t : min(b, L - 1 - t);
-        const float gt = g[t];
-        if (a > imax || gt == 0.f) continue;
+    const int lane = threadIdx.x & 63;
+    for (int base = 0; base < L; base += blockDim.x) {
+        const int tb = base + (int)threadIdx.x - lane;
+        const int t = tb + lane;
+        const int imax = t >= L ? -1 : (b < 0 ? L - 1 - t : min(b, L - 1 - t));
+        const float gt = t < L ? g[t] : 0.f;
+        const bool act = a <= imax && gt != 0.f;
         SP* myck = ck + (size_t)threadIdx.x * ncks;
-        SP P = sp_zero(), Z = sp_zero();
-        for (int i = 0; i <= imax; ++i) {
-            if (i % UCK == 0) myck[i / UCK] = P;
-            P = sp_add(P, Ephi[t + i]);
-            if (i >= a) {
-                SP Dn = sp_add(P, Epsi[t + i]);
-                Z = sp_add(Z, SP{(w ? w[i] : 1.f) / Dn.s, -Dn.r});
+        SP Z = sp_zero();
+        if (act) {
+            SP P = sp_zero();
+            for (int i = 0; i <= imax; ++i) {
+                if (i % UCK == 0) myck[i / UCK] = P;
+                P = sp_add(P, Ephi[t + i]);
+                if (i >= a) {
+                    SP Dn = sp_add(P, Epsi[t + i]);
+                    Z = sp_add(Z, SP{(w ? w[i] : 1.f) / Dn.s, -Dn.r});
+                }
             }
         }
-        const float gz = gt / Z.s;          // G / Z = gz * 2^{-Z.r}
+        const float gz = act ? gt / Z.s : 0.f;      // G / Z = gz * 2^{-Z.r}
+        const int imax0 = b < 0 ? L - 1 - base : min(b, L - 1 - base);     // t = base: the longest chain
+        const int wblk = a <= imax0 ? imax0 / UCK + 1 : 0;
+        float accp = 0.f, accq = 0.f, stp = 0.f, stq = 0.f;
         SP A = sp_zero();                   // suffix sum of w_i Y_i^2
-        for (int blk = imax / UCK; blk >= 0; --blk) {
-            const int i0 = blk * UCK, i1 = min(imax, i0 + UCK - 1);
+        for (int blk = wblk - 1; blk >= 0; --blk) {
+            const int i0 = blk * UCK;
+            const int i1 = act ? min(imax, i0 + UCK - 1) : i0 - 1;      // this lane's last step in the block
             SP Ps[UCK];
-            SP Pc = myck[blk];
+            SP Pc = i0 <= i1 ? myck[blk] : sp_zero();
 #pragma unroll
             for (int q = 0; q < UCK; ++q) {
                 if (i0 + q <= i1) Pc = sp_add(Pc, Ephi[t + i0 + q]);
@@ -893,25 +922,32 @@ DEV void until_smooth_adj(const Env& e, int a, int b, const float* w, const floa
 #pragma unroll
             for (int q = UCK - 1; q >= 0; --q) {
                 const int i = i0 + q;
-                if (i > i1) continue;
-                if (i >= a) {
-                    const SP Q = Epsi[t + i];
-                    const SP Dn = sp_add(Ps[q], Q);
-                    const float y = 1.f / Dn.s;       // Y = y * 2^{-Dn.r}
-                    const SP Y2{(w ? w[i] : 1.f) * y * y, -2 * Dn.r};
-                    A = sp_add(A, Y2);
-                    // psi: gz * w Y^2 * Q  (exponent -Z.r - 2 Dn.r + Q.r)
-                    atomicAdd(&gpsi[t + i], ldexpf(gz * Y2.s * Q.s, clampe((long long)Y2.r + Q.r - Z.r)));
-                    if (w) {
-                        const int ex = clampe(-(long long)Dn.r - Z.r);
-                        pa += ldexpf(gz * dwa[i] * y, ex);
-                        pb += ldexpf(gz * dwb[i] * y, ex);
+                if (i <= i1) {
+                    if (i >= a) {
+                        const SP Q = Epsi[t + i];
+                        const SP Dn = sp_add(Ps[q], Q);
+                        const float y = 1.f / Dn.s;       // Y = y * 2^{-Dn.r}
+                        const SP Y2{(w ? w[i] : 1.f) * y * y, -2 * Dn.r};
+                        A = sp_add(A, Y2);
+                        // psi: gz * w Y^2 * Q  (exponent -Z.r - 2 Dn.r + Q.r)
+                        accq += ldexpf(gz * Y2.s * Q.s, clampe((long long)Y2.r + Q.r - Z.r));
+                        if (w) {
+                            const int ex = clampe(-(long long)Dn.r - Z.r);
+                            pa += ldexpf(gz * dwa[i] * y, ex);
+                            pb += ldexpf(gz * dwb[i] * y, ex);
+                        }
                     }
+                    const SP E = Ephi[t + i];
+                    accp += ldexpf(gz * A.s * E.s, clampe((long long)A.r + E.r - Z.r));
                 }
-                const SP E = Ephi[t + i];
-                atomicAdd(&gphi[t + i], ldexpf(gz * A.s * E.s, clampe((long long)A.r + E.r - Z.r)));
+                if (i > 0) lane_stage_f(i, tb, lane, L, accp, accq, stp, stq, gphi, gpsi);
             }
         }
+        if (wblk > 0 && t < L) {
+            gphi[t] += accp;
+            gpsi[t] += accq;
+        }
+        __syncthreads();
     }
 }
 
@@ -1059,6 +1095,43 @@ DEV float lane_shr1(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 
+// One step of the lane-shifted adjoint accumulators of the Until adjoints
+// (step i > 0, walked downwards, the same i in every wave of the
+// work-group): lane 63 holds the finished sum of position tb + 64 + s,
+// s = i - 1; it is parked in lane s % 64 of the staging pair, and a full
+// stage (s a multiple of 64: positions tb + 64 + s + lane) is added to the
+// adjoint slots, followed by a barrier.  Then the accumulators move up a lane.
+template <class FP>
+DEV void lane_stage(int i, int tb, int lane, int L, float& accp, float& accq, float& stp, float& stq, FP gphi,
+                    FP gpsi)
+{
+    const int s_ = i - 1, j = s_ & 63;
+    const float dp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(accp), 63));
+    const float dq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(accq), 63));
+    if (lane == j) {
+        stp = dp;
+        stq = dq;
+    }
+    if (j == 0) {
+        const int pos = tb + 64 + s_ + lane;
+        if (pos < L) {
+            gphi[pos] += stp;
+            gpsi[pos] += stq;
+        }
+        stp = 0.f;
+        stq = 0.f;
+        __syncthreads();
+    }
+    accp = lane_shr1(accp);
+    accq = lane_shr1(accq);
+}
+
+DEV void lane_stage_f(int i, int tb, int lane, int L, float& accp, float& accq, float& stp, float& stq,
+                      float* gphi, float* gpsi)
+{
+    lane_stage<float*>(i, tb, lane, L, accp, accq, stp, stq, gphi, gpsi);
+}
+
 // Adjoint on the fp64 terms (the derivatives are ratios of terms, so the
 // reference cancels).  Z_t comes from the forward recompute (zs); a forward
 // sweep of additions keeps P every UCK steps; the reverse sweep rebuilds each
@@ -1069,7 +1142,11 @@ DEV float lane_shr1(float v)
 // accumulator per lane for these positions and moves them up one lane per
 // step.  The position leaving lane 63 is complete for this wave; it is parked
 // in one lane of a staging register, and every 64 steps the stage is added to
-// the adjoint slots with one atomic per lane.  The rest are added at the end.
+// the adjoint slots.  The rest are added at the end.  All waves of the
+// work-group walk the same steps (those of the longest chain of the pass), so
+// the stages are added at the same points in every wave: at one point the
+// waves' stages cover disjoint positions, and a barrier separates the points,
+// which fixes the order of every addition (results are bitwise reproducible).
 // With smooth mask weights (MW) each term carries w_i: Z = sum w_i Y_i, A
 // sums w_i Y_i^2, and d out / d w_i = Y_i / (beta Z) is summed against
 // d w/da, d w/db into pa, pb (per thread, before the division by beta).
@@ -1080,7 +1157,8 @@ DEV void until_adj_d(const Env& e, int a, int b, const float* w, const float* dw
 {
     const int L = e.L;
     const int lane = threadIdx.x & 63;
-    for (int tb = (int)threadIdx.x - lane; tb < L; tb += blockDim.x) {
+    for (int base = 0; base < L; base += blockDim.x) {
+        const int tb = base + (int)threadIdx.x - lane;
         const int t = tb + lane;
         const int imax = t >= L ? -1 : (b < 0 ? L - 1 - t : min(b, L - 1 - t));
         const float gt = t < L ? g[t] : 0.f;
@@ -1107,8 +1185,8 @@ DEV void until_adj_d(const Env& e, int a, int b, const float* w, const float* dw
             }
         }
         const double wz = act ? (double)gt / Z : 0.0;
-        int wblk = nblk;
-        for (int d = 32; d > 0; d >>= 1) wblk = max(wblk, __shfl_xor(wblk, d));
+        const int imax0 = b < 0 ? L - 1 - base : min(b, L - 1 - base);     // t = base: the longest chain
+        const int wblk = a <= imax0 ? imax0 / UCK + 1 : 0;
         float accp = 0.f, accq = 0.f;
         float stp = 0.f, stq = 0.f;         // staged finished sums (see the shift below)
         double A = 0.0;                     // G/Z times the suffix sum of w_i Y_i^2
@@ -1144,35 +1222,14 @@ DEV void until_adj_d(const Env& e, int a, int b, const float* w, const float* dw
                     }
                     accp += (float)(A * v[k]);
                 }
-                if (i > 0) {
-                    // lane 63 holds the finished sum of position tb + 64 + s, s = i - 1:
-                    // park it in lane s % 64 of the staging pair; a full stage
-                    // (s a multiple of 64) goes out with one atomic per lane
-                    const int s_ = i - 1, j = s_ & 63;
-                    const float dp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(accp), 63));
-                    const float dq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(accq), 63));
-                    if (lane == j) {
-                        stp = dp;
-                        stq = dq;
-                    }
-                    if (j == 0) {
-                        const int pos = tb + 64 + s_ + lane;
-                        if (pos < L) {
-                            __hip_atomic_fetch_add(gphi + pos, stp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            __hip_atomic_fetch_add(gpsi + pos, stq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        }
-                        stp = 0.f;
-                        stq = 0.f;
-                    }
-                    accp = lane_shr1(accp);
-                    accq = lane_shr1(accq);
-                }
+                if (i > 0) lane_stage(i, tb, lane, L, accp, accq, stp, stq, gphi, gpsi);
             }
         }
         if (wblk > 0 && t < L) {
-            __hip_atomic_fetch_add(gphi + t, accp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(gpsi + t, accq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            gphi[t] += accp;
+            gpsi[t] += accq;
         }
+        __syncthreads();
         if (MW) {
             pa += (float)(wz * da);
             pb += (float)(wz * db);
@@ -1353,7 +1410,7 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
             w = wt;
         }
         if (!is_smooth(I)) {
-            until_hard(e, ua, ub, phi, psi, out, nullptr, nullptr, nullptr);
+            until_hard(e, ua, ub, phi, psi, out, nullptr, nullptr, nullptr, nullptr);
         } else {
             const float bl = pbeta(e, I) * LOG2E;
             int M;
@@ -1625,7 +1682,7 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
         if (none) {
             // empty support: constant output
         } else if (!is_smooth(I)) {
-            until_hard(e, ua, ub, phi, psi, nullptr, g, gphi, gpsi);
+            until_hard(e, ua, ub, phi, psi, nullptr, g, gphi, gpsi, (int*)S(e, 0));
         } else {
             const float bl = pbeta(e, I) * LOG2E;
             const int bmax = ub < 0 ? L - 1 : min(ub, L - 1);
