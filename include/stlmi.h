@@ -231,9 +231,12 @@ stl_status stl_backward(const stl_plan* plan, const stl_batch* batch, const floa
  *
  * stl_saved_size: bytes of the caller-owned device buffer `d_saved` for this
  * batch: a header of B int32 validity flags (padded to 256 bytes) followed by
- * [n_mask][B][T] float32 traces when a fused fast path applies (n_mask = the
- * number of smooth-mask children of the root), and for the matrix-core path
- * the per-chunk exponent ranges of those traces; only the header otherwise.
+ * [n_mask][B][T] float32 values when a fused fast path applies (n_mask = the
+ * number of smooth-mask children of the root: the fp64 kernels keep the
+ * children's traces, the matrix-core kernels log2 of each child's softmax
+ * weight at the root minus log2 of its window sum), and for the matrix-core
+ * path each trajectory's exponent range and reference ([B][n_mask][3]
+ * int32); only the header otherwise.  The contents are private to the pair.
  * A flag is 1 (fp64 fused forward) or 2 (matrix-core forward) where the
  * trajectory's saved data are valid for the backward of the same path.
  *

@@ -680,7 +680,7 @@ stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch*
             off += (size_t)bt->B * sizeof(int);
             off = (off + 255) / 256 * 256;
             g->off_mxrange = off;
-            off += (size_t)bt->B * dp.fused.n * 2 * sizeof(int);
+            off += (size_t)bt->B * dp.fused.n * 3 * sizeof(int);
             off = (off + 255) / 256 * 256;
         }
         g->off_arena = off;
@@ -742,9 +742,11 @@ extern "C" stl_status stl_workspace_size(const stl_plan* plan, const stl_batch* 
 
 static size_t saved_header(int64_t B) { return ((size_t)B * sizeof(int32_t) + 255) / 256 * 256; }
 
-// saved buffer: B int32 flags (padded to 256 bytes), [n][B][T] float32 mask
-// traces when a fused path applies, and for the matrix-core path the
-// ranges of the traces' exponents ([B][n][2] int32)
+// saved buffer: B int32 flags (padded to 256 bytes), [n][B][T] float32 per
+// mask node and output when a fused path applies (the fp64 kernels: the
+// node's trace; the matrix-core kernels: log2 of the root's softmax weight of
+// the node minus lg2 of its window sum), and for the matrix-core path each
+// trajectory's exponent range and reference ([B][n][3] int32)
 static size_t saved_traces_bytes(const stl_plan* plan, const stl_batch* bt)
 {
     return (size_t)plan->dev.fused.n * bt->B * bt->T * sizeof(float);
@@ -756,7 +758,7 @@ static size_t saved_bytes_needed(const stl_plan* plan, const stl_batch* bt)
     const bool mx = mx_applies(plan->dev, bt, nullptr, false);
     const bool fusable = n > 0 && bt->offsets == nullptr && (bt->T <= fused_max_T() || mx);
     size_t s = saved_header(bt->B) + (fusable ? saved_traces_bytes(plan, bt) : 0);
-    if (mx) s += (size_t)bt->B * n * 2 * sizeof(int32_t);
+    if (mx) s += (size_t)bt->B * n * 3 * sizeof(int32_t);
     return s;
 }
 

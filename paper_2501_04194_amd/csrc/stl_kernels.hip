@@ -2003,12 +2003,12 @@ hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& pla
 size_t mx_tab_bytes() { return sizeof(MxTab); }
 
 // dynamic LDS of the matrix-core kernels: the rings (n masks x 16 rows), the
-// exchange area of masks 1 .. n-1 (forward: traces; backward: d/dx), the
-// backward's derivative tiles and the lo weight tiles
+// exchange area (forward: traces; backward: d/dx), the backward's derivative
+// tiles and the lo weight tiles
 size_t mx_lds_bytes(int n, int D, bool bwd)
 {
-    return (size_t)n * MXG * MXRS + (size_t)(n - 1) * MXG * MXXS * (bwd ? D : 1) * sizeof(float) +
-           (bwd ? (size_t)n * NDMAX * 2 * 64 * 16 : 0) + (size_t)n * NKMAX * 64 * 16;
+    return (size_t)n * MXG * MXRS + mx_xch_bytes(n, D, bwd) + (bwd ? (size_t)n * NDMAX * 2 * 64 * 16 : 0) +
+           (size_t)n * NKMAX * 64 * 16;
 }
 size_t mx_static_lds() { return sizeof(MxShared); }
 
@@ -2021,16 +2021,21 @@ hipError_t set_max_lds_mx(size_t bytes)
                                                   (int)bytes);                                            \
         if (e2 != hipSuccess) e = e2;                                                                     \
     }
-    STLMI_MX_ATTR((stl_mx_fwd<1, 2>)) STLMI_MX_ATTR((stl_mx_fwd<1, 1>))
-    STLMI_MX_ATTR((stl_mx_fwd<2, 2>)) STLMI_MX_ATTR((stl_mx_fwd<2, 1>))
-    STLMI_MX_ATTR((stl_mx_bwd<1, 2>)) STLMI_MX_ATTR((stl_mx_bwd<1, 1>))
-    STLMI_MX_ATTR((stl_mx_bwd<2, 2>)) STLMI_MX_ATTR((stl_mx_bwd<2, 1>))
+#define STLMI_MX_ATTR2(NN, DD)                                                                            \
+    STLMI_MX_ATTR((stl_mx_fwd<NN, DD, false>)) STLMI_MX_ATTR((stl_mx_fwd<NN, DD, true>))                  \
+    STLMI_MX_ATTR((stl_mx_bwd<NN, DD, false>)) STLMI_MX_ATTR((stl_mx_bwd<NN, DD, true>))
+    STLMI_MX_ATTR2(1, 1) STLMI_MX_ATTR2(1, 2) STLMI_MX_ATTR2(2, 1) STLMI_MX_ATTR2(2, 2)
+#undef STLMI_MX_ATTR2
 #undef STLMI_MX_ATTR
     return e;
 }
 
+static bool al16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
+
 // tables (saved_flag: marked valid for a saving forward, else NULL), then
-// the forward or backward kernel over (trajectory groups) x (chunks)
+// the forward or backward kernel over groups of 16 trajectories.  The
+// 16-byte-load variants need T a multiple of 4 and aligned x (and, for the
+// backward, G and the saved values).
 hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs& ka, const MxArgs& mx,
                      int* table_saved_flag, bool tables, size_t lds, hipStream_t s)
 {
@@ -2042,12 +2047,16 @@ hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs
     }
     const dim3 grid((unsigned)((bt.B + MXG - 1) / MXG)), block(256 * plan.fused.n);
     const bool d2 = bt.D == 2;
+    const bool vec = bt.T % 4 == 0 && bt.T >= 4 && al16(bt.x) && (!bwd || (al16(ka.G) && al16(ka.saved_in)));
+#define STLMI_MX_K(NN, DD, VV)                                                                            \
+    if (bwd) hipLaunchKernelGGL((stl_mx_bwd<NN, DD, VV>), grid, block, lds, s, plan, bt, ka, mx);          \
+    else hipLaunchKernelGGL((stl_mx_fwd<NN, DD, VV>), grid, block, lds, s, plan, bt, ka, mx);
 #define STLMI_MX_CASE(NN)                                                                                 \
     case NN:                                                                                              \
-        if (bwd && d2) hipLaunchKernelGGL((stl_mx_bwd<NN, 2>), grid, block, lds, s, plan, bt, ka, mx);     \
-        else if (bwd) hipLaunchKernelGGL((stl_mx_bwd<NN, 1>), grid, block, lds, s, plan, bt, ka, mx);      \
-        else if (d2) hipLaunchKernelGGL((stl_mx_fwd<NN, 2>), grid, block, lds, s, plan, bt, ka, mx);       \
-        else hipLaunchKernelGGL((stl_mx_fwd<NN, 1>), grid, block, lds, s, plan, bt, ka, mx);               \
+        if (d2 && vec) { STLMI_MX_K(NN, 2, true) }                                                        \
+        else if (d2) { STLMI_MX_K(NN, 2, false) }                                                         \
+        else if (vec) { STLMI_MX_K(NN, 1, true) }                                                         \
+        else { STLMI_MX_K(NN, 1, false) }                                                                 \
         break;
     switch (plan.fused.n) {
         STLMI_MX_CASE(1)
@@ -2056,6 +2065,7 @@ hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs
         return hipErrorInvalidValue;
     }
 #undef STLMI_MX_CASE
+#undef STLMI_MX_K
     return hipGetLastError();
 }
 

@@ -17,11 +17,19 @@
 // so its relative error is a few 2^-18 at worst and far smaller on average.
 // The weights are divided by the core weight (core offsets have W = 1).
 //
-// The backward needs, for the adjoint terms H_t = G_m(t) 2^{-O_t - Q}
-// (O_t = sg beta log2(e) out_t, G_m the root's adjoint share of the node),
+// The backward needs, for the adjoint terms H_t = G(t) p_m(t) 2^{-O_t - Q}
+// (O_t = sg beta log2(e) out_t, p_m the root's softmax weight of the node),
 // the transposed window sums D_j = sum_t w_{j - t} H_t (for d/dx) and
 // sum_t dw_{j - t} H_t for the band derivative tables (for d/da, d/db): the
-// same products with transposed weight tiles over H.
+// same products with transposed weight tiles over H.  The forward keeps, per
+// mask and output, l = log2 p_m - (O - R) against its own reference R, so the
+// backward's adjoint term is one exp2 of l plus a per-trajectory constant.
+//
+// Tile origins: the forward tiles start at klo rounded down to a multiple
+// of 4, the backward tiles at khi rounded up (zero weights in between), so
+// that every staged group of 4 positions starts at a multiple of 4; when T is
+// a multiple of 4 such a group lies wholly inside or outside the trajectory
+// and is loaded with 16-byte loads.
 //
 // Work decomposition: a work-group takes 16 trajectories from start to end,
 // four waves per mask node.  The terms (or adjoint terms) of each mask
@@ -49,8 +57,9 @@ constexpr int MXNBLK = 5;               // blocks in the ring
 constexpr int MXRING = MXBLK * MXNBLK;  // ring positions per trajectory
 constexpr int MXRS = MXRING / 8 * 32 + 16;   // LDS row stride (bytes): 16 bytes of pad put the 16
                                              // rows a wave reads at once on distinct bank groups
-constexpr int MXXS = MXROUND + 4;       // exchange row stride (floats per state component): the
-                                        // 16 bytes of pad spread the rows over the banks
+constexpr int MXXS = MXROUND + 4;       // forward exchange row stride (floats): the 16 bytes of
+                                        // pad spread the rows over the banks
+constexpr int MXXH = MXROUND / 2 + 4;   // backward exchange row stride (positions): half a round
 constexpr float MX_HALF = 100.f;       // largest |z - R| (and half the range of O), log2 units
 constexpr int MX_MAXN = 2;              // mask nodes under the root
 
@@ -64,13 +73,14 @@ struct MxTab {
     int ok;                    // 0: the window needs more than NKMAX K-steps
     int any;                   // the support {w > 0} is non-empty
     int klo, khi, clo, chi;    // support and constant core (clo > chi: no core)
+    int kf, kb;                // tile origins: klo rounded down, khi rounded up to a multiple of 4
     int NK;                    // K-steps of an output tile
     float lscale;              // log2 of the weight scale (the core weight, or 1)
     int flo_f[NKMAX];          // tile s of the forward (backward) product has a
     int flo_b[NKMAX];          //   non-zero lo part
     int fd[NKMAX];             // backward K-step s has d/da (bit 0) / d/db (bit 1) weights
-    uint4 Wf[NKMAX][2][64];    // forward tiles [s][hi, lo][lane]: row t, column j: w(klo + 32 s + j - t)
-    uint4 Wb[NKMAX][2][64];    // backward tiles: row j, column t: w(khi - 32 s + j - t)
+    uint4 Wf[NKMAX][2][64];    // forward tiles [s][hi, lo][lane]: row t, column j: w(kf + 32 s + j - t)
+    uint4 Wb[NKMAX][2][64];    // backward tiles: row j, column t: w(kb - 32 s + j - t)
     uint4 Dt[NKMAX][2][2][64]; // derivative tiles [s][d/da, d/db][hi, lo][lane], backward layout
 };
 
@@ -153,7 +163,8 @@ __global__ void __launch_bounds__(256) stl_mx_tables(DevPlan plan, const float* 
     MxTab& T = tabs[m];
     const MaskInfo mi = mask_info(params, I, L, sh, nullptr, nullptr, nullptr);
     const bool core = mi.any && mi.clo <= mi.chi;
-    const int NK = mi.any ? (16 + mi.khi - mi.klo + 31) / 32 : 0;
+    const int kf = mi.klo & ~3, kb = (mi.khi + 3) & ~3;
+    const int NK = mi.any ? (16 + kb - kf + 31) / 32 : 0;
     const double scale = core ? (double)mi.wc : 1.0;
     const MaskP mp = mask_params(params + I.mask, I.flags & F_MASK_UNB);
     if (s == 0 && tid == 0) {
@@ -163,6 +174,8 @@ __global__ void __launch_bounds__(256) stl_mx_tables(DevPlan plan, const float* 
         T.khi = mi.khi;
         T.clo = core ? mi.clo : 1;
         T.chi = core ? mi.chi : 0;
+        T.kf = kf;
+        T.kb = kb;
         T.NK = NK;
         T.lscale = (float)log2(scale);
     }
@@ -180,11 +193,11 @@ __global__ void __launch_bounds__(256) stl_mx_tables(DevPlan plan, const float* 
         const int l = e >> 3, v = e & 7;
         const int row = l & 15, col = 8 * (l >> 4) + v;
         unsigned h, lo;
-        split2(wk(mi.klo + 32 * s + col - row), h, lo);
+        split2(wk(kf + 32 * s + col - row), h, lo);
         ((unsigned short*)&T.Wf[s][0][l])[v] = (unsigned short)h;
         ((unsigned short*)&T.Wf[s][1][l])[v] = (unsigned short)lo;
         lf |= lo != 0;
-        const int k = mi.khi - 32 * s + row - col;
+        const int k = kb - 32 * s + row - col;
         split2(wk(k), h, lo);
         ((unsigned short*)&T.Wb[s][0][l])[v] = (unsigned short)h;
         ((unsigned short*)&T.Wb[s][1][l])[v] = (unsigned short)lo;
@@ -217,6 +230,7 @@ __global__ void __launch_bounds__(256) stl_mx_tables(DevPlan plan, const float* 
 
 struct MxShared {
     float R[MX_MAXN][MXG];       // forward: reference of the terms; backward: Q
+    float C[MX_MAXN][MXG];       // backward: constant of the adjoint terms' exponent
     int frag[MXG];               // trajectory handed to the generic executor
     int omin[MX_MAXN][MXG];      // forward: floor(min O), ceil(max O) over the trajectory
     int omax[MX_MAXN][MXG];
@@ -362,7 +376,95 @@ DEV void mx_load_x8(const float* xb, int j, int L, float* v)
 
 
 
-template <int N, int DD>
+// The same 8 positions j .. j+7 with 16-byte loads, for T a multiple of 4
+// and 16-byte aligned rows (j a multiple of 4): each group of 4 positions
+// lies wholly inside or outside [0, L); it is loaded from a clamped group
+// start and zeroed where outside or where act is false.
+template <int DD>
+DEV void mx_load_x8v(const float* xb, int j, int L, bool act, float* v)
+{
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const int jg = j + 4 * g;
+        const bool in = act && jg >= 0 && jg < L;
+        const float4* p = (const float4*)(xb + (int64_t)min(max(jg, 0), L - 4) * DD);
+#pragma unroll
+        for (int d = 0; d < DD; ++d) {
+            const float4 u = p[d];
+            float* o = v + 4 * g * DD + 4 * d;
+            o[0] = keep_if(u.x, in);
+            o[1] = keep_if(u.y, in);
+            o[2] = keep_if(u.z, in);
+            o[3] = keep_if(u.w, in);
+        }
+    }
+}
+
+template <int DD, bool VEC>
+DEV void mx_load8(const float* xb, int j, int L, bool act, float* v)
+{
+    if (VEC) mx_load_x8v<DD>(xb, j, L, act, v);
+    else mx_load_x8<DD>(xb, j, act ? L : 0, v);
+}
+
+// 4 positions j .. j+3 (j >= 0 a multiple of 4 when VEC) of row xb
+template <int DD, bool VEC>
+DEV void mx_load4(const float* xb, int j, int L, bool act, float* v)
+{
+    if (VEC) {
+        const bool in = act && j < L;
+        const float4* p = (const float4*)(xb + (int64_t)min(j, L - 4) * DD);
+#pragma unroll
+        for (int d = 0; d < DD; ++d) {
+            const float4 u = p[d];
+            v[4 * d] = keep_if(u.x, in);
+            v[4 * d + 1] = keep_if(u.y, in);
+            v[4 * d + 2] = keep_if(u.z, in);
+            v[4 * d + 3] = keep_if(u.w, in);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int jc = min(j + r, L - 1);
+#pragma unroll
+            for (int d = 0; d < DD; ++d) v[r * DD + d] = keep_if(xb[(int64_t)jc * DD + d], act && j + r < L);
+        }
+    }
+}
+
+// the root (as mx_root) and log2 of the softmax weight of child `own`
+template <int N>
+DEV float mx_root_lw(const MxRoot& R, const float* v, int own, float& lw)
+{
+    if (N == 1 && !R.nary) {
+        lw = 0.f;
+        return v[0];
+    }
+    float m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < N; ++k) m = fmaxf(m, R.sg * v[k]);
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) s += ex2((R.sg * v[k] - m) * R.bl);
+    const float ls = lg2(s);
+    float vo = v[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) vo = k == own ? v[k] : vo;
+    lw = (R.sg * vo - m) * R.bl - ls;
+    return R.sg * (m + ls * R.ibl);
+}
+
+// bytes of LDS of the matrix-core kernels beyond the rings
+constexpr size_t mx_xch_bytes(int n, int D, bool bwd)
+{
+    return n < 2 ? 0 : bwd ? (size_t)n * MXG * MXXH * D * sizeof(float) : (size_t)n * MXG * MXXS * sizeof(float);
+}
+
+// Forward: traces of both masks, the root, and for the backward l = log2 p_m
+// - lg2(S) per mask and output (saved), plus each trajectory's range of O
+// and its reference R.  Waves of mask m store the root of tile m of each
+// pair (both tiles when N = 1) and their own mask's l of both tiles.
+template <int N, int DD, bool VEC>
 __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt, KArgs ka, MxArgs mx)
 {
     extern __shared__ __align__(16) unsigned char mxs[];
@@ -415,14 +517,14 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     }
     __syncthreads();
     // ---- staging: thread tid owns the 8-position group g of trajectory row sr
-    // of mask sm in every block
+    // of mask sm in every block; position p holds the term of x at kf + p
     const int sm = tid >> 8, sr = (tid >> 4) & 15, sg8 = tid & 15;
     const int64_t sb = g0 + sr;
     const bool srow = sb < bt.B;
     const MxTab& TS = mx.tabs[sm];
     const MxMask<DD> MS = mx_mask<DD>(Pk, ka.params, sm);
-    const int sklo = TS.klo;
-    const bool sany = TS.any;
+    const int skf = TS.kf;
+    const bool sact = srow && TS.any;
     const float* sxb = bt.x + (srow ? sb : 0) * (int64_t)L * DD;
     unsigned char* srowp = mxs + (sm * MXG + sr) * MXRS;
     const float sR = sh.R[sm][sr];
@@ -433,9 +535,9 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         float e[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int j = p0 + q + sklo;
+            const int j = p0 + q + skf;
             e[q] = 0.f;
-            if (srow && sany && j < L) {
+            if (sact && j < L) {
                 const float d = mx_zx<DD>(MS, xv + q * DD) - sR;
                 sfrag |= !(fabsf(d) <= MX_HALF);
                 e[q] = ex2(fminf(fmaxf(d, -MX_HALF), MX_HALF));
@@ -450,7 +552,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     {
         float xv[4][8 * DD];
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) mx_load_x8<DD>(sxb, MXBLK * blk + 8 * sg8 + sklo, srow && sany ? L : 0, xv[blk]);
+        for (int blk = 0; blk < 4; ++blk) mx_load8<DD, VEC>(sxb, MXBLK * blk + 8 * sg8 + skf, L, sact, xv[blk]);
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk) stage_write(blk, xv[blk]);
     }
@@ -460,9 +562,9 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     const float ibl = 1.f / (M.beta * LOG2E);
     const int klo = T.klo;
     const bool any = T.any;
-    const float lscale = T.lscale;
+    const float Rb = sh.R[m][lane & 15] + T.lscale;     // O = Rb + lg2(window sum)
     // hi tiles in registers, lo tiles (zero on the core steps) in LDS
-    uint4* wlds = (uint4*)(mxs + N * MXG * MXRS + (size_t)(N - 1) * MXG * MXXS * sizeof(float));
+    uint4* wlds = (uint4*)(mxs + N * MXG * MXRS + mx_xch_bytes(N, DD, false));
     for (int e = tid; e < N * NKMAX * 64; e += blockDim.x) {
         const int mm = e / (NKMAX * 64), st = (e / 64) % NKMAX, l = e & 63;
         wlds[e] = mx.tabs[mm].Wf[st][1][l];
@@ -478,18 +580,17 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     const int64_t bo = g0 + bc;
     const bool bvalid = bo < bt.B;
     const unsigned char* ebase = mxs + (m * MXG + bc) * MXRS;
-    float* xch = (float*)(mxs + N * MXG * MXRS);     // [N-1][16][MXXS] traces of masks 1..N-1
+    float* xch = (float*)(mxs + N * MXG * MXRS);     // [N][16][MXXS] traces of the round
     float omin = INFINITY, omax = -INFINITY;
     const int nround = (L + MXROUND - 1) / MXROUND;
     __syncthreads();
-    const float Rb = sh.R[m][bc] + lscale;
     // x of block k+4 is loaded two rounds before it is written (memory latency
     // under load exceeds one round); the loop is unrolled by two so that the
     // two prefetch buffers keep static register names
     float xq0[8 * DD], xq1[8 * DD];
-    mx_load_x8<DD>(sxb, MXBLK * 4 + 8 * sg8 + sklo, srow && sany ? L : 0, xq0);
+    mx_load8<DD, VEC>(sxb, MXBLK * 4 + 8 * sg8 + skf, L, sact, xq0);
     auto round = [&](const int k, const float* xn, float* xnext) {
-        mx_load_x8<DD>(sxb, MXBLK * (k + 5) + 8 * sg8 + sklo, srow && sany ? L : 0, xnext);
+        mx_load8<DD, VEC>(sxb, MXBLK * (k + 5) + 8 * sg8 + skf, L, sact, xnext);
         const int tA = mx_pair_t(k, wq);
         mxf4 accA = {0.f, 0.f, 0.f, 0.f}, accB = accA;
         const int pr = (tA + 8 * rq) % MXRING;
@@ -515,51 +616,66 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
                 accB = mfma(wlp, eh, accB);
             }
         }
-        // traces of this lane's outputs t0 + 4 (l / 16) + rr of both tiles
-        float tr[2][4];
+        // traces of this lane's outputs t0 + 4 (l / 16) + rr of both tiles, and
+        // lg2 of the window sums (O - R)
+        float tr[2][4], la[2][4];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const mxf4 a = h ? accB : accA;
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
                 const int t = tA + 32 * h + 4 * rq + rr;
-                float o = -M.sg * P.rho_pad;
+                float o = -M.sg * P.rho_pad, lo = 0.f;
                 if (any && t + klo <= L - 1) {
-                    const float O = Rb + lg2(a[rr]);
+                    lo = lg2(a[rr]);
+                    const float O = Rb + lo;
                     o = M.sg * O * ibl;
                     omin = fminf(omin, O);
                     omax = fmaxf(omax, O);
                 }
                 tr[h][rr] = o;
+                la[h][rr] = lo;
             }
         }
-        if (N > 1 && m > 0) {
+        // the other mask's traces of both tiles through LDS
+        float to[2][4];
+        const int pos = tA - MXROUND * k + 4 * rq;
+        if (N > 1) {
 #pragma unroll
             for (int h = 0; h < 2; ++h)
-                *(float4*)&xch[((m - 1) * MXG + bc) * MXXS + (tA - MXROUND * k) + 32 * h + 4 * rq] =
+                *(float4*)&xch[(m * MXG + bc) * MXXS + pos + 32 * h] =
                     make_float4(tr[h][0], tr[h][1], tr[h][2], tr[h][3]);
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 u = *(const float4*)&xch[((1 - m) * MXG + bc) * MXXS + pos + 32 * h];
+                to[h][0] = u.x;
+                to[h][1] = u.y;
+                to[h][2] = u.z;
+                to[h][3] = u.w;
+            }
         }
-        if (N > 1) __syncthreads();
         if (bvalid) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int t0 = tA + 32 * h + 4 * rq;
                 const int nv = L - t0;
                 if (nv <= 0) continue;
-                if (m == 0) {
-                    float rt[4];
+                float rt[4], ll[4];
 #pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        float v[N];
-                        v[0] = tr[h][rr];
-#pragma unroll
-                        for (int mm = 1; mm < N; ++mm)
-                            v[mm] = xch[((mm - 1) * MXG + bc) * MXXS + (t0 - MXROUND * k) + rr];
-                        rt[rr] = mx_root<N>(RC, v, nullptr);
+                for (int rr = 0; rr < 4; ++rr) {
+                    float v[N];
+                    v[0] = tr[h][rr];
+                    if (N > 1) {
+                        v[0] = m == 0 ? tr[h][rr] : to[h][rr];
+                        v[N - 1] = m == 0 ? to[h][rr] : tr[h][rr];
                     }
-                    if (ka.root) store4(ka.root, bo * (int64_t)L + t0, nv, rt);
+                    float lw;
+                    rt[rr] = mx_root_lw<N>(RC, v, m, lw);
+                    ll[rr] = lw - la[h][rr];
                 }
-                if (ka.saved) store4(ka.saved, ((int64_t)m * bt.B + bo) * L + t0, nv, tr[h]);
+                if (ka.root && (N == 1 || h == m)) store4(ka.root, bo * (int64_t)L + t0, nv, rt);
+                if (ka.saved) store4(ka.saved, ((int64_t)m * bt.B + bo) * L + t0, nv, ll);
             }
         }
         stage_write(k + 4, xn);
@@ -571,7 +687,8 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         round(k, xq0, xq1);
         if (k + 1 < nround) round(k + 1, xq1, xq0);
     }
-    // ---- exponent ranges of the traces (for the backward), hand-offs
+    // ---- exponent ranges of the traces and the references (for the
+    // backward), hand-offs
     if (any && bvalid && omin <= omax) {
         atomicMin(&sh.omin[m][bc], (int)floorf(omin));
         atomicMax(&sh.omax[m][bc], (int)ceilf(omax));
@@ -581,22 +698,22 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     if (mx.ranges && tid < N * MXG) {
         const int mm = tid / MXG, r = tid % MXG;
         if (g0 + r < bt.B) {
-            int* rp = mx.ranges + ((g0 + r) * N + mm) * 2;
+            int* rp = mx.ranges + ((g0 + r) * N + mm) * 3;
             rp[0] = sh.omin[mm][r];
             rp[1] = sh.omax[mm][r];
+            rp[2] = (int)sh.R[mm][r];
         }
     }
     if (tid < MXG && sh.frag[tid] && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
 }
 
-template <int N, int DD>
+template <int N, int DD, bool VEC>
 __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt, KArgs ka, MxArgs mx)
 {
     extern __shared__ __align__(16) unsigned char mxs[];
     __shared__ MxShared sh;
     const DevPlan& P = plan;
     const DevPlan* Pk = (const DevPlan*)__builtin_amdgcn_kernarg_segment_ptr();
-    const MxRoot RC = mx_root_consts(P, ka.params);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = wv / MXWPM, wq = wv % MXWPM;
     const int L = (int)bt.T;
@@ -630,79 +747,60 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         sh.nd[tid] = nd;
         if (over) sh.over = 1;
     }
-    // ---- per trajectory: saved traces valid, reference Q from the forward's range of O
+    // ---- per trajectory: saved data valid; the reference Q (from the
+    // forward's range of O) and the constant C = -(R + lscale) - Q of the
+    // adjoint terms' exponent l + C
     if (tid < N * MXG) {
         const int mm = tid / MXG, r = tid % MXG;
         const int64_t b = g0 + r;
-        float Q = 0.f;
+        float Q = 0.f, C = 0.f;
         if (b < bt.B) {
             bool frag = ka.saved_flag[b] != 2;
             if (!frag) {
-                const int* rp = mx.ranges + (b * N + mm) * 2;
+                const int* rp = mx.ranges + (b * N + mm) * 3;
                 const int lo = rp[0], hi = rp[1];
                 if (lo <= hi) {
                     if ((float)hi - (float)lo > 2.f * MX_HALF) frag = true;
                     else Q = -floorf(0.5f * ((float)lo + (float)hi));
                 }
+                C = ((float)(-rp[2]) - Q) - mx.tabs[mm].lscale;
             }
             if (frag) atomicOr(&sh.frag[r], 1);
         }
         sh.R[mm][r] = Q;
+        sh.C[mm][r] = C;
     }
     __syncthreads();
     const bool over = sh.over != 0;
     // ---- staging: thread tid owns the 8-position group g of trajectory row sr
-    // of mask sm in every block.  Position p of mask m is time t = p - khi_m;
-    // H_m(t) = G(t) wt_m(t) 2^{-O_m(t) - Q} (0 outside the trajectory and where
-    // the window of t is empty)
+    // of mask sm in every block.  Position p of mask m is time t = p - kb_m;
+    // H_m(t) = G(t) 2^{l_m(t) + C} (0 outside the trajectory and where the
+    // window of t is empty)
     const int sm = tid >> 8, sr = (tid >> 4) & 15, sg8 = tid & 15;
     const int64_t sb = g0 + sr;
     const bool srow = sb < bt.B && !sh.frag[sr] && !over;
     const MxTab& TS = mx.tabs[sm];
-    const MxMask<DD> MS = mx_mask<DD>(Pk, ka.params, sm);
-    const int skhi = TS.khi, sklo = TS.klo;
-    const bool sany = TS.any;
+    const int skb = TS.kb, sklo = TS.klo;
+    const bool sact = srow && TS.any;
     const float* sG = ka.G + (srow ? sb : 0) * (int64_t)L;
-    const float* str[N];
-#pragma unroll
-    for (int n = 0; n < N; ++n) str[n] = ka.saved_in + ((int64_t)n * bt.B + (srow ? sb : 0)) * L;
+    const float* sl = ka.saved_in + ((int64_t)sm * bt.B + (srow ? sb : 0)) * L;
     unsigned char* srowp = mxs + (sm * MXG + sr) * MXRS;
-    const float sQ = sh.R[sm][sr];
-    const bool sact = srow && sany;
-    // G and the saved traces at t .. t+7 (zero outside [0, L))
-    auto stage_load = [&](int blk, float* gv, float (*tv)[8]) {
-        const int t0 = MXBLK * blk + 8 * sg8 - skhi;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int t = t0 + q;
-            const bool in = sact && t >= 0 && t < L;
-            const int tc = min(max(t, 0), L - 1);     // unconditional loads (see mx_load_x8)
-            gv[q] = keep_if(sG[tc], in);
-#pragma unroll
-            for (int n = 0; n < N; ++n) tv[n][q] = keep_if(str[n][tc], in);
-        }
+    const float sC = sh.C[sm][sr];
+    // G and l at t .. t+7 (zero outside [0, L))
+    auto stage_load = [&](int blk, float* gv, float* lv) {
+        const int t0 = MXBLK * blk + 8 * sg8 - skb;
+        mx_load8<1, VEC>(sG, t0, L, sact, gv);
+        mx_load8<1, VEC>(sl, t0, L, sact, lv);
     };
-    auto stage_write = [&](int blk, const float* gv, float (*tv)[8]) {
-        const int p0 = MXBLK * blk + 8 * sg8, t0 = p0 - skhi;
+    auto stage_write = [&](int blk, const float* gv, const float* lv) {
+        const int p0 = MXBLK * blk + 8 * sg8, t0 = p0 - skb;
         float h[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int t = t0 + q;
-            h[q] = 0.f;
-            if (sact && t >= 0 && t + sklo <= L - 1) {
-                float v[N], wts[N];
-#pragma unroll
-                for (int n = 0; n < N; ++n) v[n] = tv[n][q];
-                mx_root<N>(RC, v, wts);
-                float wm = wts[0], tm = v[0];
-#pragma unroll
-                for (int n = 1; n < N; ++n) {
-                    wm = n == sm ? wts[n] : wm;
-                    tm = n == sm ? v[n] : tm;
-                }
-                // -O - Q lies within [-MX_HALF, MX_HALF] (the forward's range check)
-                h[q] = gv[q] * wm * ex2(fminf(fmaxf(-MS.sbl * tm - sQ, -2.f * MX_HALF), 2.f * MX_HALF));
-            }
+            // l + C <= -O - Q lies within [-MX_HALF, MX_HALF] (the forward's range check)
+            const float hv = gv[q] * ex2(fminf(fmaxf(lv[q] + sC, -2.f * MX_HALF), 2.f * MX_HALF));
+            h[q] = sact && t >= 0 && t + sklo <= L - 1 ? hv : 0.f;
         }
         bf16x8 hh, hl;
         split8(h, hh, hl);
@@ -711,19 +809,19 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         *(bf16x8*)(q + 16) = hl;
     };
     {
-        float gv[4][8], tv[4][N][8];
+        float gv[4][8], lv[4][8];
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) stage_load(blk, gv[blk], tv[blk]);
+        for (int blk = 0; blk < 4; ++blk) stage_load(blk, gv[blk], lv[blk]);
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) stage_write(blk, gv[blk], tv[blk]);
+        for (int blk = 0; blk < 4; ++blk) stage_write(blk, gv[blk], lv[blk]);
     }
     // ---- this wave's mask: weight and derivative tiles, constants
     const MxTab& T = mx.tabs[m];
     const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, m);
     const bool any = T.any;
     // hi tiles in registers, lo tiles in LDS (after the derivative tiles)
-    uint4* wlds = (uint4*)(mxs + N * MXG * MXRS + (size_t)(N - 1) * MXG * MXXS * DD * sizeof(float)) +
-                  N * NDMAX * 128;
+    uint4* dlds = (uint4*)(mxs + N * MXG * MXRS + mx_xch_bytes(N, DD, true));
+    uint4* wlds = dlds + N * NDMAX * 128;
     for (int e = tid; e < N * NKMAX * 64; e += blockDim.x) {
         const int mm = e / (NKMAX * 64), st = (e / 64) % NKMAX, l = e & 63;
         wlds[e] = mx.tabs[mm].Wb[st][1][l];
@@ -736,7 +834,6 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
     // derivative tiles of every mask in LDS ([n][NDMAX][hi, lo][lane], zero
     // tiles in unused slots)
-    uint4* dlds = (uint4*)(mxs + N * MXG * MXRS + (size_t)(N - 1) * MXG * MXXS * DD * sizeof(float));
     for (int e = tid; e < N * NDMAX * 2 * 64; e += blockDim.x) {
         const int mm = e / (NDMAX * 128), d = (e / 128) % NDMAX, hl = (e / 64) & 1, l = e & 63;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
@@ -758,28 +855,21 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     const bool bvalid = bo < bt.B && !sh.frag[bc] && !over;
     const float* xo = bt.x + (bo < bt.B ? bo : 0) * (int64_t)L * DD;
     const unsigned char* hbase = mxs + (m * MXG + bc) * MXRS;
-    float* xch = (float*)(mxs + N * MXG * MXRS);     // [N-1][16][MXXS][DD] d/dx of masks 1..N-1
+    // [N][16][MXXH][DD]: d/dx of the tile of each pair the other mask's waves store
+    float* xch = (float*)(mxs + N * MXG * MXRS);
     const float Qb = sh.R[m][bc];
     float pam = 0.f, pbm = 0.f;
     const int nround = (L + MXROUND - 1) / MXROUND;
     __syncthreads();
     for (int k = 0; k < nround; ++k) {
         // loads of block k+4 go out first
-        float gn[8], tn[N][8];
-        stage_load(k + 4, gn, tn);
-        const int tA0 = mx_pair_t(k, wq);
+        float gn[8], ln[8];
+        stage_load(k + 4, gn, ln);
+        const int tA = mx_pair_t(k, wq);
         // and x at this lane's outputs
         float xv[2][4 * DD];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int j = tA0 + 32 * h + 4 * rq + rr;
-                const int jc = min(j, L - 1);
-#pragma unroll
-                for (int d = 0; d < DD; ++d) xv[h][rr * DD + d] = keep_if(xo[(int64_t)jc * DD + d], bvalid && j < L);
-            }
-        const int tA = mx_pair_t(k, wq);
+        for (int h = 0; h < 2; ++h) mx_load4<DD, VEC>(xo, tA + 32 * h + 4 * rq, L, bvalid, xv[h]);
         mxf4 accA = {0.f, 0.f, 0.f, 0.f}, accB = accA;
         const int pr = (tA + 8 * rq) % MXRING;
         bf16x8 wlp;
@@ -849,25 +939,39 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                 pbm += isb[d] ? sum : 0.f;
             }
         }
-        if (N > 1 && m > 0) {
+        // the waves of mask m store d/dx of tile m of each pair (both when
+        // N = 1): the other tile's contribution goes to the other mask's waves
+        const int cpos = 16 * (wq & 1) + 4 * rq + 32 * (wq >> 1);     // half-round position of both tiles
+        if (N > 1) {
 #pragma unroll
             for (int h = 0; h < 2; ++h)
+                if (h != m) {
+                    float* xp = xch + ((m * MXG + bc) * MXXH + cpos) * DD;
 #pragma unroll
-                for (int q = 0; q < 4 * DD; ++q)
-                    xch[(((m - 1) * MXG + bc) * MXXS + (tA - MXROUND * k) + 32 * h + 4 * rq) * DD + q] = gx[h][q];
+                    for (int q = 0; q < DD; ++q)
+                        *(float4*)(xp + 4 * q) = make_float4(gx[h][4 * q], gx[h][4 * q + 1], gx[h][4 * q + 2],
+                                                             gx[h][4 * q + 3]);
+                }
+            __syncthreads();
         }
-        if (N > 1) __syncthreads();
-        if (m == 0 && bvalid) {
+        if (bvalid) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
+                if (N > 1 && h != m) continue;
                 const int j0 = tA + 32 * h + 4 * rq;
                 const int nv = min(4, L - j0);
                 if (nv <= 0) continue;
+                if (N > 1) {
+                    const float* xp = xch + (((1 - m) * MXG + bc) * MXXH + cpos) * DD;
 #pragma unroll
-                for (int mm = 1; mm < N; ++mm)
-#pragma unroll
-                    for (int q = 0; q < 4 * DD; ++q)
-                        gx[h][q] += xch[(((mm - 1) * MXG + bc) * MXXS + (j0 - MXROUND * k)) * DD + q];
+                    for (int q = 0; q < DD; ++q) {
+                        const float4 u = *(const float4*)(xp + 4 * q);
+                        gx[h][4 * q] += u.x;
+                        gx[h][4 * q + 1] += u.y;
+                        gx[h][4 * q + 2] += u.z;
+                        gx[h][4 * q + 3] += u.w;
+                    }
+                }
                 float* dp = ka.dx + (bo * (int64_t)L + j0) * DD;
                 if (nv == 4 && (((uintptr_t)dp) & 15) == 0) {
 #pragma unroll
@@ -878,7 +982,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                 }
             }
         }
-        stage_write(k + 4, gn, tn);
+        stage_write(k + 4, gn, ln);
 #pragma unroll
         for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
         __syncthreads();

@@ -133,7 +133,7 @@ struct MxTab;
 struct MxArgs {
     const MxTab* tabs;
     int* handed;           // [B] 1 once a trajectory is on the hand-off list
-    int* ranges;           // [B][n][2] floor(min), ceil(max) of O over each trajectory's trace
+    int* ranges;           // [B][n][3] floor(min), ceil(max) of O over each trajectory's trace, reference R
     float* part;           // [B][n_masks][2] d/da, d/db partials
 };
 

@@ -159,7 +159,7 @@ def test_saved_size_and_errors():
     sv = g.plan.saved_buffer(xd)
     # flags, two [B][T] traces, and (matrix-core path) the exponent range of
     # each trajectory's two traces
-    assert sv.numel() == 256 + 2 * 3 * 500 * 4 + 3 * 2 * 2 * 4
+    assert sv.numel() == 256 + 2 * 3 * 500 * 4 + 3 * 2 * 3 * 4
     small = sv[:1000]
     with pytest.raises(stl.StlError, match="saved buffer too small"):
         g.plan.forward(xd, g.pv, saved=small)

@@ -48,11 +48,13 @@ def test_mx_agrees_with_fp64_and_generic():
     agree(spec, x, params, G, GENERIC, "mx/generic")
 
 
+@pytest.mark.parametrize("T", [800, 799])
 @pytest.mark.parametrize("case", range(6))
-def test_mx_shapes(case):
+def test_mx_shapes(case, T):
+    """T = 800 takes the 16-byte-load kernels, T = 799 the others."""
     rng = np.random.default_rng(70 + case)
     D = 1 if case == 3 else 2
-    x = np.cumsum(rng.normal(size=(21, 800, D)) * 0.05, axis=1).astype(np.float32)
+    x = np.cumsum(rng.normal(size=(21, T, D)) * 0.05, axis=1).astype(np.float32)
     p0 = lin([1.0] * D)
     p1 = lin([-1.0] + [0.5] * (D - 1), -0.3)
     specs = [
@@ -68,7 +70,7 @@ def test_mx_shapes(case):
             mask("eventually", p0, 10.0, 44.5), mask("always", p1, 10.0, 45.0)]},      # cores of 1 and 2 steps
     ]
     params = {"a": 100.0, "b": 400.0}
-    check_formula(specs[case], x, params=params, what="mx shape %d" % case)
+    check_formula(specs[case], x, params=params, what="mx shape %d T=%d" % (case, T))
 
 
 def test_mx_hands_off_wide_range_and_wide_masks():
@@ -155,3 +157,28 @@ def test_mx_full_size_sampled_against_oracle():
     got = g.plan.param_grads(gp.cpu().numpy())
     for k, v in dpr.items():
         assert abs(got[k] - v) <= REL * abs(dpa[k]) + 1e-12, (k, got[k], v, dpa[k])
+
+
+def test_mx_unaligned_inputs_match_aligned():
+    """x, G and the saved buffer at addresses that are not 16-byte aligned
+    take the kernels with scalar loads: the same bits as the aligned call."""
+    import torch
+    spec, params, x = W.workload(2, B=24, T=1024)
+    G = W.upstream_grad(12, x.shape[:2])
+    g = Gpu(spec, 2, params)
+    xa, Ga = torch.from_numpy(x).cuda(), torch.from_numpy(G).cuda()
+    xu = torch.empty(x.size + 1, dtype=torch.float32, device="cuda")[1:].view(x.shape)
+    Gu = torch.empty(G.size + 1, dtype=torch.float32, device="cuda")[1:].view(G.shape)
+    xu.copy_(xa)
+    Gu.copy_(Ga)
+    assert xu.data_ptr() % 16 != 0 and Gu.data_ptr() % 16 != 0
+    outs = []
+    for xd, Gd in ((xa, Ga), (xu, Gu)):
+        sv = g.plan.saved_buffer(xd)
+        r = g.plan.forward(xd, g.pv, saved=sv)
+        d, p = g.plan.backward(xd, Gd, g.pv, saved=sv)
+        d2, p2 = g.plan.backward(xd, Gd, g.pv)
+        outs.append((r, d, p, d2, p2))
+    torch.cuda.synchronize()
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
