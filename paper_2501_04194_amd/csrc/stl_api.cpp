@@ -642,7 +642,9 @@ stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch*
     g->mx_lds = 0;
     g->off_handed = g->off_mxtr = g->off_mxflag = g->off_mxrange = 0;
     if (mx_applies(dp, bt, cfg, trace)) {
-        const size_t lds = mx_lds_bytes(dp.fused.n, bt->D, bwd);
+        // (a backward without saved traces runs the forward kernel first, with the same LDS size)
+        const size_t lds = bwd ? std::max(mx_lds_bytes(dp.fused.n, bt->D, false), mx_lds_bytes(dp.fused.n, bt->D, true))
+                               : mx_lds_bytes(dp.fused.n, bt->D, false);
         if (lds <= di.lds_mx) {
             g->mx = true;
             g->mx_lds = lds;

@@ -2034,8 +2034,8 @@ static bool al16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
 
 // tables (saved_flag: marked valid for a saving forward, else NULL), then
 // the forward or backward kernel over groups of 16 trajectories.  The
-// 16-byte-load variants need T a multiple of 4 and aligned x (and, for the
-// backward, G and the saved values).
+// 16-byte load / store variants need T a multiple of 4 and 16-byte aligned
+// arrays (x; forward: root and saved values; backward: G, saved values, dx).
 hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs& ka, const MxArgs& mx,
                      int* table_saved_flag, bool tables, size_t lds, hipStream_t s)
 {
@@ -2047,7 +2047,8 @@ hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs
     }
     const dim3 grid((unsigned)((bt.B + MXG - 1) / MXG)), block(256 * plan.fused.n);
     const bool d2 = bt.D == 2;
-    const bool vec = bt.T % 4 == 0 && bt.T >= 4 && al16(bt.x) && (!bwd || (al16(ka.G) && al16(ka.saved_in)));
+    const bool vec = bt.T % 4 == 0 && bt.T >= 4 && al16(bt.x) &&
+                     (bwd ? al16(ka.G) && al16(ka.saved_in) && al16(ka.dx) : al16(ka.root) && al16(ka.saved));
 #define STLMI_MX_K(NN, DD, VV)                                                                            \
     if (bwd) hipLaunchKernelGGL((stl_mx_bwd<NN, DD, VV>), grid, block, lds, s, plan, bt, ka, mx);          \
     else hipLaunchKernelGGL((stl_mx_fwd<NN, DD, VV>), grid, block, lds, s, plan, bt, ka, mx);

@@ -348,86 +348,85 @@ DEV void store4(float* p, int64_t i0, int n_valid, const float* v)
     }
 }
 
+// a where c, else b, as bit operations on a mask the compiler cannot see
+// through (a select of an expensive value may otherwise become a branch
+// around its computation)
+DEV float mx_sel(bool c, float a, float b)
+{
+    int m = -(int)c;
+    asm volatile("" : "+v"(m));
+    return __int_as_float((__float_as_int(a) & m) | (__float_as_int(b) & ~m));
+}
+
+// four consecutive outputs at p (n_valid >= 1 of them in the trajectory).
+// VEC: T is a multiple of 4 and the rows are 16-byte aligned, so all four
+// are valid and one 16-byte store writes them.
+template <bool VEC>
+DEV void mx_store4(float* p, int n_valid, const float* v)
+{
+    if (VEC) *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
+    else store4(p, 0, n_valid, v);
+}
+
 // keep a value in registers across a loop (the compiler may otherwise reload
 // loop-invariant tiles from memory inside it, each load followed by a wait)
 DEV void mx_pin(bf16x8& v) { asm volatile("" : "+v"(v)); }
 
-// x where keep, else 0, without a select: a select of a loaded value lets
-// the compiler turn the load into a conditional one under a branch, followed
-// by a wait for it
-DEV float keep_if(float x, bool keep) { return __int_as_float(__float_as_int(x) & -(int)keep); }
 
-// 8 DD floats of x (positions j .. j+7 of row xb) into v; positions at or
-// past L (all of them when L = 0) read as zero.  The loads themselves are
-// unconditional (clamped addresses, then a select): a load under a branch
-// would be followed by a wait for it.
-template <int DD>
-DEV void mx_load_x8(const float* xb, int j, int L, float* v)
-{
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int jc = min(max(j + q, 0), max(L - 1, 0));
-#pragma unroll
-        for (int d = 0; d < DD; ++d) {
-            v[q * DD + d] = keep_if(xb[(int64_t)jc * DD + d], j + q < L);
-        }
-    }
-}
-
-
-
-// The same 8 positions j .. j+7 with 16-byte loads, for T a multiple of 4
-// and 16-byte aligned rows (j a multiple of 4): each group of 4 positions
-// lies wholly inside or outside [0, L); it is loaded from a clamped group
-// start and zeroed where outside or where act is false.
-template <int DD>
-DEV void mx_load_x8v(const float* xb, int j, int L, bool act, float* v)
-{
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        const int jg = j + 4 * g;
-        const bool in = act && jg >= 0 && jg < L;
-        const float4* p = (const float4*)(xb + (int64_t)min(max(jg, 0), L - 4) * DD);
-#pragma unroll
-        for (int d = 0; d < DD; ++d) {
-            const float4 u = p[d];
-            float* o = v + 4 * g * DD + 4 * d;
-            o[0] = keep_if(u.x, in);
-            o[1] = keep_if(u.y, in);
-            o[2] = keep_if(u.z, in);
-            o[3] = keep_if(u.w, in);
-        }
-    }
-}
-
+// 8 positions j .. j+7 (DD floats each) of row xb, from clamped addresses
+// and with no mask: values at positions outside [0, L) are those of a valid
+// position, and every user masks them itself (a mask applied here makes the
+// compiler wait for the load where the masked value is formed).  VEC: T a
+// multiple of 4, 16-byte aligned rows and j a multiple of 4, so that each
+// group of 4 positions lies wholly inside or outside [0, L) and is read with
+// 16-byte loads from its clamped start.
 template <int DD, bool VEC>
-DEV void mx_load8(const float* xb, int j, int L, bool act, float* v)
-{
-    if (VEC) mx_load_x8v<DD>(xb, j, L, act, v);
-    else mx_load_x8<DD>(xb, j, act ? L : 0, v);
-}
-
-// 4 positions j .. j+3 (j >= 0 a multiple of 4 when VEC) of row xb
-template <int DD, bool VEC>
-DEV void mx_load4(const float* xb, int j, int L, bool act, float* v)
+DEV void mx_load8(const float* xb, int j, int L, float* v)
 {
     if (VEC) {
-        const bool in = act && j < L;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const float4* p = (const float4*)(xb + (int64_t)min(max(j + 4 * g, 0), L - 4) * DD);
+#pragma unroll
+            for (int d = 0; d < DD; ++d) {
+                const float4 u = p[d];
+                float* o = v + 4 * g * DD + 4 * d;
+                o[0] = u.x;
+                o[1] = u.y;
+                o[2] = u.z;
+                o[3] = u.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int jc = min(max(j + q, 0), L - 1);
+#pragma unroll
+            for (int d = 0; d < DD; ++d) v[q * DD + d] = xb[(int64_t)jc * DD + d];
+        }
+    }
+}
+
+// 4 positions j .. j+3 (j >= 0; a multiple of 4 when VEC), unmasked as mx_load8
+template <int DD, bool VEC>
+DEV void mx_load4(const float* xb, int j, int L, float* v)
+{
+    if (VEC) {
         const float4* p = (const float4*)(xb + (int64_t)min(j, L - 4) * DD);
 #pragma unroll
         for (int d = 0; d < DD; ++d) {
             const float4 u = p[d];
-            v[4 * d] = keep_if(u.x, in);
-            v[4 * d + 1] = keep_if(u.y, in);
-            v[4 * d + 2] = keep_if(u.z, in);
-            v[4 * d + 3] = keep_if(u.w, in);
+            v[4 * d] = u.x;
+            v[4 * d + 1] = u.y;
+            v[4 * d + 2] = u.z;
+            v[4 * d + 3] = u.w;
         }
     } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int jc = min(j + r, L - 1);
 #pragma unroll
-            for (int d = 0; d < DD; ++d) v[r * DD + d] = keep_if(xb[(int64_t)jc * DD + d], act && j + r < L);
+            for (int d = 0; d < DD; ++d) v[r * DD + d] = xb[(int64_t)jc * DD + d];
         }
     }
 }
@@ -454,16 +453,45 @@ DEV float mx_root_lw(const MxRoot& R, const float* v, int own, float& lw)
     return R.sg * (m + ls * R.ibl);
 }
 
-// bytes of LDS of the matrix-core kernels beyond the rings
+// bytes of LDS of the matrix-core kernels beyond the rings (forward: two
+// buffers of window sums; backward: the d/dx exchange)
 constexpr size_t mx_xch_bytes(int n, int D, bool bwd)
 {
-    return n < 2 ? 0 : bwd ? (size_t)n * MXG * MXXH * D * sizeof(float) : (size_t)n * MXG * MXXS * sizeof(float);
+    return bwd ? (n < 2 ? 0 : (size_t)n * MXG * MXXH * D * sizeof(float)) : (size_t)2 * n * 8 * 64 * 16;
 }
 
-// Forward: traces of both masks, the root, and for the backward l = log2 p_m
+// the root (as mx_root) and log2 of the softmax weight of every child
+template <int N>
+DEV float mx_root_lws(const MxRoot& R, const float* v, float* lw)
+{
+    if (N == 1 && !R.nary) {
+        lw[0] = 0.f;
+        return v[0];
+    }
+    float m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < N; ++k) m = fmaxf(m, R.sg * v[k]);
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) s += ex2((R.sg * v[k] - m) * R.bl);
+    const float ls = lg2(s);
+#pragma unroll
+    for (int k = 0; k < N; ++k) lw[k] = (R.sg * v[k] - m) * R.bl - ls;
+    return R.sg * (m + ls * R.ibl);
+}
+
+// Forward: traces of the masks, the root, and for the backward l = log2 p_m
 // - lg2(S) per mask and output (saved), plus each trajectory's range of O
-// and its reference R.  Waves of mask m store the root of tile m of each
-// pair (both tiles when N = 1) and their own mask's l of both tiles.
+// and its reference R.
+//
+// The work-group's 4N waves take two roles, one wave of each per SIMD, one
+// round apart.  Matrix waves (2 per mask: w < 2N) compute the window sums of
+// round k for their mask: four tiles at outputs 128 k + 16 h + 32 j
+// (h = w % 2, j < 4), which read the same staged terms at K-steps s - j, so
+// each read of the ring feeds up to 12 products; the hi and lo weight tiles
+// stay in registers.  The sums go to an LDS buffer (two, alternating by
+// round).  Staging waves turn round k - 1's sums into traces, the root and
+// l, store them, and stage block k + 4 of every mask.  One barrier per round.
 template <int N, int DD, bool VEC>
 __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt, KArgs ka, MxArgs mx)
 {
@@ -476,7 +504,6 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     const DevPlan* Pk = (const DevPlan*)__builtin_amdgcn_kernarg_segment_ptr();
     const MxRoot RC = mx_root_consts(P, ka.params);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int m = wv / MXWPM, wq = wv % MXWPM;
     const int L = (int)bt.T;
     const int64_t g0 = (int64_t)blockIdx.x * MXG;
     bool ok = true;
@@ -516,184 +543,235 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         }
     }
     __syncthreads();
-    // ---- staging: thread tid owns the 8-position group g of trajectory row sr
-    // of mask sm in every block; position p holds the term of x at kf + p
-    const int sm = tid >> 8, sr = (tid >> 4) & 15, sg8 = tid & 15;
-    const int64_t sb = g0 + sr;
-    const bool srow = sb < bt.B;
-    const MxTab& TS = mx.tabs[sm];
-    const MxMask<DD> MS = mx_mask<DD>(Pk, ka.params, sm);
-    const int skf = TS.kf;
-    const bool sact = srow && TS.any;
-    const float* sxb = bt.x + (srow ? sb : 0) * (int64_t)L * DD;
-    unsigned char* srowp = mxs + (sm * MXG + sr) * MXRS;
-    const float sR = sh.R[sm][sr];
-    bool sfrag = false;
-    // terms of block blk from the DD x 8 values xv (positions 128 blk + 8 g ..)
-    auto stage_write = [&](int blk, const float* xv) {
-        const int p0 = MXBLK * blk + 8 * sg8;
+    // ---- staging units: unit u = (mask u / 256, row (u / 16) % 16, 8-position
+    // group u % 16) of a block; position p of mask m holds the term of x at
+    // kf_m + p.  The prologue stages blocks 0..3 with every thread (one unit
+    // each per block); in the rounds each staging thread owns two units.
+    struct Unit {
+        MxMask<DD> M;
+        const float* xb;
+        unsigned char* row;
+        float R;
+        int off;        // kf + 8 g: x index of the unit's first position in block 0
+        int g8;         // 8 g
+        bool act;
+    };
+    auto unit = [&](int u) {
+        Unit U;
+        const int um = u >> 8, ur = (u >> 4) & 15, ug = u & 15;
+        const MxTab& TU = mx.tabs[um];
+        const int64_t b = g0 + ur;
+        U.M = mx_mask<DD>(Pk, ka.params, um);
+        U.xb = bt.x + (b < bt.B ? b : 0) * (int64_t)L * DD;
+        U.row = mxs + (um * MXG + ur) * MXRS;
+        U.R = sh.R[um][ur];
+        U.off = TU.kf + 8 * ug;
+        U.g8 = 8 * ug;
+        U.act = b < bt.B && TU.any;
+        return U;
+    };
+    auto stage_load = [&](const Unit& U, int blk, float* xv) {
+        mx_load8<DD, VEC>(U.xb, MXBLK * blk + U.off, L, xv);
+    };
+    auto stage_write = [&](const Unit& U, int blk, const float* xv, bool& frag) {
+        const int p0 = MXBLK * blk + U.g8, j0 = MXBLK * blk + U.off;
         float e[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int j = p0 + q + skf;
-            e[q] = 0.f;
-            if (sact && j < L) {
-                const float d = mx_zx<DD>(MS, xv + q * DD) - sR;
-                sfrag |= !(fabsf(d) <= MX_HALF);
-                e[q] = ex2(fminf(fmaxf(d, -MX_HALF), MX_HALF));
-            }
+            // (selects, not branches: x reads as 0 outside the trajectory)
+            const bool in = U.act && j0 + q < L;
+            const float d = mx_zx<DD>(U.M, xv + q * DD) - U.R;
+            frag |= in & !(fabsf(d) <= MX_HALF);
+            e[q] = mx_sel(in, ex2(fminf(fmaxf(d, -MX_HALF), MX_HALF)), 0.f);
         }
         bf16x8 h, l;
         split8(e, h, l);
-        unsigned char* q = srowp + ring_off(p0);
+        unsigned char* q = U.row + ring_off(p0);
         *(bf16x8*)q = h;
         *(bf16x8*)(q + 16) = l;
     };
+    bool sfrag[2] = {false, false};     // per unit of a staging thread
     {
+        const Unit U = unit(tid);
         float xv[4][8 * DD];
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) mx_load8<DD, VEC>(sxb, MXBLK * blk + 8 * sg8 + skf, L, sact, xv[blk]);
+        for (int blk = 0; blk < 4; ++blk) stage_load(U, blk, xv[blk]);
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) stage_write(blk, xv[blk]);
+        for (int blk = 0; blk < 4; ++blk) stage_write(U, blk, xv[blk], sfrag[0]);
+        if (sfrag[0]) atomicOr(&sh.frag[(tid >> 4) & 15], 1);
+        sfrag[0] = false;
     }
-    // ---- this wave's mask: weight tiles, constants
-    const MxTab& T = mx.tabs[m];
-    const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, m);
-    const float ibl = 1.f / (M.beta * LOG2E);
-    const int klo = T.klo;
-    const bool any = T.any;
-    const float Rb = sh.R[m][lane & 15] + T.lscale;     // O = Rb + lg2(window sum)
-    // hi tiles in registers, lo tiles (zero on the core steps) in LDS
-    uint4* wlds = (uint4*)(mxs + N * MXG * MXRS + mx_xch_bytes(N, DD, false));
+    // lo tiles of every mask in LDS (read by the matrix waves into registers)
+    float* accb = (float*)(mxs + N * MXG * MXRS);                   // [2][N][2][4][64][4] window sums
+    uint4* wlds = (uint4*)(mxs + N * MXG * MXRS + (size_t)2 * N * 8 * 64 * 16);
     for (int e = tid; e < N * NKMAX * 64; e += blockDim.x) {
         const int mm = e / (NKMAX * 64), st = (e / 64) % NKMAX, l = e & 63;
         wlds[e] = mx.tabs[mm].Wf[st][1][l];
     }
-    const uint4* wl_m = wlds + m * NKMAX * 64 + lane;
-    bf16x8 Wh[NKMAX];
-#pragma unroll
-    for (int s = 0; s < NKMAX; ++s) Wh[s] = tile_ld(&T.Wf[s][0][lane]);
-    // (pinned here: the wait for these loads happens once, before the loop)
-#pragma unroll
-    for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
-    const int bc = lane & 15, rq = lane >> 4;
-    const int64_t bo = g0 + bc;
-    const bool bvalid = bo < bt.B;
-    const unsigned char* ebase = mxs + (m * MXG + bc) * MXRS;
-    float* xch = (float*)(mxs + N * MXG * MXRS);     // [N][16][MXXS] traces of the round
-    float omin = INFINITY, omax = -INFINITY;
     const int nround = (L + MXROUND - 1) / MXROUND;
+    // bodies of the loop below (both roles run the same number, one barrier
+    // each): round k's sums in body k, its outputs in body k + 1; an even
+    // count lets the staging waves unroll by two with no conditional body
+    const int nbody = (nround + 2) & ~1;
+    const bool matrix = wv < 2 * N;
     __syncthreads();
-    // x of block k+4 is loaded two rounds before it is written (memory latency
-    // under load exceeds one round); the loop is unrolled by two so that the
-    // two prefetch buffers keep static register names
-    float xq0[8 * DD], xq1[8 * DD];
-    mx_load8<DD, VEC>(sxb, MXBLK * 4 + 8 * sg8 + skf, L, sact, xq0);
-    auto round = [&](const int k, const float* xn, float* xnext) {
-        mx_load8<DD, VEC>(sxb, MXBLK * (k + 5) + 8 * sg8 + skf, L, sact, xnext);
-        const int tA = mx_pair_t(k, wq);
-        mxf4 accA = {0.f, 0.f, 0.f, 0.f}, accB = accA;
-        const int pr = (tA + 8 * rq) % MXRING;
-        bf16x8 wlp;
+    if (matrix) {
+        // ---------------------------------------------------------- matrix waves
+        const int m = wv >> 1, hh = wv & 1;
+        const MxTab& T = mx.tabs[m];
+        bf16x8 Wh[NKMAX], Wl[NKMAX];
 #pragma unroll
-        for (int s = 0; s <= NKMAX; ++s) {
-            const unsigned char* ep = ebase + ring_off2(pr, 32 * s);
-            const bf16x8 eh = ld_bf16x8(ep), el = ld_bf16x8(ep + 16);
-            if (s < NKMAX) {
-                const bf16x8 wl = ld_bf16x8(wl_m + s * 64);
-                accA = mfma(Wh[s], eh, accA);
-                accA = mfma(Wh[s], el, accA);
-                accA = mfma(wl, eh, accA);
-                if (s >= 1) {
-                    accB = mfma(Wh[s - 1], eh, accB);
-                    accB = mfma(Wh[s - 1], el, accB);
-                    accB = mfma(wlp, eh, accB);
-                }
-                wlp = wl;
-            } else {
-                accB = mfma(Wh[s - 1], eh, accB);
-                accB = mfma(Wh[s - 1], el, accB);
-                accB = mfma(wlp, eh, accB);
-            }
+        for (int s = 0; s < NKMAX; ++s) {
+            Wh[s] = tile_ld(&T.Wf[s][0][lane]);
+            Wl[s] = ld_bf16x8(wlds + (m * NKMAX + s) * 64 + lane);
         }
-        // traces of this lane's outputs t0 + 4 (l / 16) + rr of both tiles, and
-        // lg2 of the window sums (O - R)
-        float tr[2][4], la[2][4];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const mxf4 a = h ? accB : accA;
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int t = tA + 32 * h + 4 * rq + rr;
-                float o = -M.sg * P.rho_pad, lo = 0.f;
-                if (any && t + klo <= L - 1) {
-                    lo = lg2(a[rr]);
-                    const float O = Rb + lo;
-                    o = M.sg * O * ibl;
-                    omin = fminf(omin, O);
-                    omax = fmaxf(omax, O);
-                }
-                tr[h][rr] = o;
-                la[h][rr] = lo;
-            }
+        for (int s = 0; s < NKMAX; ++s) {
+            mx_pin(Wh[s]);
+            mx_pin(Wl[s]);
         }
-        // the other mask's traces of both tiles through LDS
-        float to[2][4];
-        const int pos = tA - MXROUND * k + 4 * rq;
-        if (N > 1) {
+        const int bc = lane & 15, rq = lane >> 4;
+        const unsigned char* ebase = mxs + (m * MXG + bc) * MXRS;
+        for (int k = 0; k < nbody; ++k) {
+            if (k < nround) {
+                const int t0 = MXROUND * k + 16 * hh;
+                const int pr = (t0 + 8 * rq) % MXRING;
+                mxf4 acc[4];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                *(float4*)&xch[(m * MXG + bc) * MXXS + pos + 32 * h] =
-                    make_float4(tr[h][0], tr[h][1], tr[h][2], tr[h][3]);
-            __syncthreads();
+                for (int j = 0; j < 4; ++j) acc[j] = mxf4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const float4 u = *(const float4*)&xch[((1 - m) * MXG + bc) * MXXS + pos + 32 * h];
-                to[h][0] = u.x;
-                to[h][1] = u.y;
-                to[h][2] = u.z;
-                to[h][3] = u.w;
-            }
-        }
-        if (bvalid) {
+                for (int s = 0; s < NKMAX + 3; ++s) {
+                    const unsigned char* ep = ebase + ring_off2(pr, 32 * s);
+                    const bf16x8 eh = ld_bf16x8(ep), el = ld_bf16x8(ep + 16);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int t0 = tA + 32 * h + 4 * rq;
-                const int nv = L - t0;
-                if (nv <= 0) continue;
-                float rt[4], ll[4];
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) {
-                    float v[N];
-                    v[0] = tr[h][rr];
-                    if (N > 1) {
-                        v[0] = m == 0 ? tr[h][rr] : to[h][rr];
-                        v[N - 1] = m == 0 ? to[h][rr] : tr[h][rr];
+                    for (int j = 0; j < 4; ++j) {
+                        const int st = s - j;
+                        if (st >= 0 && st < NKMAX) {
+                            acc[j] = mfma(Wh[st], eh, acc[j]);
+                            acc[j] = mfma(Wh[st], el, acc[j]);
+                            acc[j] = mfma(Wl[st], eh, acc[j]);
+                        }
                     }
-                    float lw;
-                    rt[rr] = mx_root_lw<N>(RC, v, m, lw);
-                    ll[rr] = lw - la[h][rr];
                 }
-                if (ka.root && (N == 1 || h == m)) store4(ka.root, bo * (int64_t)L + t0, nv, rt);
-                if (ka.saved) store4(ka.saved, ((int64_t)m * bt.B + bo) * L + t0, nv, ll);
-            }
-        }
-        stage_write(k + 4, xn);
+                float4* ob = (float4*)accb + ((((k & 1) * N + m) * 2 + hh) * 4) * 64 + lane;
 #pragma unroll
-        for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
-        __syncthreads();
-    };
-    for (int k = 0; k < nround; k += 2) {
-        round(k, xq0, xq1);
-        if (k + 1 < nround) round(k + 1, xq1, xq0);
+                for (int j = 0; j < 4; ++j) ob[j * 64] = make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+            }
+#pragma unroll
+            for (int s = 0; s < NKMAX; ++s) {
+                mx_pin(Wh[s]);
+                mx_pin(Wl[s]);
+            }
+            __syncthreads();
+        }
+    } else {
+        // ---------------------------------------------------------- staging waves
+        const int vw = wv - 2 * N, vt = tid - 128 * N;
+        const int bc = lane & 15, rq = lane >> 4;
+        const int64_t bo = g0 + bc;
+        const bool bvalid = bo < bt.B;
+        float Rb[N], sgm[N], ibl[N], pad[N];
+        int klo[N];
+        bool any[N];
+#pragma unroll
+        for (int mm = 0; mm < N; ++mm) {
+            const MxTab& T = mx.tabs[mm];
+            const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, mm);
+            Rb[mm] = sh.R[mm][bc] + T.lscale;                   // O = Rb + lg2(window sum)
+            sgm[mm] = M.sg;
+            ibl[mm] = 1.f / (M.beta * LOG2E);
+            pad[mm] = -M.sg * P.rho_pad;                        // empty window
+            klo[mm] = T.klo;
+            any[mm] = T.any;
+        }
+        float omin[N], omax[N];
+#pragma unroll
+        for (int mm = 0; mm < N; ++mm) {
+            omin[mm] = INFINITY;
+            omax[mm] = -INFINITY;
+        }
+        float* const root = ka.root;
+        float* const saved = ka.saved;
+        // x of block k + 4 is loaded two rounds before it is staged (memory
+        // latency under load exceeds one round); the loop is unrolled by two
+        // so that the two prefetch buffers keep static register names
+        const Unit U0 = unit(vt), U1 = unit(vt + 128 * N);
+        float xq0[2][8 * DD], xq1[2][8 * DD];
+        stage_load(U0, 4, xq0[0]);
+        stage_load(U1, 4, xq0[1]);
+        auto body = [&](const int k, float (*xn)[8 * DD], float (*xnext)[8 * DD]) {
+            // (unconditional: the addresses are clamped, and a conditional load
+            // would be waited for where the branches join)
+            stage_load(U0, k + 5, xnext[0]);
+            stage_load(U1, k + 5, xnext[1]);
+            if (k >= 1 && k <= nround) {
+                // outputs of round k - 1: this wave's tiles tau = vw * 4 / N + i
+                const int kr = k - 1;
+                const float4* ib = (const float4*)accb + (kr & 1) * N * 8 * 64 + lane;
+#pragma unroll
+                for (int i = 0; i < 4 / N; ++i) {
+                    const int tau = vw * (4 / N) + i, hh = tau >> 2, j = tau & 3;
+                    const int t0 = MXROUND * kr + 16 * hh + 32 * j + 4 * rq;
+                    float tr[N][4], la[N][4];
+#pragma unroll
+                    for (int mm = 0; mm < N; ++mm) {
+                        const float4 a4 = ib[((mm * 2 + hh) * 4 + j) * 64];
+                        const float a[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr) {
+                            // (selects, not branches)
+                            const bool in = any[mm] && t0 + rr + klo[mm] <= L - 1;
+                            const float lo = lg2(a[rr]);
+                            const float O = Rb[mm] + lo;
+                            tr[mm][rr] = mx_sel(in, sgm[mm] * O * ibl[mm], pad[mm]);
+                            la[mm][rr] = mx_sel(in, lo, 0.f);
+                            omin[mm] = fminf(omin[mm], mx_sel(in, O, INFINITY));
+                            omax[mm] = fmaxf(omax[mm], mx_sel(in, O, -INFINITY));
+                        }
+                    }
+                    const int nv = L - t0;
+                    if (bvalid && nv > 0) {
+                        float rt[4], ll[N][4];
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr) {
+                            float v[N], lw[N];
+#pragma unroll
+                            for (int mm = 0; mm < N; ++mm) v[mm] = tr[mm][rr];
+                            rt[rr] = mx_root_lws<N>(RC, v, lw);
+#pragma unroll
+                            for (int mm = 0; mm < N; ++mm) ll[mm][rr] = lw[mm] - la[mm][rr];
+                        }
+                        if (root) mx_store4<VEC>(root + bo * (int64_t)L + t0, nv, rt);
+                        if (saved) {
+#pragma unroll
+                            for (int mm = 0; mm < N; ++mm)
+                                mx_store4<VEC>(saved + ((int64_t)mm * bt.B + bo) * L + t0, nv, ll[mm]);
+                        }
+                    }
+                }
+            }
+            if (k < nround) {
+                stage_write(U0, k + 4, xn[0], sfrag[0]);
+                stage_write(U1, k + 4, xn[1], sfrag[1]);
+            }
+            __syncthreads();
+        };
+        for (int k = 0; k < nbody; k += 2) {
+            body(k, xq0, xq1);
+            body(k + 1, xq1, xq0);
+        }
+#pragma unroll
+        for (int mm = 0; mm < N; ++mm)
+            if (any[mm] && bvalid && omin[mm] <= omax[mm]) {
+                atomicMin(&sh.omin[mm][bc], (int)floorf(omin[mm]));
+                atomicMax(&sh.omax[mm][bc], (int)ceilf(omax[mm]));
+            }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            if (sfrag[i]) atomicOr(&sh.frag[((vt + 128 * N * i) >> 4) & 15], 1);
     }
     // ---- exponent ranges of the traces and the references (for the
     // backward), hand-offs
-    if (any && bvalid && omin <= omax) {
-        atomicMin(&sh.omin[m][bc], (int)floorf(omin));
-        atomicMax(&sh.omax[m][bc], (int)ceilf(omax));
-    }
-    if (sfrag) atomicOr(&sh.frag[sr], 1);
     __syncthreads();
     if (mx.ranges && tid < N * MXG) {
         const int mm = tid / MXG, r = tid % MXG;
@@ -789,8 +867,8 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     // G and l at t .. t+7 (zero outside [0, L))
     auto stage_load = [&](int blk, float* gv, float* lv) {
         const int t0 = MXBLK * blk + 8 * sg8 - skb;
-        mx_load8<1, VEC>(sG, t0, L, sact, gv);
-        mx_load8<1, VEC>(sl, t0, L, sact, lv);
+        mx_load8<1, VEC>(sG, t0, L, gv);
+        mx_load8<1, VEC>(sl, t0, L, lv);
     };
     auto stage_write = [&](int blk, const float* gv, const float* lv) {
         const int p0 = MXBLK * blk + 8 * sg8, t0 = p0 - skb;
@@ -800,7 +878,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
             const int t = t0 + q;
             // l + C <= -O - Q lies within [-MX_HALF, MX_HALF] (the forward's range check)
             const float hv = gv[q] * ex2(fminf(fmaxf(lv[q] + sC, -2.f * MX_HALF), 2.f * MX_HALF));
-            h[q] = sact && t >= 0 && t + sklo <= L - 1 ? hv : 0.f;
+            h[q] = mx_sel(sact && t >= 0 && t + sklo <= L - 1, hv, 0.f);
         }
         bf16x8 hh, hl;
         split8(h, hh, hl);
@@ -869,7 +947,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         // and x at this lane's outputs
         float xv[2][4 * DD];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) mx_load4<DD, VEC>(xo, tA + 32 * h + 4 * rq, L, bvalid, xv[h]);
+        for (int h = 0; h < 2; ++h) mx_load4<DD, VEC>(xo, tA + 32 * h + 4 * rq, L, xv[h]);
         mxf4 accA = {0.f, 0.f, 0.f, 0.f}, accB = accA;
         const int pr = (tA + 8 * rq) % MXRING;
         bf16x8 wlp;
@@ -905,7 +983,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                 const int j = tA + 32 * h + 4 * rq + rr;
                 const float e = mx_zx<DD>(M, xv[h] + rr * DD) + Qb;
                 const float fl = floorf(e);
-                fj[h][rr] = (any && bvalid && j < L) ? ex2(e - fl) : 0.f;
+                fj[h][rr] = mx_sel(any && bvalid && j < L, ex2(e - fl), 0.f);
                 nj[h][rr] = (int)fminf(fmaxf(fl, -300.f), 300.f);
             }
         // d/dx contributions of this mask at the lane's positions
@@ -973,7 +1051,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                     }
                 }
                 float* dp = ka.dx + (bo * (int64_t)L + j0) * DD;
-                if (nv == 4 && (((uintptr_t)dp) & 15) == 0) {
+                if (VEC || (nv == 4 && (((uintptr_t)dp) & 15) == 0)) {
 #pragma unroll
                     for (int q = 0; q < DD; ++q)
                         *(float4*)(dp + 4 * q) = make_float4(gx[h][4 * q], gx[h][4 * q + 1], gx[h][4 * q + 2], gx[h][4 * q + 3]);
