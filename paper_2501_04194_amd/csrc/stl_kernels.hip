@@ -2003,12 +2003,12 @@ hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& pla
 size_t mx_tab_bytes() { return sizeof(MxTab); }
 
 // dynamic LDS of the matrix-core kernels: the rings (n masks x 16 rows), the
-// exchange area (forward: traces; backward: d/dx), the backward's derivative
-// tiles and the lo weight tiles
+// result buffers, and the forward's lo weight tiles or the backward's
+// derivative tiles
 size_t mx_lds_bytes(int n, int D, bool bwd)
 {
-    return (size_t)n * MXG * MXRS + mx_xch_bytes(n, D, bwd) + (bwd ? (size_t)n * NDMAX * 2 * 64 * 16 : 0) +
-           (size_t)n * NKMAX * 64 * 16;
+    return (size_t)n * MXG * MXRS + mx_xch_bytes(n, D, bwd) +
+           (bwd ? (size_t)n * NDMAX * 2 * 64 * 16 : (size_t)n * NKMAX * 64 * 16);
 }
 size_t mx_static_lds() { return sizeof(MxShared); }
 

@@ -48,7 +48,6 @@
 namespace stlmi {
 
 constexpr int MXG = 16;                 // trajectories per work-group (the MFMA N)
-constexpr int MXWPM = 4;                // waves per mask node
 constexpr int NKMAX = 12;               // K-steps (32 offsets each) of a window tile
 constexpr int NDMAX = 4;                // derivative tiles per mask (a K-step with d/da and d/db weights has two)
 constexpr int MXROUND = 128;            // outputs per round (4 pairs of 16-output tiles)
@@ -57,9 +56,6 @@ constexpr int MXNBLK = 5;               // blocks in the ring
 constexpr int MXRING = MXBLK * MXNBLK;  // ring positions per trajectory
 constexpr int MXRS = MXRING / 8 * 32 + 16;   // LDS row stride (bytes): 16 bytes of pad put the 16
                                              // rows a wave reads at once on distinct bank groups
-constexpr int MXXS = MXROUND + 4;       // forward exchange row stride (floats): the 16 bytes of
-                                        // pad spread the rows over the banks
-constexpr int MXXH = MXROUND / 2 + 4;   // backward exchange row stride (positions): half a round
 constexpr float MX_HALF = 100.f;       // largest |z - R| (and half the range of O), log2 units
 constexpr int MX_MAXN = 2;              // mask nodes under the root
 
@@ -238,7 +234,7 @@ struct MxShared {
     int dwhich[MX_MAXN][NDMAX];
     int nd[MX_MAXN];
     int over;                    // backward: more derivative tiles than NDMAX
-    float pp[MX_MAXN][2][MXWPM][MXG];   // backward: d/da, d/db partials per wave
+    float pp[MX_MAXN][2][2][MXG];       // backward: d/da, d/db partials per matrix wave
 };
 
 DEV void mx_handoff(const KArgs& ka, const MxArgs& mx, int64_t b)
@@ -258,10 +254,6 @@ DEV int ring_off2(int pr, int d)
     q = q >= MXRING ? q - MXRING : q;
     return q / 8 * 32;
 }
-
-// the two output tiles (16 outputs each) of wave pair index wq in round k:
-// (t, t + 32) with t = 128 k + 64 (wq / 2) + 16 (wq % 2)
-DEV int mx_pair_t(int k, int wq) { return MXROUND * k + 64 * (wq >> 1) + 16 * (wq & 1); }
 
 // per-mask constants of the linear predicate and the exponent scale, in
 // registers (reading them from the plan inside a loop would put a load and a
@@ -310,31 +302,6 @@ DEV MxRoot mx_root_consts(const DevPlan& P, const float* params)
     r.sg = P.fused.nary_min ? -1.f : 1.f;
     r.bl = r.nary ? params[P.fused.nary_beta] * LOG2E : 1.f;
     r.ibl = 1.f / r.bl;
-    return r;
-}
-
-template <int N>
-DEV float mx_root(const MxRoot& R, const float* v, float* wts)
-{
-    if (N == 1 && !R.nary) {
-        if (wts) wts[0] = 1.f;
-        return v[0];
-    }
-    float m = -INFINITY;
-#pragma unroll
-    for (int k = 0; k < N; ++k) m = fmaxf(m, R.sg * v[k]);
-    float s = 0.f, ek[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        ek[k] = ex2((R.sg * v[k] - m) * R.bl);
-        s += ek[k];
-    }
-    const float r = R.sg * (m + lg2(s) * R.ibl);
-    if (wts) {
-        const float is = __builtin_amdgcn_rcpf(s);
-#pragma unroll
-        for (int k = 0; k < N; ++k) wts[k] = ek[k] * is;
-    }
     return r;
 }
 
@@ -431,36 +398,15 @@ DEV void mx_load4(const float* xb, int j, int L, float* v)
     }
 }
 
-// the root (as mx_root) and log2 of the softmax weight of child `own`
-template <int N>
-DEV float mx_root_lw(const MxRoot& R, const float* v, int own, float& lw)
-{
-    if (N == 1 && !R.nary) {
-        lw = 0.f;
-        return v[0];
-    }
-    float m = -INFINITY;
-#pragma unroll
-    for (int k = 0; k < N; ++k) m = fmaxf(m, R.sg * v[k]);
-    float s = 0.f;
-#pragma unroll
-    for (int k = 0; k < N; ++k) s += ex2((R.sg * v[k] - m) * R.bl);
-    const float ls = lg2(s);
-    float vo = v[0];
-#pragma unroll
-    for (int k = 1; k < N; ++k) vo = k == own ? v[k] : vo;
-    lw = (R.sg * vo - m) * R.bl - ls;
-    return R.sg * (m + ls * R.ibl);
-}
-
-// bytes of LDS of the matrix-core kernels beyond the rings (forward: two
-// buffers of window sums; backward: the d/dx exchange)
+// bytes of LDS of the matrix-core kernels beyond the rings: two buffers
+// (alternating rounds) of the matrix waves' results, 8 tiles per mask
 constexpr size_t mx_xch_bytes(int n, int D, bool bwd)
 {
-    return bwd ? (n < 2 ? 0 : (size_t)n * MXG * MXXH * D * sizeof(float)) : (size_t)2 * n * 8 * 64 * 16;
+    return (void)D, (void)bwd, (size_t)2 * n * 8 * 64 * 16;
 }
 
-// the root (as mx_root) and log2 of the softmax weight of every child
+// the root (the smooth And/Or of the mask traces) and log2 of the softmax
+// weight of every child
 template <int N>
 DEV float mx_root_lws(const MxRoot& R, const float* v, float* lw)
 {
@@ -785,6 +731,12 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     if (tid < MXG && sh.frag[tid] && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
 }
 
+// Backward, with the forward's two roles: matrix waves (2 per mask) compute
+// round k's transposed window sums D_j = sum_t w_{j-t} H_t over four 32-aligned
+// output tiles (sharing each ring read) and the band derivative sums, take
+// 2^{z_j + Q} at their outputs, add d/da, d/db into their partials and pass
+// the d/dx factors to LDS; staging waves add the masks' d/dx of round k - 1,
+// store it, and stage block k + 4 of every mask's H.
 template <int N, int DD, bool VEC>
 __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt, KArgs ka, MxArgs mx)
 {
@@ -793,7 +745,6 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     const DevPlan& P = plan;
     const DevPlan* Pk = (const DevPlan*)__builtin_amdgcn_kernarg_segment_ptr();
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int m = wv / MXWPM, wq = wv % MXWPM;
     const int L = (int)bt.T;
     const int64_t g0 = (int64_t)blockIdx.x * MXG;
     bool ok = true;
@@ -850,240 +801,277 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     }
     __syncthreads();
     const bool over = sh.over != 0;
-    // ---- staging: thread tid owns the 8-position group g of trajectory row sr
-    // of mask sm in every block.  Position p of mask m is time t = p - kb_m;
-    // H_m(t) = G(t) 2^{l_m(t) + C} (0 outside the trajectory and where the
-    // window of t is empty)
-    const int sm = tid >> 8, sr = (tid >> 4) & 15, sg8 = tid & 15;
-    const int64_t sb = g0 + sr;
-    const bool srow = sb < bt.B && !sh.frag[sr] && !over;
-    const MxTab& TS = mx.tabs[sm];
-    const int skb = TS.kb, sklo = TS.klo;
-    const bool sact = srow && TS.any;
-    const float* sG = ka.G + (srow ? sb : 0) * (int64_t)L;
-    const float* sl = ka.saved_in + ((int64_t)sm * bt.B + (srow ? sb : 0)) * L;
-    unsigned char* srowp = mxs + (sm * MXG + sr) * MXRS;
-    const float sC = sh.C[sm][sr];
-    // G and l at t .. t+7 (zero outside [0, L))
-    auto stage_load = [&](int blk, float* gv, float* lv) {
-        const int t0 = MXBLK * blk + 8 * sg8 - skb;
-        mx_load8<1, VEC>(sG, t0, L, gv);
-        mx_load8<1, VEC>(sl, t0, L, lv);
+    // ---- staging units (as in the forward): unit u = (mask u / 256, row
+    // (u / 16) % 16, 8-position group u % 16).  Position p of mask m is time
+    // t = p - kb_m; H_m(t) = G(t) 2^{l_m(t) + C} (0 outside the trajectory and
+    // where the window of t is empty)
+    struct Unit {
+        const float* G;
+        const float* l;
+        unsigned char* row;
+        float C;
+        int t0;         // time of the unit's first position in block 0
+        int g8;
+        int klo;
+        bool act;
     };
-    auto stage_write = [&](int blk, const float* gv, const float* lv) {
-        const int p0 = MXBLK * blk + 8 * sg8, t0 = p0 - skb;
+    auto unit = [&](int u) {
+        Unit U;
+        const int um = u >> 8, ur = (u >> 4) & 15, ug = u & 15;
+        const MxTab& TU = mx.tabs[um];
+        const int64_t b = g0 + ur;
+        const bool row = b < bt.B && !sh.frag[ur] && !over;
+        U.G = ka.G + (row ? b : 0) * (int64_t)L;
+        U.l = ka.saved_in + ((int64_t)um * bt.B + (row ? b : 0)) * L;
+        U.row = mxs + (um * MXG + ur) * MXRS;
+        U.C = sh.C[um][ur];
+        U.t0 = 8 * ug - TU.kb;
+        U.g8 = 8 * ug;
+        U.klo = TU.klo;
+        U.act = row && TU.any;
+        return U;
+    };
+    auto stage_load = [&](const Unit& U, int blk, float* gv, float* lv) {
+        mx_load8<1, VEC>(U.G, MXBLK * blk + U.t0, L, gv);
+        mx_load8<1, VEC>(U.l, MXBLK * blk + U.t0, L, lv);
+    };
+    auto stage_write = [&](const Unit& U, int blk, const float* gv, const float* lv) {
+        const int t0 = MXBLK * blk + U.t0;
         float h[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int t = t0 + q;
             // l + C <= -O - Q lies within [-MX_HALF, MX_HALF] (the forward's range check)
-            const float hv = gv[q] * ex2(fminf(fmaxf(lv[q] + sC, -2.f * MX_HALF), 2.f * MX_HALF));
-            h[q] = mx_sel(sact && t >= 0 && t + sklo <= L - 1, hv, 0.f);
+            const float hv = gv[q] * ex2(fminf(fmaxf(lv[q] + U.C, -2.f * MX_HALF), 2.f * MX_HALF));
+            h[q] = mx_sel(U.act && t >= 0 && t + U.klo <= L - 1, hv, 0.f);
         }
         bf16x8 hh, hl;
         split8(h, hh, hl);
-        unsigned char* q = srowp + ring_off(p0);
+        unsigned char* q = U.row + ring_off(MXBLK * blk + U.g8);
         *(bf16x8*)q = hh;
         *(bf16x8*)(q + 16) = hl;
     };
     {
+        const Unit U = unit(tid);
         float gv[4][8], lv[4][8];
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) stage_load(blk, gv[blk], lv[blk]);
+        for (int blk = 0; blk < 4; ++blk) stage_load(U, blk, gv[blk], lv[blk]);
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) stage_write(blk, gv[blk], lv[blk]);
+        for (int blk = 0; blk < 4; ++blk) stage_write(U, blk, gv[blk], lv[blk]);
     }
-    // ---- this wave's mask: weight and derivative tiles, constants
-    const MxTab& T = mx.tabs[m];
-    const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, m);
-    const bool any = T.any;
-    // hi tiles in registers, lo tiles in LDS (after the derivative tiles)
-    uint4* dlds = (uint4*)(mxs + N * MXG * MXRS + mx_xch_bytes(N, DD, true));
-    uint4* wlds = dlds + N * NDMAX * 128;
-    for (int e = tid; e < N * NKMAX * 64; e += blockDim.x) {
-        const int mm = e / (NKMAX * 64), st = (e / 64) % NKMAX, l = e & 63;
-        wlds[e] = mx.tabs[mm].Wb[st][1][l];
-    }
-    const uint4* wl_m = wlds + m * NKMAX * 64 + lane;
-    bf16x8 Wh[NKMAX];
-#pragma unroll
-    for (int s = 0; s < NKMAX; ++s) Wh[s] = tile_ld(&T.Wb[s][0][lane]);
-#pragma unroll
-    for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
     // derivative tiles of every mask in LDS ([n][NDMAX][hi, lo][lane], zero
     // tiles in unused slots)
+    float* gbuf = (float*)(mxs + N * MXG * MXRS);       // [2][N][2][4][64][4] d/dx factors
+    uint4* dlds = (uint4*)(mxs + N * MXG * MXRS + mx_xch_bytes(N, DD, true));
     for (int e = tid; e < N * NDMAX * 2 * 64; e += blockDim.x) {
         const int mm = e / (NDMAX * 128), d = (e / 128) % NDMAX, hl = (e / 64) & 1, l = e & 63;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (d < sh.nd[mm]) v = mx.tabs[mm].Dt[sh.dstep[mm][d]][sh.dwhich[mm][d]][hl][l];
         dlds[e] = v;
     }
-    const int nd = sh.nd[m];
-    int dst[NDMAX];
-    bool isb[NDMAX];
-#pragma unroll
-    for (int d = 0; d < NDMAX; ++d) {
-        const bool use = d < nd;
-        dst[d] = use ? sh.dstep[m][d] : 0;
-        isb[d] = use && sh.dwhich[m][d] != 0;
-    }
-    const uint4* dl_m = dlds + m * NDMAX * 128 + lane;
+    const int nround = (L + MXROUND - 1) / MXROUND;
+    const int nbody = (nround + 2) & ~1;        // as in the forward: even, both roles alike
+    const bool matrix = wv < 2 * N;
     const int bc = lane & 15, rq = lane >> 4;
     const int64_t bo = g0 + bc;
     const bool bvalid = bo < bt.B && !sh.frag[bc] && !over;
-    const float* xo = bt.x + (bo < bt.B ? bo : 0) * (int64_t)L * DD;
-    const unsigned char* hbase = mxs + (m * MXG + bc) * MXRS;
-    // [N][16][MXXH][DD]: d/dx of the tile of each pair the other mask's waves store
-    float* xch = (float*)(mxs + N * MXG * MXRS);
-    const float Qb = sh.R[m][bc];
-    float pam = 0.f, pbm = 0.f;
-    const int nround = (L + MXROUND - 1) / MXROUND;
     __syncthreads();
-    for (int k = 0; k < nround; ++k) {
-        // loads of block k+4 go out first
-        float gn[8], ln[8];
-        stage_load(k + 4, gn, ln);
-        const int tA = mx_pair_t(k, wq);
-        // and x at this lane's outputs
-        float xv[2][4 * DD];
+    if (matrix) {
+        // ---------------------------------------------------------- matrix waves
+        const int m = wv >> 1, hh = wv & 1;
+        const MxTab& T = mx.tabs[m];
+        const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, m);
+        const bool any = T.any;
+        bf16x8 Wh[NKMAX], Wl[NKMAX];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) mx_load4<DD, VEC>(xo, tA + 32 * h + 4 * rq, L, xv[h]);
-        mxf4 accA = {0.f, 0.f, 0.f, 0.f}, accB = accA;
-        const int pr = (tA + 8 * rq) % MXRING;
-        bf16x8 wlp;
-#pragma unroll
-        for (int s = 0; s <= NKMAX; ++s) {
-            const unsigned char* ep = hbase + ring_off2(pr, 32 * s);
-            const bf16x8 hh = ld_bf16x8(ep), hl = ld_bf16x8(ep + 16);
-            if (s < NKMAX) {
-                const bf16x8 wl = ld_bf16x8(wl_m + s * 64);
-                accA = mfma(Wh[s], hh, accA);
-                accA = mfma(Wh[s], hl, accA);
-                accA = mfma(wl, hh, accA);
-                if (s >= 1) {
-                    accB = mfma(Wh[s - 1], hh, accB);
-                    accB = mfma(Wh[s - 1], hl, accB);
-                    accB = mfma(wlp, hh, accB);
-                }
-                wlp = wl;
-            } else {
-                accB = mfma(Wh[s - 1], hh, accB);
-                accB = mfma(Wh[s - 1], hl, accB);
-                accB = mfma(wlp, hh, accB);
-            }
+        for (int s = 0; s < NKMAX; ++s) {
+            Wh[s] = tile_ld(&T.Wb[s][0][lane]);
+            Wl[s] = tile_ld(&T.Wb[s][1][lane]);
         }
-        // 2^{z_j + Q} = f 2^n at this lane's outputs (the products below are
-        // moderate even where the factors are not); f = 0 where j is not an output
-        float fj[2][4];
-        int nj[2][4];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int j = tA + 32 * h + 4 * rq + rr;
-                const float e = mx_zx<DD>(M, xv[h] + rr * DD) + Qb;
-                const float fl = floorf(e);
-                fj[h][rr] = mx_sel(any && bvalid && j < L, ex2(e - fl), 0.f);
-                nj[h][rr] = (int)fminf(fmaxf(fl, -300.f), 300.f);
-            }
-        // d/dx contributions of this mask at the lane's positions
-        float gx[2][4 * DD];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const mxf4 a = h ? accB : accA;
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const float gu = ldexpf(a[rr] * fj[h][rr], nj[h][rr]);
-#pragma unroll
-                for (int d = 0; d < DD; ++d) gx[h][rr * DD + d] = M.w[d] * gu;
-            }
+        for (int s = 0; s < NKMAX; ++s) {
+            mx_pin(Wh[s]);
+            mx_pin(Wl[s]);
         }
-        // derivative sums (K-step dst[d] of tile A, and of tile B one step
-        // later), added straight into this lane's d/da, d/db partials
+        const int nd = sh.nd[m];
+        int dst[NDMAX];
+        bool isb[NDMAX];
 #pragma unroll
         for (int d = 0; d < NDMAX; ++d) {
-            const bf16x8 Dh = ld_bf16x8(dl_m + d * 128), Dl = ld_bf16x8(dl_m + d * 128 + 64);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const unsigned char* ep = hbase + ring_off2(pr, 32 * (dst[d] + h));
-                const bf16x8 hh = ld_bf16x8(ep), hl = ld_bf16x8(ep + 16);
-                mxf4 a = mfma(Dh, hh, mxf4{0.f, 0.f, 0.f, 0.f});
-                a = mfma(Dh, hl, a);
-                a = mfma(Dl, hh, a);
-                float sum = 0.f;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) sum += ldexpf(a[q] * fj[h][q], nj[h][q]);
-                pam += isb[d] ? 0.f : sum;
-                pbm += isb[d] ? sum : 0.f;
-            }
+            const bool use = d < nd;
+            dst[d] = use ? sh.dstep[m][d] : 0;
+            isb[d] = use && sh.dwhich[m][d] != 0;
         }
-        // the waves of mask m store d/dx of tile m of each pair (both when
-        // N = 1): the other tile's contribution goes to the other mask's waves
-        const int cpos = 16 * (wq & 1) + 4 * rq + 32 * (wq >> 1);     // half-round position of both tiles
-        if (N > 1) {
+        const uint4* dl_m = dlds + m * NDMAX * 128 + lane;
+        const float* xo = bt.x + (bo < bt.B ? bo : 0) * (int64_t)L * DD;
+        const unsigned char* hbase = mxs + (m * MXG + bc) * MXRS;
+        const float Qb = sh.R[m][bc];
+        float pam = 0.f, pbm = 0.f;
+        // x at this lane's outputs of the four tiles, loaded one round ahead
+        // (unconditionally: the addresses are clamped)
+        float xv[4][4 * DD];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                if (h != m) {
-                    float* xp = xch + ((m * MXG + bc) * MXXH + cpos) * DD;
+        for (int j = 0; j < 4; ++j) mx_load4<DD, VEC>(xo, 16 * hh + 32 * j + 4 * rq, L, xv[j]);
+        for (int k = 0; k < nbody; ++k) {
+            if (k < nround) {
+                const int t0 = MXROUND * k + 16 * hh;
+                // z_j + Q at this lane's outputs
+                float ez[4][4];
 #pragma unroll
-                    for (int q = 0; q < DD; ++q)
-                        *(float4*)(xp + 4 * q) = make_float4(gx[h][4 * q], gx[h][4 * q + 1], gx[h][4 * q + 2],
-                                                             gx[h][4 * q + 3]);
-                }
-            __syncthreads();
-        }
-        if (bvalid) {
+                for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (N > 1 && h != m) continue;
-                const int j0 = tA + 32 * h + 4 * rq;
-                const int nv = min(4, L - j0);
-                if (nv <= 0) continue;
-                if (N > 1) {
-                    const float* xp = xch + (((1 - m) * MXG + bc) * MXXH + cpos) * DD;
+                    for (int rr = 0; rr < 4; ++rr) ez[j][rr] = mx_zx<DD>(M, xv[j] + rr * DD) + Qb;
+                const int pr = (t0 + 8 * rq) % MXRING;
+                mxf4 acc[4];
 #pragma unroll
-                    for (int q = 0; q < DD; ++q) {
-                        const float4 u = *(const float4*)(xp + 4 * q);
-                        gx[h][4 * q] += u.x;
-                        gx[h][4 * q + 1] += u.y;
-                        gx[h][4 * q + 2] += u.z;
-                        gx[h][4 * q + 3] += u.w;
+                for (int j = 0; j < 4; ++j) acc[j] = mxf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < NKMAX + 3; ++s) {
+                    const unsigned char* ep = hbase + ring_off2(pr, 32 * s);
+                    const bf16x8 eh = ld_bf16x8(ep), el = ld_bf16x8(ep + 16);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int st = s - j;
+                        if (st >= 0 && st < NKMAX) {
+                            acc[j] = mfma(Wh[st], eh, acc[j]);
+                            acc[j] = mfma(Wh[st], el, acc[j]);
+                            acc[j] = mfma(Wl[st], eh, acc[j]);
+                        }
                     }
                 }
-                float* dp = ka.dx + (bo * (int64_t)L + j0) * DD;
-                if (VEC || (nv == 4 && (((uintptr_t)dp) & 15) == 0)) {
+                // 2^{z_j + Q} = f 2^n at this lane's outputs (the products below are
+                // moderate even where the factors are not); f = 0 where j is not an output
 #pragma unroll
-                    for (int q = 0; q < DD; ++q)
-                        *(float4*)(dp + 4 * q) = make_float4(gx[h][4 * q], gx[h][4 * q + 1], gx[h][4 * q + 2], gx[h][4 * q + 3]);
-                } else {
-                    for (int q = 0; q < nv * DD; ++q) dp[q] = gx[h][q];
+                for (int j = 0; j < 4; ++j) mx_load4<DD, VEC>(xo, t0 + MXROUND + 32 * j + 4 * rq, L, xv[j]);
+                float fj[4][4];
+                int nj[4][4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int t = t0 + 32 * j + 4 * rq + rr;
+                        const float e = ez[j][rr];
+                        const float fl = floorf(e);
+                        fj[j][rr] = mx_sel(any && bvalid && t < L, ex2(e - fl), 0.f);
+                        nj[j][rr] = (int)fminf(fmaxf(fl, -300.f), 300.f);
+                    }
+                // d/dx factors (times w of the predicate, by the staging waves)
+                float4* ob = (float4*)gbuf + ((((k & 1) * N + m) * 2 + hh) * 4) * 64 + lane;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float g[4];
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) g[rr] = ldexpf(acc[j][rr] * fj[j][rr], nj[j][rr]);
+                    ob[j * 64] = make_float4(g[0], g[1], g[2], g[3]);
+                }
+                // derivative sums: K-step dst[d] of every tile, added straight
+                // into this lane's d/da, d/db partials
+#pragma unroll
+                for (int d = 0; d < NDMAX; ++d) {
+                    const bf16x8 Dh = ld_bf16x8(dl_m + d * 128), Dl = ld_bf16x8(dl_m + d * 128 + 64);
+                    float sum = 0.f;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const unsigned char* ep = hbase + ring_off2(pr, 32 * (dst[d] + j));
+                        const bf16x8 eh = ld_bf16x8(ep), el = ld_bf16x8(ep + 16);
+                        mxf4 a = mfma(Dh, eh, mxf4{0.f, 0.f, 0.f, 0.f});
+                        a = mfma(Dh, el, a);
+                        a = mfma(Dl, eh, a);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) sum += ldexpf(a[q] * fj[j][q], nj[j][q]);
+                    }
+                    pam += isb[d] ? 0.f : sum;
+                    pbm += isb[d] ? sum : 0.f;
                 }
             }
-        }
-        stage_write(k + 4, gn, ln);
 #pragma unroll
-        for (int s = 0; s < NKMAX; ++s) mx_pin(Wh[s]);
-        __syncthreads();
-    }
-    // ---- d/da, d/db partials: lanes of one trajectory (l, l + 16, l + 32,
-    // l + 48), then the mask's waves in order
-    pam *= M.sg / M.beta;
-    pbm *= M.sg / M.beta;
-    pam += __shfl_xor(pam, 16);
-    pbm += __shfl_xor(pbm, 16);
-    pam += __shfl_xor(pam, 32);
-    pbm += __shfl_xor(pbm, 32);
-    if (lane < MXG) {
-        sh.pp[m][0][wq][lane] = pam;
-        sh.pp[m][1][wq][lane] = pbm;
+            for (int s = 0; s < NKMAX; ++s) {
+                mx_pin(Wh[s]);
+                mx_pin(Wl[s]);
+            }
+            __syncthreads();
+        }
+        // ---- d/da, d/db partials: lanes of one trajectory (l, l + 16, l + 32,
+        // l + 48), then the mask's two matrix waves in order
+        pam *= M.sg / M.beta;
+        pbm *= M.sg / M.beta;
+        pam += __shfl_xor(pam, 16);
+        pbm += __shfl_xor(pbm, 16);
+        pam += __shfl_xor(pam, 32);
+        pbm += __shfl_xor(pbm, 32);
+        if (lane < MXG) {
+            sh.pp[m][0][hh][lane] = pam;
+            sh.pp[m][1][hh][lane] = pbm;
+        }
+    } else {
+        // ---------------------------------------------------------- staging waves
+        const int vw = wv - 2 * N, vt = tid - 128 * N;
+        float wd[N][DD];
+#pragma unroll
+        for (int mm = 0; mm < N; ++mm) {
+            const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, mm);
+#pragma unroll
+            for (int d = 0; d < DD; ++d) wd[mm][d] = M.w[d];
+        }
+        float* const dx = ka.dx;
+        const Unit U0 = unit(vt), U1 = unit(vt + 128 * N);
+        // G and l of block k + 4 are loaded two rounds before they are staged
+        float gq0[2][8], lq0[2][8], gq1[2][8], lq1[2][8];
+        stage_load(U0, 4, gq0[0], lq0[0]);
+        stage_load(U1, 4, gq0[1], lq0[1]);
+        auto body = [&](const int k, float (*gn)[8], float (*ln)[8], float (*gx)[8], float (*lx)[8]) {
+            stage_load(U0, k + 5, gx[0], lx[0]);
+            stage_load(U1, k + 5, gx[1], lx[1]);
+            if (k >= 1 && k <= nround) {
+                // d/dx of round k - 1: this wave's tiles tau = vw * 4 / N + i
+                const int kr = k - 1;
+                const float4* ib = (const float4*)gbuf + (kr & 1) * N * 8 * 64 + lane;
+#pragma unroll
+                for (int i = 0; i < 4 / N; ++i) {
+                    const int tau = vw * (4 / N) + i, hh = tau >> 2, j = tau & 3;
+                    const int j0 = MXROUND * kr + 16 * hh + 32 * j + 4 * rq;
+                    float g[4 * DD];
+#pragma unroll
+                    for (int q = 0; q < 4 * DD; ++q) g[q] = 0.f;
+#pragma unroll
+                    for (int mm = 0; mm < N; ++mm) {
+                        const float4 a4 = ib[((mm * 2 + hh) * 4 + j) * 64];
+                        const float a[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                            for (int d = 0; d < DD; ++d) g[rr * DD + d] = fmaf(wd[mm][d], a[rr], g[rr * DD + d]);
+                    }
+                    const int nv = min(4, L - j0);
+                    if (bvalid && nv > 0) {
+                        float* dp = dx + (bo * (int64_t)L + j0) * DD;
+                        if (VEC || (nv == 4 && (((uintptr_t)dp) & 15) == 0)) {
+#pragma unroll
+                            for (int q = 0; q < DD; ++q)
+                                *(float4*)(dp + 4 * q) = make_float4(g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]);
+                        } else {
+                            for (int q = 0; q < nv * DD; ++q) dp[q] = g[q];
+                        }
+                    }
+                }
+            }
+            if (k < nround) {
+                stage_write(U0, k + 4, gn[0], ln[0]);
+                stage_write(U1, k + 4, gn[1], ln[1]);
+            }
+            __syncthreads();
+        };
+        for (int k = 0; k < nbody; k += 2) {
+            body(k, gq0, lq0, gq1, lq1);
+            body(k + 1, gq1, lq1, gq0, lq0);
+        }
     }
     __syncthreads();
     if (tid < 2 * N * MXG) {
         const int mm = tid / (2 * MXG), ab = (tid / MXG) & 1, r = tid % MXG;
         const int64_t bq = g0 + r;
         if (bq < bt.B && !sh.frag[r] && !over) {
-            float s = 0.f;
-            for (int w = 0; w < MXWPM; ++w) s += sh.pp[mm][ab][w][r];
+            const float s = sh.pp[mm][ab][0][r] + sh.pp[mm][ab][1][r];
             const int slot = Pk->ins[Pk->fused.ins[mm]].mslot;
             if (slot >= 0) mx.part[(bq * P.n_masks + slot) * 2 + ab] = s;
         }
