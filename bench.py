@@ -30,8 +30,41 @@ BYTES_BWD = 20       # per signal-step: x (8 B) + G (4 B) + dx (8 B)
 METRIC = "fwd+bwd signal-steps/s (B=4096,T=2048 smooth STL); % of HBM roofline"
 
 
-def cpu_baseline(n_traj=4096):
-    """The FP64 oracle (unchanged) on a bounded sample of the same workload."""
+def cpu_model():
+    """The host CPU's model name (what lscpu prints), from /proc/cpuinfo."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads for the all-cores oracle run: the process's CPU share."""
+    n = os.environ.get("OMP_NUM_THREADS")
+    if n and n.isdigit() and int(n) > 0:
+        return int(n)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _oracle_child(n_traj, threads):
+    """Time the FP64 oracle (forward + backward of the headline workload on its
+    first n_traj trajectories) in a child process with `threads` OpenMP threads
+    (the thread count of an OpenMP runtime is fixed once it starts).  The child
+    is this script in --oracle-child mode; it never touches the GPU."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-child", str(n_traj)], env=env,
+                       capture_output=True, text=True, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])["seconds"]
+
+
+def oracle_child_main(n_traj):
     import oracle
     from paper_2501_04194_amd import workloads as W
     oracle.build()
@@ -41,23 +74,53 @@ def cpu_baseline(n_traj=4096):
     t0 = time.perf_counter()
     oracle.forward(spec, x, params=p32)
     oracle.backward(spec, x, G, params=p32)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n_traj * x.shape[1] / dt, "unit": "signal-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of the 4096 trajectories (T=2048), forward + backward, FP64 C oracle with OpenMP, %.1f s"
-                      % (n_traj, dt)}
+    print(json.dumps({"seconds": time.perf_counter() - t0}), flush=True)
+
+
+def cpu_baseline(n_traj=4096, n_traj_1t=512):
+    """The FP64 oracle (unchanged, OpenMP over trajectories) on bounded samples
+    of the same workload: all host threads on n_traj trajectories, one thread
+    on n_traj_1t."""
+    T = 2048
+    nt = host_threads()
+    dt_all = _oracle_child(n_traj, nt)
+    dt_one = _oracle_child(n_traj_1t, 1)
+    return {"value": n_traj * T / dt_all, "unit": "signal-steps/s", "cores": nt, "kind": "oracle",
+            "sample": "%d of the 4096 trajectories (T=%d), forward + backward, FP64 C oracle, %d OpenMP threads, "
+                      "%.2f s" % (n_traj, T, nt, dt_all),
+            "value_1thread": n_traj_1t * T / dt_one,
+            "sample_1thread": "%d trajectories, 1 thread, %.2f s" % (n_traj_1t, dt_one),
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+MFMA_PEAK_TFLOPS = 2500.0     # dense bf16
+MFMA_FLOP = 2 * 16 * 16 * 32  # one v_mfma_f32_16x16x32_bf16
+
+
+def mfma_executed(B, T, fwd_ms, bwd_ms, n_masks=2, nkmax=12, ndmax=4):
+    """bf16 matrix-core throughput of the two calls as executed: per group of
+    16 trajectories and round of 128 outputs, two matrix waves per mask run
+    4 tiles x nkmax K-steps x 3 products (forward), plus ndmax x 4 x 3
+    derivative products (backward)."""
+    groups, rounds = -(-B // 16), -(-T // 128)
+    per = groups * rounds * 2 * n_masks * MFMA_FLOP
+    f = per * 4 * nkmax * 3
+    b = per * (4 * nkmax * 3 + ndmax * 4 * 3)
+    tf = {"forward": f / (fwd_ms * 1e-3) / 1e12, "backward": b / (bwd_ms * 1e-3) / 1e12}
+    return {"unit": "TFLOP/s", "peak": MFMA_PEAK_TFLOPS, "forward": tf["forward"], "backward": tf["backward"],
+            "frac_backward": tf["backward"] / MFMA_PEAK_TFLOPS, "flop_per_step": f + b}
 
 
 def traffic_per_launch():
     """HBM bytes per backward launch from the committed rocprofv3 counter summary,
     or None when the kernel sources changed since the counters were taken."""
     import hashlib
-    tf = os.path.join(ROOT, "profiles", "traffic_bwd_smooth_mask_B4096_T2048.json")
+    tf = os.path.join(ROOT, "profiles", "traffic_stl_mx_bwd_B4096_T2048.json")
     if not os.path.exists(tf):
         return None
     rec = json.load(open(tf))
     csrc = os.path.join(ROOT, "paper_2501_04194_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("stl_fused.h", "stl_kernels.hip", "stl_plan.h"))
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("stl_mx.h", "stl_kernels.hip", "stl_plan.h"))
     if hashlib.sha256(src).hexdigest() != rec.get("sources_sha256"):
         return None
     return rec.get("bytes_per_launch")
@@ -359,7 +422,10 @@ def main():
                              "planning"],
                     help="smooth_mask: the headline workload; the others are secondary measurements")
     ap.add_argument("--interval-batch", type=int, default=1, help="signals per interval sweep (--workload intervals)")
+    ap.add_argument("--oracle-child", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_child:
+        return oracle_child_main(args.oracle_child)
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (trajectories shard with no "
               "communication; see the design notes).  Run with --gpus 1.", file=sys.stderr)
@@ -461,9 +527,15 @@ def main():
         "hbm_frac_step": (BYTES_FWD + BYTES_BWD) * value / (HBM_PEAK_GBS * 1e9),
         "kernel_ms": {"forward": fwd_ms, "backward": bwd_ms},
         "wall_s": t_wall,
-        "roofline": {"bound": "hbm", "kernel": "stl_fused_bwd" if dom_is_bwd else "stl_fused_fwd",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("stl_mx_bwd + hand-off fix-up (the stl_backward_saved call)" if dom_is_bwd
+                                else "stl_mx_tables + stl_mx_fwd + hand-off fix-up (the stl_forward_saving call)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_step": BYTES_BWD if dom_is_bwd else BYTES_FWD},
+        # the matrix cores' bf16 products as executed (three per split factor,
+        # zero tiles included), against the dense bf16 peak
+        "mfma_executed": mfma_executed(B, T, fwd_ms, bwd_ms),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_traj)

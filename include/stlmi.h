@@ -236,7 +236,9 @@ stl_status stl_backward(const stl_plan* plan, const stl_batch* batch, const floa
  * children's traces, the matrix-core kernels log2 of each child's softmax
  * weight at the root minus log2 of its window sum), and for the matrix-core
  * path each trajectory's exponent range and reference ([B][n_mask][3]
- * int32); only the header otherwise.  The contents are private to the pair.
+ * int32), the masks' weight tables and three counters of the backward's
+ * hand-off list; only the header otherwise.  The contents are private to the
+ * pair (stl_backward_saved writes the counters back to zero).
  * A flag is 1 (fp64 fused forward) or 2 (matrix-core forward) where the
  * trajectory's saved data are valid for the backward of the same path.
  *

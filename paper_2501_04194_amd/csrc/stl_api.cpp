@@ -36,8 +36,11 @@ size_t mx_tab_bytes();
 size_t mx_lds_bytes(int n, int D, bool bwd);
 size_t mx_static_lds();
 hipError_t set_max_lds_mx(size_t bytes);
+hipError_t launch_mx_tables(const DevPlan& plan, const struct Batch& bt, const float* params, struct MxTab* tabs,
+                            int* counters2, hipStream_t s);
 hipError_t launch_mx(bool bwd, const DevPlan& plan, const struct Batch& bt, const struct KArgs& ka,
-                     const struct MxArgs& mx, int* table_saved_flag, bool tables, size_t lds, hipStream_t s);
+                     const struct MxArgs& mx, int* table_saved_flag, int* counters2, bool tables, size_t lds,
+                     hipStream_t s);
 int interval_max_T();
 int pstl_max_BT();
 hipError_t launch_pstl_descent(const float* x, int B, int T, int D, const float* w, float c, int op_sg, float eps,
@@ -754,14 +757,27 @@ static size_t saved_traces_bytes(const stl_plan* plan, const stl_batch* bt)
     return (size_t)plan->dev.fused.n * bt->B * bt->T * sizeof(float);
 }
 
+// matrix-core path: after the ranges (256-aligned) the per-mask tables the
+// saving forward computed, then three counters of the backward's hand-off list
+static size_t saved_tables_offset(const stl_plan* plan, const stl_batch* bt)
+{
+    const size_t e = saved_header(bt->B) + saved_traces_bytes(plan, bt) +
+                     (size_t)bt->B * plan->dev.fused.n * 3 * sizeof(int32_t);
+    return (e + 255) / 256 * 256;
+}
+
+static size_t saved_counters_offset(const stl_plan* plan, const stl_batch* bt)
+{
+    return saved_tables_offset(plan, bt) + ((size_t)plan->dev.fused.n * mx_tab_bytes() + 255) / 256 * 256;
+}
+
 static size_t saved_bytes_needed(const stl_plan* plan, const stl_batch* bt)
 {
     const int n = plan->dev.fused.n;
     const bool mx = mx_applies(plan->dev, bt, nullptr, false);
     const bool fusable = n > 0 && bt->offsets == nullptr && (bt->T <= fused_max_T() || mx);
-    size_t s = saved_header(bt->B) + (fusable ? saved_traces_bytes(plan, bt) : 0);
-    if (mx) s += (size_t)bt->B * n * 3 * sizeof(int32_t);
-    return s;
+    if (mx) return saved_counters_offset(plan, bt) + 256;
+    return saved_header(bt->B) + (fusable ? saved_traces_bytes(plan, bt) : 0);
 }
 
 // saved: 0 none, 1 forward writes d_saved, 2 backward reads it
@@ -831,20 +847,31 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
         mx.handed = (int*)(wsb + g.off_handed);
         mx.part = ka.mask_part;
         mx.ranges = nullptr;
+        mx.own_flags = 0;
         hipError_t e;
         int* traces_flags = nullptr;
+        int* saved_counters = nullptr;
         if (saved) {
             traces_flags = (int*)d_saved;
             float* traces = (float*)((char*)d_saved + saved_header(bt->B));
             ka.saved_flag = traces_flags;
             mx.ranges = (int*)((char*)traces + saved_traces_bytes(plan, bt));
+            // the saving forward's tables serve the backward; the backward's
+            // hand-off list counts through counters kept beside them (cleared
+            // by the forward's tables kernel and by the backward's fix-up)
+            mx.tabs = (const MxTab*)((char*)d_saved + saved_tables_offset(plan, bt));
+            saved_counters = (int*)((char*)d_saved + saved_counters_offset(plan, bt));
             if (saved == 1) ka.saved = traces;
             else ka.saved_in = traces;
         }
         if (!bwd) {
-            e = launch_mx(false, dp, b, ka, mx, saved == 1 ? traces_flags : nullptr, true, g.mx_lds, st);
+            e = launch_mx(false, dp, b, ka, mx, saved == 1 ? traces_flags : nullptr, saved_counters, true, g.mx_lds,
+                          st);
         } else if (saved == 2) {
-            e = launch_mx(true, dp, b, ka, mx, nullptr, true, g.mx_lds, st);
+            ka.counter = saved_counters;
+            ka.list_count = saved_counters + 1;
+            mx.own_flags = 1;
+            e = launch_mx(true, dp, b, ka, mx, nullptr, nullptr, false, g.mx_lds, st);
         } else {
             // no saved traces: the forward fills workspace copies first
             KArgs kf = ka;
@@ -853,12 +880,12 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
             kf.saved = (float*)(wsb + g.off_mxtr);
             kf.saved_flag = (int*)(wsb + g.off_mxflag);
             mf.ranges = (int*)(wsb + g.off_mxrange);
-            e = launch_mx(false, dp, b, kf, mf, kf.saved_flag, true, g.mx_lds, st);
+            e = launch_mx(false, dp, b, kf, mf, kf.saved_flag, nullptr, true, g.mx_lds, st);
             if (e == hipSuccess) {
                 KArgs kb = ka;
                 kb.saved_in = kf.saved;
                 kb.saved_flag = kf.saved_flag;
-                e = launch_mx(true, dp, b, kb, mf, nullptr, false, g.mx_lds, st);
+                e = launch_mx(true, dp, b, kb, mf, nullptr, nullptr, false, g.mx_lds, st);
             }
         }
         if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -875,6 +902,13 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
             if (e != hipSuccess) return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(e));
         }
         return STL_OK;
+    }
+    if (saved == 1 && mx_applies(plan->dev, bt, nullptr, false)) {
+        // the buffer has the matrix-core layout: its tables and the backward's
+        // list counters must be valid whichever path this forward takes
+        if (launch_mx_tables(plan->dev, b, params, (MxTab*)((char*)d_saved + saved_tables_offset(plan, bt)),
+                             (int*)((char*)d_saved + saved_counters_offset(plan, bt)), st) != hipSuccess)
+            return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
     if (saved) {
         int* flags = (int*)d_saved;

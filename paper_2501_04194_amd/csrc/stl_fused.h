@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(256) stl_mask_tables(DevPlan plan, const float
                                                        int* counters)
 {
     __shared__ TabShared sh;
-    if (blockIdx.x == 0 && threadIdx.x < 2) counters[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 3) counters[threadIdx.x] = 0;
     const DevPlan& P = plan;
     const int m = blockIdx.x;
     const Instr& I = P.ins[P.fused.ins[m]];

@@ -1758,7 +1758,7 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
     bool first = true;
     while (next_item(ka, sh, item, first)) {
         first = false;
-        const int64_t nitems = ka.list_mode ? (int64_t)*ka.list_count : bt.B;
+        const int64_t nitems = ka.list_mode ? min(max((int64_t)*ka.list_count, (int64_t)0), bt.B) : bt.B;
         if (item >= nitems) break;
         const int64_t b = ka.list_mode ? (int64_t)ka.list[item] : (bt.order ? (int64_t)bt.order[item] : item);
         const int64_t off = bt.offsets ? bt.offsets[b] : b * bt.T;
@@ -1827,6 +1827,17 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
             __syncthreads();
         }
     }
+    if (ka.list_mode) {
+        // the last work-group out clears the item counter, the list count and
+        // this ticket, so that the next call through the same counters starts
+        // from zero without a clearing kernel
+        __syncthreads();
+        if (threadIdx.x == 0 && atomicAdd(ka.counter + 2, 1) == (int)gridDim.x - 1) {
+            ka.counter[0] = 0;
+            ka.counter[1] = 0;
+            ka.counter[2] = 0;
+        }
+    }
 }
 
 // One work-group per parameter p: d/dp is the sum, over the per-trajectory
@@ -1867,7 +1878,7 @@ __global__ void __launch_bounds__(1024) stl_reduce_params(const float* part, int
     if (tid == 0) gp[p] = red[0];
 }
 
-__global__ void stl_zero_counter(int* c) { if (threadIdx.x < 2) c[threadIdx.x] = 0; }
+__global__ void stl_zero_counter(int* c) { if (threadIdx.x < 3) c[threadIdx.x] = 0; }
 
 __global__ void stl_fill_int(int* p, int64_t n, int v)
 {
@@ -2032,16 +2043,25 @@ hipError_t set_max_lds_mx(size_t bytes)
 
 static bool al16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
 
-// tables (saved_flag: marked valid for a saving forward, else NULL), then
+// tables (saved_flag: marked valid for a saving forward, else NULL;
+// counters2: a second counter triple to clear, else NULL), then
 // the forward or backward kernel over groups of 16 trajectories.  The
 // 16-byte load / store variants need T a multiple of 4 and 16-byte aligned
 // arrays (x; forward: root and saved values; backward: G, saved values, dx).
+hipError_t launch_mx_tables(const DevPlan& plan, const Batch& bt, const float* params, MxTab* tabs, int* counters2,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(stl_mx_tables, dim3(NKMAX, plan.fused.n), dim3(256), 0, s, plan, params, (int)bt.T, tabs,
+                       (int*)nullptr, counters2, (int*)nullptr, (int*)nullptr, bt.B);
+    return hipGetLastError();
+}
+
 hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs& ka, const MxArgs& mx,
-                     int* table_saved_flag, bool tables, size_t lds, hipStream_t s)
+                     int* table_saved_flag, int* counters2, bool tables, size_t lds, hipStream_t s)
 {
     if (tables) {
         hipLaunchKernelGGL(stl_mx_tables, dim3(NKMAX, plan.fused.n), dim3(256), 0, s, plan, ka.params, (int)bt.T,
-                           (MxTab*)mx.tabs, ka.counter, mx.handed, table_saved_flag, bt.B);
+                           (MxTab*)mx.tabs, ka.counter, counters2, mx.handed, table_saved_flag, bt.B);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -142,19 +142,24 @@ DEV float half_min(float v) { return -half_max(-v); }
 // core).  The work-groups also clear the hand-off flags (and, for a saving
 // forward, mark every trajectory's saved traces valid with the value 2:
 // traces written by this path, with their exponent ranges; the fp64 fused
-// kernels write 1 and no ranges); work-group (0, 0) resets the two counters.
+// kernels write 1 and no ranges); work-group (0, 0) resets the counters
+// (and those a saving forward keeps for the backward).  handed, counters
+// and saved_flag may be NULL (a saving forward that takes another path
+// still writes the tables and clears the backward's counters).
 __global__ void __launch_bounds__(256) stl_mx_tables(DevPlan plan, const float* params, int L, MxTab* tabs,
-                                                     int* counters, int* handed, int* saved_flag, int64_t B)
+                                                     int* counters, int* counters2, int* handed, int* saved_flag,
+                                                     int64_t B)
 {
     __shared__ TabShared sh;
     const int tid = threadIdx.x;
     const int s = blockIdx.x, m = blockIdx.y;
     const int flat = m * gridDim.x + s, nblk = gridDim.x * gridDim.y;
     for (int64_t b = (int64_t)flat * blockDim.x + tid; b < B; b += (int64_t)nblk * blockDim.x) {
-        handed[b] = 0;
+        if (handed) handed[b] = 0;
         if (saved_flag) saved_flag[b] = 2;
     }
-    if (flat == 0 && tid < 2) counters[tid] = 0;
+    if (flat == 0 && counters && tid < 3) counters[tid] = 0;
+    if (flat == 0 && counters2 && tid < 3) counters2[tid] = 0;
     const Instr& I = plan.ins[plan.fused.ins[m]];
     MxTab& T = tabs[m];
     const MaskInfo mi = mask_info(params, I, L, sh, nullptr, nullptr, nullptr);
@@ -237,9 +242,14 @@ struct MxShared {
     float pp[MX_MAXN][2][2][MXG];       // backward: d/da, d/db partials per matrix wave
 };
 
-DEV void mx_handoff(const KArgs& ka, const MxArgs& mx, int64_t b)
+// (the list index is checked against B: a counter that was not cleared must
+// not turn into a write out of bounds)
+DEV void mx_handoff(const KArgs& ka, const MxArgs& mx, int64_t b, int64_t B)
 {
-    if (atomicExch(&mx.handed[b], 1) == 0) ka.list[atomicAdd(ka.list_count, 1)] = (int)b;
+    if (atomicExch(&mx.handed[b], 1) == 0) {
+        const int i = atomicAdd(ka.list_count, 1);
+        if (i >= 0 && i < B) ka.list[i] = (int)b;
+    }
     if (ka.saved_flag) ka.saved_flag[b] = 0;
 }
 
@@ -457,7 +467,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     for (int mm = 0; mm < N; ++mm) ok = ok && mx.tabs[mm].ok;
     if (!ok) {
         // the masks do not fit the matrix-core path: the generic executor takes every trajectory
-        if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
+        if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid, bt.B);
         return;
     }
     if (tid < MXG) {
@@ -728,7 +738,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
             rp[2] = (int)sh.R[mm][r];
         }
     }
-    if (tid < MXG && sh.frag[tid] && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
+    if (tid < MXG && sh.frag[tid] && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid, bt.B);
 }
 
 // Backward, with the forward's two roles: matrix waves (2 per mask) compute
@@ -747,11 +757,14 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int L = (int)bt.T;
     const int64_t g0 = (int64_t)blockIdx.x * MXG;
+    // this group's hand-off flags (no other work-group touches them), when
+    // no tables kernel ran before this kernel in the same call
+    if (mx.own_flags && tid < MXG && g0 + tid < bt.B) mx.handed[g0 + tid] = 0;
     bool ok = true;
 #pragma unroll
     for (int mm = 0; mm < N; ++mm) ok = ok && mx.tabs[mm].ok;
     if (!ok) {
-        if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
+        if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid, bt.B);
         return;
     }
     // ---- per mask: the list of derivative tiles (K-step, kind)
@@ -762,7 +775,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         const MxTab& T = mx.tabs[tid];
         int nd = 0;
         bool over = false;
-        for (int s = 0; s < T.NK; ++s)
+        for (int s = 0; s < min(T.NK, NKMAX); ++s)
             for (int w = 0; w < 2; ++w)
                 if ((T.fd[s] >> w) & 1) {
                     if (nd < NDMAX) {
@@ -1076,7 +1089,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
             if (slot >= 0) mx.part[(bq * P.n_masks + slot) * 2 + ab] = s;
         }
     }
-    if (tid < MXG && (sh.frag[tid] || over) && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
+    if (tid < MXG && (sh.frag[tid] || over) && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid, bt.B);
 }
 
 }  // namespace stlmi

@@ -135,6 +135,7 @@ struct MxArgs {
     int* handed;           // [B] 1 once a trajectory is on the hand-off list
     int* ranges;           // [B][n][3] floor(min), ceil(max) of O over each trajectory's trace, reference R
     float* part;           // [B][n_masks][2] d/da, d/db partials
+    int own_flags;         // backward: each work-group clears its rows' hand-off flags (no tables kernel ran)
 };
 
 }  // namespace stlmi

@@ -92,21 +92,29 @@ def test_mx_hands_off_wide_range_and_wide_masks():
 
 
 def test_mx_saved_equals_recompute_and_is_deterministic():
+    """Saved pair vs recompute, bit for bit, with two trajectories handed to
+    the generic executor; the saved backward runs twice after one forward
+    (its hand-off list counters must be back at zero for the second call)."""
     import torch
     spec, params, x = W.workload(2, B=40, T=1200)
+    x[5, 600:, 0] += 25.0
+    x[33, :200, 1] -= 20.0
     G = W.upstream_grad(9, x.shape[:2])
     g = Gpu(spec, 2, params)
     xd, Gd = torch.from_numpy(x).cuda(), torch.from_numpy(G).cuda()
     sv = g.plan.saved_buffer(xd)
     r1 = g.plan.forward(xd, g.pv, saved=sv)
     d1, p1 = g.plan.backward(xd, Gd, g.pv, saved=sv)
+    d1b, p1b = g.plan.backward(xd, Gd, g.pv, saved=sv)
     r2 = g.plan.forward(xd, g.pv)
     d2, p2 = g.plan.backward(xd, Gd, g.pv)
     d3, p3 = g.plan.backward(xd, Gd, g.pv)
     torch.cuda.synchronize()
     assert torch.equal(r1, r2)
     assert torch.equal(d1, d2) and torch.equal(p1, p2)
+    assert torch.equal(d1b, d1) and torch.equal(p1b, p1)
     assert torch.equal(d2, d3) and torch.equal(p2, p3)
+    check_formula(spec, x, params=params, what="mx saved handoff")
 
 
 def test_mx_graph_replay_matches_eager():
