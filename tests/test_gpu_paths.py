@@ -140,3 +140,28 @@ def test_interval_sweep_benchmark_size_sampled():
     sc = 1.0 / (4 * 10.0)
     assert_close(got[1], ga0, scale=sc, what="full-size sweep d/da")
     assert_close(got[2], gb0, scale=sc, what="full-size sweep d/db")
+
+
+def test_ragged_forward_with_node_traces_captures_in_a_graph():
+    """stl_forward on a ragged batch writing every node's trace ([n_nodes][N_total],
+    N_total read from offsets on the device) neither synchronises nor copies to
+    the host, so it records into a graph; three replays equal the eager call."""
+    import torch
+    spec, params, xp, off = W.ragged_workload(n=30)
+    T = int(np.diff(off).max())
+    plan = stl.Plan(spec, xp.shape[-1], params)
+    pv = torch.from_numpy(plan.param_vector()).cuda()
+    xd, od = torch.from_numpy(xp).cuda(), torch.from_numpy(off).cuda()
+    root0, nodes0 = plan.forward(xd, pv, offsets=od, T=T, node_traces=True)     # eager (sizes the workspace)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        root1, nodes1 = plan.forward(xd, pv, offsets=od, T=T, node_traces=True)
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(root1, root0), rep
+        assert torch.equal(nodes1, nodes0), rep
+        _ = (xd * 2).sum().item()                 # other eager work between replays
+    ref = oracle.forward(spec, xp, offsets=off)
+    assert_close(root1.cpu().numpy(), ref, what="captured ragged root")
