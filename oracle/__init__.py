@@ -59,7 +59,8 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
+        # STL_ORACLE_LIB: another build of stl_oracle.c (the host sanitizer test's)
+        lib = ctypes.CDLL(os.environ.get("STL_ORACLE_LIB") or build())
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         lp = ctypes.POINTER(ctypes.c_longlong)

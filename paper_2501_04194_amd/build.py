@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstlmi.so")
-SOURCES = ["stl_kernels.hip", "stl_api.cpp", "mlp_kernels.hip"]
+SOURCES = ["stl_kernels.hip", "stl_api.cpp", "stl_compile.cpp", "mlp_kernels.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -72,37 +72,49 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise StlError("libstlmi.so is not built: run paper_2501_04194_amd/build.py (or __graft_entry__.build())")
-    L = ctypes.CDLL(LIB_PATH)
-    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
-    L.stl_compile.argtypes = [ctypes.POINTER(Node), i32, ctypes.POINTER(i32), i32, i32, ctypes.POINTER(Pred), i32,
-                              i32, i32, ctypes.c_float, ctypes.c_float, ctypes.POINTER(vp)]
-    L.stl_plan_destroy.argtypes = [vp]
-    L.stl_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
-    L.stl_workspace_size.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Launch), ctypes.POINTER(sz),
-                                     ctypes.POINTER(sz)]
-    L.stl_forward.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, sz, ctypes.POINTER(Launch), vp]
-    L.stl_backward.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, sz, ctypes.POINTER(Launch), vp]
-    L.stl_saved_size.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(sz)]
-    L.stl_forward_saving.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, sz, vp, sz, ctypes.POINTER(Launch), vp]
-    L.stl_backward_saved.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, sz, vp, vp, vp, vp, sz,
-                                     ctypes.POINTER(Launch), vp]
-    L.stl_forward_static.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, ctypes.POINTER(Launch), vp]
-    L.stl_last_error.restype = ctypes.c_char_p
-    L.stl_lpt_order.argtypes = [ctypes.POINTER(i64), i64, ctypes.POINTER(i32)]
-    L.stl_autotune.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(Launch),
-                               ctypes.POINTER(ctypes.c_float)]
-    L.stl_graph_capture.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, vp, sz, ctypes.POINTER(Launch),
-                                    vp, ctypes.POINTER(vp)]
-    L.stl_graph_launch.argtypes = [vp, vp]
-    L.stl_graph_destroy.argtypes = [vp]
-    L.stl_interval_sweep.argtypes = [ctypes.POINTER(IntervalDesc), vp, i64, i64, vp, vp, i64, vp, vp, vp, vp]
-    f32 = ctypes.c_float
-    L.stl_pstl_descent.argtypes = [ctypes.POINTER(IntervalDesc), vp, i64, i64, f32, f32, f32, f32, i32, f32, f32, vp,
-                                   vp, vp]
-    for f in EXPORTS:
-        if f != "stl_last_error":
-            getattr(L, f).restype = ctypes.c_int
+    L = _bind(ctypes.CDLL(LIB_PATH))
     _lib = L
+    return L
+
+
+def _signatures():
+    vp, i32, i64, sz, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_float
+    B, La = ctypes.POINTER(Batch), ctypes.POINTER(Launch)
+    return {
+        "stl_compile": [ctypes.POINTER(Node), i32, ctypes.POINTER(i32), i32, i32, ctypes.POINTER(Pred), i32, i32, i32,
+                        f32, f32, ctypes.POINTER(vp)],
+        "stl_plan_destroy": [vp],
+        "stl_plan_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "stl_workspace_size": [vp, B, La, ctypes.POINTER(sz), ctypes.POINTER(sz)],
+        "stl_forward": [vp, B, vp, vp, vp, vp, sz, La, vp],
+        "stl_backward": [vp, B, vp, vp, vp, vp, vp, sz, La, vp],
+        "stl_saved_size": [vp, B, ctypes.POINTER(sz)],
+        "stl_forward_saving": [vp, B, vp, vp, vp, sz, vp, sz, La, vp],
+        "stl_backward_saved": [vp, B, vp, vp, sz, vp, vp, vp, vp, sz, La, vp],
+        "stl_forward_static": [vp, B, vp, vp, vp, La, vp],
+        "stl_last_error": [],
+        "stl_lpt_order": [ctypes.POINTER(i64), i64, ctypes.POINTER(i32)],
+        "stl_autotune": [vp, B, vp, vp, vp, vp, vp, vp, sz, vp, La, ctypes.POINTER(f32)],
+        "stl_graph_capture": [vp, B, vp, vp, vp, vp, vp, vp, sz, La, vp, ctypes.POINTER(vp)],
+        "stl_graph_launch": [vp, vp],
+        "stl_graph_destroy": [vp],
+        "stl_interval_sweep": [ctypes.POINTER(IntervalDesc), vp, i64, i64, vp, vp, i64, vp, vp, vp, vp],
+        "stl_pstl_descent": [ctypes.POINTER(IntervalDesc), vp, i64, i64, f32, f32, f32, f32, i32, f32, f32, vp, vp,
+                             vp],
+    }
+
+
+def _bind(L):
+    """Argument and result types of the entry points L exports: every one of
+    EXPORTS for libstlmi.so; a library with a subset of them (a host-only
+    build of the plan compiler) gets those it has."""
+    for name, args in _signatures().items():
+        try:
+            f = getattr(L, name)
+        except AttributeError:
+            continue
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name == "stl_last_error" else ctypes.c_int
     return L
 
 
