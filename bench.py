@@ -407,6 +407,29 @@ def bench_planning(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_warmstart(args):
+    """Learned warm start for STL trajectory optimisation (Sec. VII-A form):
+    50,000 training problems solved by plain gradient ascent on the smooth
+    robustness, a BF16 MLP (4-256-256-400) trained on their solutions, then
+    1,000 held-out problems solved from the straight line (plain) and from
+    the MLP's proposal (learned, inference included in the timed region)."""
+    from paper_2501_04194_amd import warmstart as WS
+    res = WS.experiment(n_train=50_000, n_test=1000, epochs=30, log=lambda *a: None)
+    lp, ll = res["plain"], res["learned"]
+    out = {"metric": "time to plain ascent's solved count, 1,000 held-out problems (learned warm start)",
+           "value": ll["s_to_plain_solved"], "unit": "s", "n_gpus": 1, "steps": res["max_steps"], "warmup": 1,
+           "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "warmstart_reach_avoid_T200_train50000", "n_train_problems": res["n_train_problems"],
+                      "n_test": res["n_test"], "T": res["T"], "max_steps": res["max_steps"],
+                      "mlp": "4-256-256-400 bf16, fp32 master weights, Adam", "epochs": 30},
+           "result": {"plain": lp, "learned": ll, "speedup_to_plain_solved": lp["s_to_plain_solved"] /
+                      max(ll["s_to_plain_solved"], 1e-9), "datagen_s": res["datagen_s"], "train_s": res["train_s"],
+                      "train_solved_frac": res["train_solved_frac"]},
+           "roofline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,7 +442,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer three times (the reference kernel for HBM counters)")
     ap.add_argument("--workload", default="smooth_mask", choices=["smooth_mask", "smooth_until", "ragged", "intervals", "table2", "mining",
-                             "planning"],
+                             "planning", "warmstart"],
                     help="smooth_mask: the headline workload; the others are secondary measurements")
     ap.add_argument("--interval-batch", type=int, default=1, help="signals per interval sweep (--workload intervals)")
     ap.add_argument("--oracle-child", type=int, default=0, help=argparse.SUPPRESS)
@@ -446,6 +469,8 @@ def main():
         return bench_mining(args)
     if args.workload == "planning":
         return bench_planning(args)
+    if args.workload == "warmstart":
+        return bench_warmstart(args)
     if args.workload != "smooth_mask":
         return bench_graph(args)
 

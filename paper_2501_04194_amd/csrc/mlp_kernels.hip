@@ -1,5 +1,5 @@
 // Learned warm-start kernels for gfx950: BF16 matrix product on the matrix
-// cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation) with a fused
+// cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation) with a fused
 // bias/ReLU epilogue, BF16 rounding, ReLU derivative mask, column sums, MSE
 // gradient, Adam and the trajectory gradient-ascent step.  C ABI in
 // include/stlmi_mlp.h.
@@ -17,7 +17,6 @@ namespace stlmi_mlp {
 
 #define DEV static __device__ __forceinline__
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // float -> bf16, round to nearest even on the 16 dropped mantissa bits
@@ -31,53 +30,89 @@ DEV uint16_t f2bf(float f)
 
 DEV float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TM = 64, TN = 64, TK = 32;
+constexpr int LDK = TK + 8;     // LDS row: 32 k-values and 8 of pad (rows 80 bytes apart fall on distinct banks)
 
-// C[M,N] = act(A[M,K] B[K,N] + bias); work-group tile 64x64, four waves of
-// 32x32 (2x2 MFMA blocks of 16x16), K in steps of 16 through LDS.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// 8 elements p[0], p[s], .., p[7 s] of which the first nvalid exist (zeros
+// after them); one 16-byte load when vec (s = 1, nvalid = 8, aligned)
+DEV void load8(const uint16_t* p, int64_t s, int nvalid, bool vec, uint16_t* v)
+{
+    if (vec) {
+        const uint4 u = *(const uint4*)p;
+        __builtin_memcpy(v, &u, 16);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = i < nvalid ? p[i * s] : (uint16_t)0;
+    }
+}
+
+DEV bool al16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
+
+// C[M,N] = act(A[M,K] B[K,N] + bias) on v_mfma_f32_16x16x32_bf16.  Work-group
+// tile 64x64, four waves of 32x32 (2x2 blocks of 16x16), K in steps of 32.
+// LDS holds A as [m][k] and B as [n][k] (k contiguous), so each lane's MFMA
+// operand (row or column l % 16, k = 8 (l / 16) .. + 7) is one 16-byte read.
+// Each of the 256 threads stages 8 consecutive elements of A and of B along
+// the dimension that is contiguous in memory (one 16-byte load when aligned
+// and in range); any strides work, transposed operands included.
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(const uint16_t* A, int64_t sam, int64_t sak,
                                                         const uint16_t* B, int64_t sbk, int64_t sbn, int M, int N,
                                                         int K, const float* bias, int relu, float* c32,
                                                         int64_t ldc32, int beta32, uint16_t* c16, int64_t ldc16)
 {
-    __shared__ uint16_t As[TM][TK + 4];
-    __shared__ uint16_t Bs[TK][TN + 4];
+    __shared__ __align__(16) uint16_t As[TM][LDK];
+    __shared__ __align__(16) uint16_t Bs[TN][LDK];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    const bool a_k = sak == 1;      // A rows contiguous in k (else chunks run along m)
+    const bool b_k = sbk == 1;      // B columns contiguous in k (else chunks run along n)
     float4_t acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += TK) {
-        for (int e = tid; e < TM * TK; e += 256) {
-            const int r = e / TK, c = e % TK, gm = m0 + r, gk = k0 + c;
-            As[r][c] = (gm < M && gk < K) ? A[(int64_t)gm * sam + (int64_t)gk * sak] : (uint16_t)0;
+        uint16_t v[8];
+        if (a_k) {
+            const int r = tid >> 2, kk = (tid & 3) * 8, gm = m0 + r, gk = k0 + kk;
+            const int nv = gm < M ? max(0, min(8, K - gk)) : 0;
+            const uint16_t* p = A + (int64_t)min(gm, M - 1) * sam + (int64_t)gk;
+            load8(p, 1, nv, nv == 8 && al16(p), v);
+            *(uint4*)&As[r][kk] = *(const uint4*)v;
+        } else {
+            const int kk = tid >> 3, m8 = (tid & 7) * 8, gm = m0 + m8, gk = k0 + kk;
+            const int nv = gk < K ? max(0, min(8, M - gm)) : 0;
+            const uint16_t* p = A + (int64_t)gm * sam + (int64_t)min(gk, K - 1) * sak;
+            load8(p, sam, nv, sam == 1 && nv == 8 && al16(p), v);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[m8 + i][kk] = v[i];
         }
-        for (int e = tid; e < TK * TN; e += 256) {
-            const int r = e / TN, c = e % TN, gk = k0 + r, gn = n0 + c;
-            Bs[r][c] = (gk < K && gn < N) ? B[(int64_t)gk * sbk + (int64_t)gn * sbn] : (uint16_t)0;
+        if (b_k) {
+            const int n = tid >> 2, kk = (tid & 3) * 8, gn = n0 + n, gk = k0 + kk;
+            const int nv = gn < N ? max(0, min(8, K - gk)) : 0;
+            const uint16_t* p = B + (int64_t)gk + (int64_t)min(gn, N - 1) * sbn;
+            load8(p, 1, nv, nv == 8 && al16(p), v);
+            *(uint4*)&Bs[n][kk] = *(const uint4*)v;
+        } else {
+            const int kk = tid >> 3, n8 = (tid & 7) * 8, gn = n0 + n8, gk = k0 + kk;
+            const int nv = gk < K ? max(0, min(8, N - gn)) : 0;
+            const uint16_t* p = B + (int64_t)min(gk, K - 1) * sbk + (int64_t)gn * sbn;
+            load8(p, sbn, nv, sbn == 1 && nv == 8 && al16(p), v);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[n8 + i][kk] = v[i];
         }
         __syncthreads();
-        const int kk = 4 * (lane >> 4);
+        const int kq = 8 * (lane >> 4);
+        bf16x8_t a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int row = wm + 16 * i + (lane & 15);
-            short4_t a;
-            a[0] = (short)As[row][kk + 0];
-            a[1] = (short)As[row][kk + 1];
-            a[2] = (short)As[row][kk + 2];
-            a[3] = (short)As[row][kk + 3];
+        for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8_t*)&As[wm + 16 * i + (lane & 15)][kq];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int col = wn + 16 * j + (lane & 15);
-                short4_t b;
-                b[0] = (short)Bs[kk + 0][col];
-                b[1] = (short)Bs[kk + 1][col];
-                b[2] = (short)Bs[kk + 2][col];
-                b[3] = (short)Bs[kk + 3][col];
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i][j], 0, 0, 0);
-            }
-        }
+        for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8_t*)&Bs[wn + 16 * j + (lane & 15)][kq];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
 #pragma unroll

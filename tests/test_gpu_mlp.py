@@ -134,12 +134,13 @@ def test_ascent_update_and_colsum():
 
 
 def test_warmstart_gain():
-    """On held-out problems the learned proposal needs fewer ascent steps
+    """At the configuration's size (50,000 training problems, 1,000 held out):
+    on held-out problems the learned proposal needs fewer ascent steps
     (median) than plain ascent from the straight line, solves at least as
     many problems, and reaches the number plain ascent solves within its step
     budget in less wall time (MLP inference included)."""
     from paper_2501_04194_amd import warmstart as WS
-    res = WS.experiment(n_train=20_000, n_test=1000, epochs=20, log=print)
+    res = WS.experiment(n_train=50_000, n_test=1000, epochs=30, log=print)
     print(res)
     assert res["learned"]["median_steps"] < res["plain"]["median_steps"]
     assert res["learned"]["s_to_plain_solved"] < res["plain"]["s_to_plain_solved"]
