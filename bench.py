@@ -126,6 +126,30 @@ def traffic_per_launch():
     return rec.get("bytes_per_launch")
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def until_flops(lengths, a, b):
+    """FP64 operations of the smooth Until (fp64 form) over trajectories of the
+    given lengths, forward + backward (a reciprocal counts as one operation).
+    Per output t with imax = min(b, L-1-t) offsets and n = imax - a + 1 of them
+    at or past a: forward imax+1 running-sum adds and 3 n (add, reciprocal,
+    add of the outer sum); backward: the forward again for Z, imax+1 adds for
+    the checkpoints, and the reverse sweep (3 per offset before a: the block
+    recompute of P, the phi contribution's multiply-add; 10 per offset from a
+    on: P, P+q, reciprocal, two multiplies, the suffix sum, two multiply-adds)."""
+    total = 0
+    for L in lengths:
+        t = np.arange(L, dtype=np.int64)
+        imax = np.minimum(b, L - 1 - t)
+        n = np.maximum(imax - a + 1, 0)
+        pre = np.minimum(imax + 1, a)
+        fwd = (imax + 1) + 3 * n
+        bwd = fwd + (imax + 1) + 3 * pre + 10 * n
+        total += int((fwd + bwd)[imax >= a].sum())
+    return total
+
+
 def bench_graph(args):
     """Secondary workloads through the hipGraph-captured forward + backward.
 
@@ -191,6 +215,15 @@ def bench_graph(args):
            "roofline": {"bound": "hbm", "kernel": "stl_exec_kernel (forward + backward graph)",
                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
+    # the same step against the FP64 vector peak: the smooth Until[20,200]
+    # dominates the operation count (the windows and predicates add a few
+    # tens of float32 operations per step)
+    lens = [T] * B if offsets is None else list(np.diff(offsets))
+    fl = until_flops(lens, 20, 200)
+    tf = fl / (ms * 1e-3) / 1e12
+    out["roofline_alu"] = {"bound": "alu", "kernel": "stl_exec_kernel (smooth Until, fp64 form)", "achieved": tf,
+                           "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS,
+                           "flop_per_step": fl, "flop_per_signal_step": fl / n_steps}
     if not args.no_cpu_baseline:
         oracle.build()
         if offsets is None:
@@ -324,6 +357,18 @@ def bench_table2(args):
             f = timed(lambda: plan.forward(x, pv))
             fb = timed(lambda: (plan.forward(x, pv), plan.backward(x, G, pv)))
             sweep[name][T] = {"fwd_ms": round(f, 4), "fwd_bwd_ms": round(fb, 4)}
+    # the hard forms too (min/max; the unbounded Until of phi_3 is a linear-time clamp-map scan)
+    sweep_hard = {}
+    for name, spec in W.table2_formulas(smooth=False).items():
+        plan = stl.Plan(spec, 2)
+        pv = torch.from_numpy(plan.param_vector()).to(dev)
+        sweep_hard[name] = {}
+        for T in Ts:
+            x = torch.from_numpy(W.random_walks(60 + T, B, T, 2, 0.1)).to(dev)
+            G = torch.from_numpy(W.upstream_grad(61 + T, (B, T))).to(dev)
+            f = timed(lambda: plan.forward(x, pv))
+            fb = timed(lambda: (plan.forward(x, pv), plan.backward(x, G, pv)))
+            sweep_hard[name][T] = {"fwd_ms": round(f, 4), "fwd_bwd_ms": round(fb, 4)}
     rates = sorted(B * 512 / (sweep[n][512]["fwd_bwd_ms"] * 1e-3) for n in forms)
     out = {"metric": "fwd+bwd signal-steps/s, median over the Table II formulas (B=8, T=512)",
            "value": rates[len(rates) // 2], "unit": "signal-steps/s", "n_gpus": 1, "steps": n_rep, "warmup": 3,
@@ -331,7 +376,7 @@ def bench_table2(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "table2_suite_B8", "B": B, "T": Ts, "beta": 10.0,
                       "interval": list(W.TABLE2_INTERVAL)},
-           "sweep": sweep}
+           "sweep": sweep, "sweep_hard": sweep_hard}
     if not args.no_cpu_baseline:
         import oracle
         oracle.build()

@@ -839,6 +839,106 @@ DEV void until_hard(const Env& e, int a, int b, const float* phi, const float* p
     }
 }
 
+// Hard Until with an unbounded interval [a, inf), O(L) per trajectory.
+// With m_a(t) = min of phi over [t, t+a-1] (a > 0) and the a = 0 form
+//   U(s) = max_{j >= 0} min(min_{k <= j} phi_{s+k}, psi_{s+j}),
+// out(t) = min(m_a(t), U(t+a)).  U satisfies U(s) = f_s(U(s+1)), U(L) = -inf,
+// for the clamp map f_s(u) = min(phi_s, max(psi_s, u)) = clamp of u to
+// [min(psi_s, phi_s), phi_s]; clamp maps compose into clamp maps, so U is a
+// suffix scan of compositions.  The adjoint follows the same ties as the
+// walk of until_hard (lowest index, phi wins): output s decides at phi_s
+// (phi_s <= psi_s, or psi_s < phi_s <= U(s+1)), at psi_s (U(s+1) <= psi_s
+// < phi_s), or passes its adjoint to output s+1 (psi_s < U(s+1) < phi_s); an
+// output t goes to the window argmin of m_a when m_a(t) <= U(t+a).  The
+// passed-on sums F(s) = h(s) + [s-1 passes] F(s-1) are a scan of affine
+// maps; the window part is the hard window's adjoint.  Scratch units 0..15.
+struct ClampMap {
+    float lo, hi;   // u -> min(hi, max(lo, u)), lo <= hi
+};
+struct OpClamp {    // a after b
+    __device__ __forceinline__ ClampMap operator()(ClampMap a, ClampMap b) const
+    {
+        auto f = [&](float x) { return x < a.lo ? a.lo : (x > a.hi ? a.hi : x); };
+        return ClampMap{f(b.lo), f(b.hi)};
+    }
+};
+struct Affine {
+    float h;        // x -> h + c x, c in {0, 1}
+    int c;
+};
+struct OpAffine {   // l then r
+    __device__ __forceinline__ Affine operator()(Affine l, Affine r) const
+    {
+        return Affine{r.c ? r.h + l.h : r.h, l.c & r.c};
+    }
+};
+enum { UH_PHI = 0, UH_PSI = 1, UH_PASS = 2 };
+
+DEV void until_hard_unb(const Env& e, int a, const float* phi, const float* psi, float* out, const float* g,
+                        float* gphi, float* gpsi)
+{
+    const int L = e.L;
+    const float rho_pad = e.P->rho_pad;
+    float* mA = S(e, 4);
+    int* jA = (int*)S(e, 5);
+    ClampMap* cm = (ClampMap*)S(e, 6);      // units 6, 7
+    if (a > 0) win_hard(e, phi, mA, jA, -1.f, 0, a - 1, PAD_NEUTRAL, 0.f, (VI*)S(e, 0), (VI*)S(e, 2));
+    for (int s = threadIdx.x; s < L; s += blockDim.x) cm[s] = ClampMap{phi[s] <= psi[s] ? phi[s] : psi[s], phi[s]};
+    __syncthreads();
+    seg_scan(cm, L, 0, true, ClampMap{-INFINITY, INFINITY}, OpClamp(), *e.sh);     // cm[s].lo = U(s)
+    if (!g) {
+        for (int t = threadIdx.x; t < L; t += blockDim.x) {
+            float v = -rho_pad;
+            if (t + a <= L - 1) {
+                const float u = cm[t + a].lo;
+                v = (a > 0 && mA[t] <= u) ? mA[t] : u;
+            }
+            out[t] = v;
+        }
+        __syncthreads();
+        return;
+    }
+    int* code = (int*)S(e, 8);
+    Affine* fa = (Affine*)S(e, 9);          // units 9, 10
+    float* gw = S(e, 11);                   // adjoint sent to the window argmin of m_a
+    for (int s = threadIdx.x; s < L; s += blockDim.x) {
+        const float un = s + 1 < L ? cm[s + 1].lo : -INFINITY;
+        int c = UH_PHI;
+        if (!(phi[s] <= psi[s])) {
+            const float w = phi[s] <= un ? phi[s] : un;
+            c = w > psi[s] ? (phi[s] <= un ? UH_PHI : UH_PASS) : UH_PSI;
+        }
+        code[s] = c;
+        // output t = s: to the window argmin, or to U(s + a)
+        float gt = 0.f;
+        bool win = false;
+        if (s + a <= L - 1) {
+            gt = g[s];
+            win = a > 0 && mA[s] <= cm[s + a].lo;
+        }
+        gw[s] = win ? gt : 0.f;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < L; s += blockDim.x) {
+        const int t = s - a;
+        const float h = (t >= 0 && !(a > 0 && mA[t] <= cm[s].lo)) ? g[t] : 0.f;
+        fa[s] = Affine{h, s > 0 && code[s - 1] == UH_PASS ? 1 : 0};
+    }
+    __syncthreads();
+    seg_scan(fa, L, 0, false, Affine{0.f, 1}, OpAffine(), *e.sh);                 // fa[s].h = F(s)
+    for (int s = threadIdx.x; s < L; s += blockDim.x) {
+        if (code[s] == UH_PHI) gphi[s] += fa[s].h;
+        else if (code[s] == UH_PSI) gpsi[s] += fa[s].h;
+    }
+    __syncthreads();
+    if (a > 0) {
+        float* gu = S(e, 15);
+        win_hard_adj(e, gw, gu, jA, (double*)S(e, 12));                          // units 12..14
+        for (int j = threadIdx.x; j < L; j += blockDim.x) gphi[j] += gu[j];
+        __syncthreads();
+    }
+}
+
 // Smooth Until forward, one thread per output t:
 //   P_i = sum_{k<=i} 2^{-z_phi(t+k)}   (running scaled sum: smooth min of phi)
 //   Y_i = 1 / (P_i + 2^{-z_psi(t+i)})  (= exp(beta * smin(R_i, psi_{t+i})))
@@ -1410,7 +1510,8 @@ DEV void exec_fwd(const Env& e, const Instr& I, bool bwdmap)
             w = wt;
         }
         if (!is_smooth(I)) {
-            until_hard(e, ua, ub, phi, psi, out, nullptr, nullptr, nullptr, nullptr);
+            if (ub < 0 && I.mask < 0) until_hard_unb(e, ua, phi, psi, out, nullptr, nullptr, nullptr);
+            else until_hard(e, ua, ub, phi, psi, out, nullptr, nullptr, nullptr, nullptr);
         } else {
             const float bl = pbeta(e, I) * LOG2E;
             int M;
@@ -1682,7 +1783,8 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
         if (none) {
             // empty support: constant output
         } else if (!is_smooth(I)) {
-            until_hard(e, ua, ub, phi, psi, nullptr, g, gphi, gpsi, (int*)S(e, 0));
+            if (ub < 0 && I.mask < 0) until_hard_unb(e, ua, phi, psi, nullptr, g, gphi, gpsi);
+            else until_hard(e, ua, ub, phi, psi, nullptr, g, gphi, gpsi, (int*)S(e, 0));
         } else {
             const float bl = pbeta(e, I) * LOG2E;
             const int bmax = ub < 0 ? L - 1 : min(ub, L - 1);

@@ -412,3 +412,27 @@ def test_softmax_unsupported_forms():
                   "mask": {"a": 1.0, "b": 5.0, "c": 1.0, "eps": 1e-6}}, 1)
     with pytest.raises(stl.StlError, match="softmax"):
         stl.Plan({"op": "until", "a": 0, "b": 3, "smooth": "softmax", "beta": 1.0, "left": S1, "right": S1}, 1)
+
+
+@pytest.mark.parametrize("a", [0, 1, 5, 37, 299, 300])
+def test_hard_until_unbounded_scan_with_ties(a):
+    """Unbounded hard Until (the clamp-map scan, O(L)) on signals quantised to
+    a few levels (many ties between phi and psi, inside the running min and
+    inside the a-window): bit-exact root against the oracle, and the same
+    root and the same d/dx bits as the bounded walk with b = L - 1 (which
+    covers the whole signal); a = 300 = L leaves every window empty; L = 1."""
+    rng = np.random.default_rng(40 + a)
+    x = np.round(walk(rng, 5, 300, D=2, s=0.4) * 2.0) / 2.0
+    x = x.astype(np.float32)
+    phi = {"op": "linear", "w": [1, 0], "c": 0.0}
+    psi = {"op": "linear", "w": [0, 1], "c": 0.0}
+    spec = {"op": "until", "a": a, "b": None, "left": phi, "right": psi}
+    G = np.round(np.random.default_rng(7).normal(size=x.shape[:2]) * 4.0).astype(np.float32) / 4.0
+    check_formula(spec, x, G=G, bitexact_root=True, what="unbounded until a=%d" % a)
+    g = Gpu(spec, 2)
+    full = Gpu({"op": "until", "a": a, "b": max(a, 299), "left": phi, "right": psi}, 2)
+    assert np.array_equal(g.fwd(x), full.fwd(x))
+    d1, _ = g.bwd(x, G)
+    d2, _ = full.bwd(x, G)
+    assert np.array_equal(d1, d2)
+    check_formula(spec, x[:, :1], G=G[:, :1], bitexact_root=True, what="unbounded until L=1 a=%d" % a)
