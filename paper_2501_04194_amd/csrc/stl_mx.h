@@ -256,13 +256,13 @@ DEV void mx_handoff(const KArgs& ka, const MxArgs& mx, int64_t b, int64_t B)
 // byte offset in a ring row of the 8-position group starting at position p (p % 8 == 0)
 DEV int ring_off(int p) { return (p % MXRING) / 8 * 32; }
 
-// ring offset of position pbase + d, 0 <= d < 2 MXRING, given pr = pbase % MXRING
-DEV int ring_off2(int pr, int d)
+// byte offset in a ring row of position pr + d, for pr < MXRING and
+// 0 <= d < MXRING, both multiples of 8 (a position's two bf16 halves are 4
+// bytes, so 8-position groups of 32 bytes put position p at byte 4 p)
+DEV int ring_byte(int pr, int d)
 {
-    int q = pr + d;
-    q = q >= MXRING ? q - MXRING : q;
-    q = q >= MXRING ? q - MXRING : q;
-    return q / 8 * 32;
+    const int b = 4 * (pr + d);
+    return b >= 4 * MXRING ? b - 4 * MXRING : b;
 }
 
 // per-mask constants of the linear predicate and the exponent scale, in
@@ -595,10 +595,16 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
                 mxf4 acc[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[j] = mxf4{0.f, 0.f, 0.f, 0.f};
+                // each K-step's terms are read one step ahead of their products
+                bf16x8 eh = ld_bf16x8(ebase + ring_byte(pr, 0)), el = ld_bf16x8(ebase + ring_byte(pr, 0) + 16);
 #pragma unroll
                 for (int s = 0; s < NKMAX + 3; ++s) {
-                    const unsigned char* ep = ebase + ring_off2(pr, 32 * s);
-                    const bf16x8 eh = ld_bf16x8(ep), el = ld_bf16x8(ep + 16);
+                    bf16x8 ehn = eh, eln = el;
+                    if (s + 1 < NKMAX + 3) {
+                        const unsigned char* ep = ebase + ring_byte(pr, 32 * (s + 1));
+                        ehn = ld_bf16x8(ep);
+                        eln = ld_bf16x8(ep + 16);
+                    }
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int st = s - j;
@@ -608,6 +614,8 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
                             acc[j] = mfma(Wl[st], eh, acc[j]);
                         }
                     }
+                    eh = ehn;
+                    el = eln;
                 }
                 float4* ob = (float4*)accb + ((((k & 1) * N + m) * 2 + hh) * 4) * 64 + lane;
 #pragma unroll
@@ -938,10 +946,15 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                 mxf4 acc[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[j] = mxf4{0.f, 0.f, 0.f, 0.f};
+                bf16x8 eh = ld_bf16x8(hbase + ring_byte(pr, 0)), el = ld_bf16x8(hbase + ring_byte(pr, 0) + 16);
 #pragma unroll
                 for (int s = 0; s < NKMAX + 3; ++s) {
-                    const unsigned char* ep = hbase + ring_off2(pr, 32 * s);
-                    const bf16x8 eh = ld_bf16x8(ep), el = ld_bf16x8(ep + 16);
+                    bf16x8 ehn = eh, eln = el;
+                    if (s + 1 < NKMAX + 3) {
+                        const unsigned char* ep = hbase + ring_byte(pr, 32 * (s + 1));
+                        ehn = ld_bf16x8(ep);
+                        eln = ld_bf16x8(ep + 16);
+                    }
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int st = s - j;
@@ -951,6 +964,8 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                             acc[j] = mfma(Wl[st], eh, acc[j]);
                         }
                     }
+                    eh = ehn;
+                    el = eln;
                 }
                 // 2^{z_j + Q} = f 2^n at this lane's outputs (the products below are
                 // moderate even where the factors are not); f = 0 where j is not an output
@@ -979,19 +994,29 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                 }
                 // derivative sums: K-step dst[d] of every tile, added straight
                 // into this lane's d/da, d/db partials
+                // (the terms of each product are read one product ahead)
+                bf16x8 dh = ld_bf16x8(hbase + ring_byte(pr, 32 * dst[0])),
+                       dl = ld_bf16x8(hbase + ring_byte(pr, 32 * dst[0]) + 16);
 #pragma unroll
                 for (int d = 0; d < NDMAX; ++d) {
                     const bf16x8 Dh = ld_bf16x8(dl_m + d * 128), Dl = ld_bf16x8(dl_m + d * 128 + 64);
                     float sum = 0.f;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const unsigned char* ep = hbase + ring_off2(pr, 32 * (dst[d] + j));
-                        const bf16x8 eh = ld_bf16x8(ep), el = ld_bf16x8(ep + 16);
-                        mxf4 a = mfma(Dh, eh, mxf4{0.f, 0.f, 0.f, 0.f});
-                        a = mfma(Dh, el, a);
-                        a = mfma(Dl, eh, a);
+                        bf16x8 dhn = dh, dln = dl;
+                        if (d * 4 + j + 1 < NDMAX * 4) {
+                            const int dn = j < 3 ? d : d + 1, jn = j < 3 ? j + 1 : 0;
+                            const unsigned char* ep = hbase + ring_byte(pr, 32 * (dst[dn] + jn));
+                            dhn = ld_bf16x8(ep);
+                            dln = ld_bf16x8(ep + 16);
+                        }
+                        mxf4 a = mfma(Dh, dh, mxf4{0.f, 0.f, 0.f, 0.f});
+                        a = mfma(Dh, dl, a);
+                        a = mfma(Dl, dh, a);
 #pragma unroll
                         for (int q = 0; q < 4; ++q) sum += ldexpf(a[q] * fj[j][q], nj[j][q]);
+                        dh = dhn;
+                        dl = dln;
                     }
                     pam += isb[d] ? 0.f : sum;
                     pbm += isb[d] ? sum : 0.f;
