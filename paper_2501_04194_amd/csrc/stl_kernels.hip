@@ -2116,12 +2116,10 @@ hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& pla
 size_t mx_tab_bytes() { return sizeof(MxTab); }
 
 // dynamic LDS of the matrix-core kernels: the rings (n masks x 16 rows), the
-// result buffers, and the forward's lo weight tiles or the backward's
-// derivative tiles
+// result buffers, and the backward's derivative tiles
 size_t mx_lds_bytes(int n, int D, bool bwd)
 {
-    return (size_t)n * MXG * MXRS + mx_xch_bytes(n, D, bwd) +
-           (bwd ? (size_t)n * NDMAX * 2 * 64 * 16 : (size_t)n * NKMAX * 64 * 16);
+    return (size_t)n * MXG * MXRS + mx_xch_bytes(n, D, bwd) + (bwd ? (size_t)n * NDMAX * 2 * 64 * 16 : 0);
 }
 size_t mx_static_lds() { return sizeof(MxShared); }
 
@@ -2167,7 +2165,8 @@ hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const dim3 grid((unsigned)((bt.B + MXG - 1) / MXG)), block(256 * plan.fused.n);
+    // (forward: 2n matrix and 4n staging waves; backward: 2n of each)
+    const dim3 grid((unsigned)((bt.B + MXG - 1) / MXG)), block((bwd ? 256 : 384) * plan.fused.n);
     const bool d2 = bt.D == 2;
     const bool vec = bt.T % 4 == 0 && bt.T >= 4 && al16(bt.x) &&
                      (bwd ? al16(ka.G) && al16(ka.saved_in) && al16(ka.dx) : al16(ka.root) && al16(ka.saved));

@@ -416,23 +416,22 @@ constexpr size_t mx_xch_bytes(int n, int D, bool bwd)
 }
 
 // the root (the smooth And/Or of the mask traces) and log2 of the softmax
-// weight of every child
+// weight of every child, from su_k = sg * trace_k (sg = -1 for a smooth
+// And).  With two children the larger weight's term is exactly 1, so the
+// sum takes one exponential.
 template <int N>
-DEV float mx_root_lws(const MxRoot& R, const float* v, float* lw)
+DEV float mx_root_lws(const MxRoot& R, const float* su, float* lw)
 {
-    if (N == 1 && !R.nary) {
+    static_assert(N == 1 || N == 2, "one or two masks under the root");
+    if (N == 1) {
+        // (an n-ary root of one child: its weight is 1 and the root is the trace)
         lw[0] = 0.f;
-        return v[0];
+        return R.sg * su[0];
     }
-    float m = -INFINITY;
+    const float m = fmaxf(su[0], su[N - 1]);
+    const float ls = lg2(1.f + ex2(-fabsf(su[0] - su[N - 1]) * R.bl));
 #pragma unroll
-    for (int k = 0; k < N; ++k) m = fmaxf(m, R.sg * v[k]);
-    float s = 0.f;
-#pragma unroll
-    for (int k = 0; k < N; ++k) s += ex2((R.sg * v[k] - m) * R.bl);
-    const float ls = lg2(s);
-#pragma unroll
-    for (int k = 0; k < N; ++k) lw[k] = (R.sg * v[k] - m) * R.bl - ls;
+    for (int k = 0; k < N; ++k) lw[k] = (su[k] - m) * R.bl - ls;
     return R.sg * (m + ls * R.ibl);
 }
 
@@ -440,16 +439,18 @@ DEV float mx_root_lws(const MxRoot& R, const float* v, float* lw)
 // - lg2(S) per mask and output (saved), plus each trajectory's range of O
 // and its reference R.
 //
-// The work-group's 4N waves take two roles, one wave of each per SIMD, one
-// round apart.  Matrix waves (2 per mask: w < 2N) compute the window sums of
-// round k for their mask: four tiles at outputs 128 k + 16 h + 32 j
-// (h = w % 2, j < 4), which read the same staged terms at K-steps s - j, so
-// each read of the ring feeds up to 12 products; the hi and lo weight tiles
-// stay in registers.  The sums go to an LDS buffer (two, alternating by
-// round).  Staging waves turn round k - 1's sums into traces, the root and
-// l, store them, and stage block k + 4 of every mask.  One barrier per round.
+// The work-group's 6N waves take two roles, one round apart.  Matrix waves
+// (2 per mask: w < 2N) compute the window sums of round k for their mask:
+// four tiles at outputs 128 k + 16 h + 32 j (h = w % 2, j < 4), which read
+// the same staged terms at K-steps s - j, so each read of the ring feeds up
+// to 12 products; the hi and lo weight tiles stay in registers.  The sums go
+// to an LDS buffer (two, alternating by round).  Staging waves (4N, one
+// staging unit per thread) turn round k - 1's sums into traces, the root and
+// l, store them, and stage block k + 4 of every mask.  With N = 2 each SIMD
+// runs one matrix wave and two staging waves, whose transcendental chains
+// hide each other's latency.  One barrier per round.
 template <int N, int DD, bool VEC>
-__global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt, KArgs ka, MxArgs mx)
+__global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt, KArgs ka, MxArgs mx)
 {
     extern __shared__ __align__(16) unsigned char mxs[];
     __shared__ MxShared sh;
@@ -470,6 +471,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid, bt.B);
         return;
     }
+    // (ordered before every use by the barrier that follows the references)
     if (tid < MXG) {
         sh.frag[tid] = 0;
 #pragma unroll
@@ -478,67 +480,60 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
             sh.omax[mm][tid] = INT_MIN;
         }
     }
-    // ---- references: midpoint of the exponents over a strided sample of each
-    // trajectory (positions i * ceil(L / 32), i < 32, one load per thread for
-    // every mask), reduced over each half-wave
-    {
-        const int hw = tid >> 5, l32 = lane & 31;
-        for (int r = hw; r < MXG; r += 8 * N) {
-            const int64_t b = g0 + r;
-            const int j = min(L - 1, l32 * ((L + 31) / 32));
-            float xv[DD];
-#pragma unroll
-            for (int d = 0; d < DD; ++d) xv[d] = bt.x[((b < bt.B ? b : 0) * L + j) * DD + d];
-#pragma unroll
-            for (int mm = 0; mm < N; ++mm) {
-                const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, mm);
-                const float z = b < bt.B ? mx_zx<DD>(M, xv) : -INFINITY;
-                const float zmax = half_max(z), zmin = half_min(b < bt.B ? z : INFINITY);
-                if (l32 == 0) sh.R[mm][r] = zmax >= zmin ? floorf(0.5f * (zmax + zmin)) : 0.f;
-            }
-        }
-    }
-    __syncthreads();
     // ---- staging units: unit u = (mask u / 256, row (u / 16) % 16, 8-position
     // group u % 16) of a block; position p of mask m holds the term of x at
-    // kf_m + p.  The prologue stages blocks 0..3 with every thread (one unit
-    // each per block); in the rounds each staging thread owns two units.
+    // kf_m + p.  Staging thread v owns unit v in every block; the mask is
+    // uniform over a wave.
     struct Unit {
         MxMask<DD> M;
         const float* xb;
         unsigned char* row;
-        float R;
+        float R;        // the row's reference (set once the references are known)
         int off;        // kf + 8 g: x index of the unit's first position in block 0
         int g8;         // 8 g
-        bool act;
+        int kf;
+        bool act, any;
     };
     auto unit = [&](int u) {
         Unit U;
-        const int um = u >> 8, ur = (u >> 4) & 15, ug = u & 15;
+        const int um = __builtin_amdgcn_readfirstlane(u >> 8), ur = (u >> 4) & 15, ug = u & 15;
         const MxTab& TU = mx.tabs[um];
         const int64_t b = g0 + ur;
         U.M = mx_mask<DD>(Pk, ka.params, um);
         U.xb = bt.x + (b < bt.B ? b : 0) * (int64_t)L * DD;
         U.row = mxs + (um * MXG + ur) * MXRS;
-        U.R = sh.R[um][ur];
+        U.R = 0.f;
         U.off = TU.kf + 8 * ug;
         U.g8 = 8 * ug;
+        U.kf = TU.kf;
+        U.any = TU.any;
         U.act = b < bt.B && TU.any;
         return U;
     };
     auto stage_load = [&](const Unit& U, int blk, float* xv) {
         mx_load8<DD, VEC>(U.xb, MXBLK * blk + U.off, L, xv);
     };
-    auto stage_write = [&](const Unit& U, int blk, const float* xv, bool& frag) {
+    // block blk of the unit's mask lies wholly inside the trajectory (a
+    // uniform condition: no position needs a select; rows past the batch
+    // stage terms of a valid row, which only their own unused outputs read)
+    auto unit_full = [&](const Unit& U, int blk) { return U.any && MXBLK * blk + U.kf + MXBLK <= L; };
+    auto stage_write = [&](auto full, const Unit& U, int blk, const float* xv, bool& frag) {
+        constexpr bool FULL = decltype(full)::value;
         const int p0 = MXBLK * blk + U.g8, j0 = MXBLK * blk + U.off;
         float e[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            // (selects, not branches: x reads as 0 outside the trajectory)
-            const bool in = U.act && j0 + q < L;
             const float d = mx_zx<DD>(U.M, xv + q * DD) - U.R;
-            frag |= in & !(fabsf(d) <= MX_HALF);
-            e[q] = mx_sel(in, ex2(fminf(fmaxf(d, -MX_HALF), MX_HALF)), 0.f);
+            const float t = ex2(fminf(fmaxf(d, -MX_HALF), MX_HALF));
+            if (FULL) {
+                frag |= !(fabsf(d) <= MX_HALF);
+                e[q] = t;
+            } else {
+                // (selects, not branches: x reads as 0 outside the trajectory)
+                const bool in = U.act && j0 + q < L;
+                frag |= in & !(fabsf(d) <= MX_HALF);
+                e[q] = mx_sel(in, t, 0.f);
+            }
         }
         bf16x8 h, l;
         split8(e, h, l);
@@ -546,46 +541,32 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         *(bf16x8*)q = h;
         *(bf16x8*)(q + 16) = l;
     };
-    bool sfrag[2] = {false, false};     // per unit of a staging thread
-    {
-        const Unit U = unit(tid);
-        float xv[4][8 * DD];
-#pragma unroll
-        for (int blk = 0; blk < 4; ++blk) stage_load(U, blk, xv[blk]);
-#pragma unroll
-        for (int blk = 0; blk < 4; ++blk) stage_write(U, blk, xv[blk], sfrag[0]);
-        if (sfrag[0]) atomicOr(&sh.frag[(tid >> 4) & 15], 1);
-        sfrag[0] = false;
-    }
-    // lo tiles of every mask in LDS (read by the matrix waves into registers)
     float* accb = (float*)(mxs + N * MXG * MXRS);                   // [2][N][2][4][64][4] window sums
-    uint4* wlds = (uint4*)(mxs + N * MXG * MXRS + (size_t)2 * N * 8 * 64 * 16);
-    for (int e = tid; e < N * NKMAX * 64; e += blockDim.x) {
-        const int mm = e / (NKMAX * 64), st = (e / 64) % NKMAX, l = e & 63;
-        wlds[e] = mx.tabs[mm].Wf[st][1][l];
-    }
     const int nround = (L + MXROUND - 1) / MXROUND;
     // bodies of the loop below (both roles run the same number, one barrier
     // each): round k's sums in body k, its outputs in body k + 1; an even
     // count lets the staging waves unroll by two with no conditional body
     const int nbody = (nround + 2) & ~1;
     const bool matrix = wv < 2 * N;
-    __syncthreads();
     if (matrix) {
         // ---------------------------------------------------------- matrix waves
+        // (the weight tiles are read while the staging waves compute the
+        // references and stage blocks 0 .. 3)
         const int m = wv >> 1, hh = wv & 1;
         const MxTab& T = mx.tabs[m];
         bf16x8 Wh[NKMAX], Wl[NKMAX];
 #pragma unroll
         for (int s = 0; s < NKMAX; ++s) {
             Wh[s] = tile_ld(&T.Wf[s][0][lane]);
-            Wl[s] = ld_bf16x8(wlds + (m * NKMAX + s) * 64 + lane);
+            Wl[s] = tile_ld(&T.Wf[s][1][lane]);
         }
 #pragma unroll
         for (int s = 0; s < NKMAX; ++s) {
             mx_pin(Wh[s]);
             mx_pin(Wl[s]);
         }
+        __syncthreads();        // references known
+        __syncthreads();        // blocks 0 .. 3 staged
         const int bc = lane & 15, rq = lane >> 4;
         const unsigned char* ebase = mxs + (m * MXG + bc) * MXRS;
         for (int k = 0; k < nbody; ++k) {
@@ -631,92 +612,148 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     } else {
         // ---------------------------------------------------------- staging waves
         const int vw = wv - 2 * N, vt = tid - 128 * N;
+        Unit U = unit(vt);
+        bool sfrag = false;
+        // ---- references: midpoint of the exponents over a strided sample of
+        // each trajectory (positions i * ceil(L / 32), i < 32, one load per
+        // thread for every mask), reduced over each half-wave; the loads of
+        // blocks 0 .. 3 are in flight meanwhile
+        {
+            const int hs = vt >> 5, l32 = lane & 31;
+            const int j = min(L - 1, l32 * ((L + 31) / 32));
+            float xs[2 / N][DD];
+#pragma unroll
+            for (int i = 0; i < 2 / N; ++i) {
+                const int64_t b = g0 + hs + 8 * N * i;
+#pragma unroll
+                for (int d = 0; d < DD; ++d) xs[i][d] = bt.x[((b < bt.B ? b : 0) * L + j) * DD + d];
+            }
+            float xv[4][8 * DD];
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk) stage_load(U, blk, xv[blk]);
+#pragma unroll
+            for (int i = 0; i < 2 / N; ++i) {
+                const int r = hs + 8 * N * i;
+                const bool bin = g0 + r < bt.B;
+#pragma unroll
+                for (int mm = 0; mm < N; ++mm) {
+                    const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, mm);
+                    const float z = bin ? mx_zx<DD>(M, xs[i]) : -INFINITY;
+                    const float zmax = half_max(z), zmin = half_min(bin ? z : INFINITY);
+                    if (l32 == 0) sh.R[mm][r] = zmax >= zmin ? floorf(0.5f * (zmax + zmin)) : 0.f;
+                }
+            }
+            __syncthreads();    // references known
+            U.R = sh.R[vt >> 8][(vt >> 4) & 15];
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk) stage_write(std::false_type{}, U, blk, xv[blk], sfrag);
+        }
         const int bc = lane & 15, rq = lane >> 4;
         const int64_t bo = g0 + bc;
         const bool bvalid = bo < bt.B;
-        float Rb[N], sgm[N], ibl[N], pad[N];
+        // per mask: sg_root * trace = c2 * lg2(window sum) + c1 where the
+        // window is not empty (O = Rb + lg2(window sum)), else spad
+        float Rb[N], c1[N], c2[N], spad[N];
         int klo[N];
-        bool any[N];
+        bool any[N], allany = true;
+        int klomax = 0;
 #pragma unroll
         for (int mm = 0; mm < N; ++mm) {
             const MxTab& T = mx.tabs[mm];
             const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, mm);
-            Rb[mm] = sh.R[mm][bc] + T.lscale;                   // O = Rb + lg2(window sum)
-            sgm[mm] = M.sg;
-            ibl[mm] = 1.f / (M.beta * LOG2E);
-            pad[mm] = -M.sg * P.rho_pad;                        // empty window
+            Rb[mm] = sh.R[mm][bc] + T.lscale;
+            c2[mm] = RC.sg * M.sg / (M.beta * LOG2E);
+            c1[mm] = c2[mm] * Rb[mm];
+            spad[mm] = -RC.sg * M.sg * P.rho_pad;               // empty window
             klo[mm] = T.klo;
             any[mm] = T.any;
+            allany = allany && T.any;
+            klomax = max(klomax, T.klo);
         }
-        float omin[N], omax[N];
+        // range of lg2(window sum) over the outputs (O is monotone in it)
+        float lmin[N], lmax[N];
 #pragma unroll
         for (int mm = 0; mm < N; ++mm) {
-            omin[mm] = INFINITY;
-            omax[mm] = -INFINITY;
+            lmin[mm] = INFINITY;
+            lmax[mm] = -INFINITY;
         }
         float* const root = ka.root;
         float* const saved = ka.saved;
-        // x of block k + 4 is loaded two rounds before it is staged (memory
-        // latency under load exceeds one round); the loop is unrolled by two
-        // so that the two prefetch buffers keep static register names
-        const Unit U0 = unit(vt), U1 = unit(vt + 128 * N);
-        float xq0[2][8 * DD], xq1[2][8 * DD];
-        stage_load(U0, 4, xq0[0]);
-        stage_load(U1, 4, xq0[1]);
-        auto body = [&](const int k, float (*xn)[8 * DD], float (*xnext)[8 * DD]) {
-            // (unconditional: the addresses are clamped, and a conditional load
-            // would be waited for where the branches join)
-            stage_load(U0, k + 5, xnext[0]);
-            stage_load(U1, k + 5, xnext[1]);
-            if (k >= 1 && k <= nround) {
-                // outputs of round k - 1: this wave's tiles tau = vw * 4 / N + i
-                const int kr = k - 1;
-                const float4* ib = (const float4*)accb + (kr & 1) * N * 8 * 64 + lane;
+        // outputs of round kr, tile tau: the traces, the root and l.  FULL:
+        // every output of the round has a window inside the trajectory for
+        // every mask (a uniform condition), so no output needs a select.
+        auto outputs = [&](auto full, const int kr, const int tau) {
+            constexpr bool FULL = decltype(full)::value;
+            const float4* ib = (const float4*)accb + (kr & 1) * N * 8 * 64 + lane;
+            const int hh = tau >> 2, j = tau & 3;
+            const int t0 = MXROUND * kr + 16 * hh + 32 * j + 4 * rq;
+            float su[N][4], la[N][4];
 #pragma unroll
-                for (int i = 0; i < 4 / N; ++i) {
-                    const int tau = vw * (4 / N) + i, hh = tau >> 2, j = tau & 3;
-                    const int t0 = MXROUND * kr + 16 * hh + 32 * j + 4 * rq;
-                    float tr[N][4], la[N][4];
+            for (int mm = 0; mm < N; ++mm) {
+                const float4 a4 = ib[((mm * 2 + hh) * 4 + j) * 64];
+                const float a[4] = {a4.x, a4.y, a4.z, a4.w};
 #pragma unroll
-                    for (int mm = 0; mm < N; ++mm) {
-                        const float4 a4 = ib[((mm * 2 + hh) * 4 + j) * 64];
-                        const float a[4] = {a4.x, a4.y, a4.z, a4.w};
-#pragma unroll
-                        for (int rr = 0; rr < 4; ++rr) {
-                            // (selects, not branches)
-                            const bool in = any[mm] && t0 + rr + klo[mm] <= L - 1;
-                            const float lo = lg2(a[rr]);
-                            const float O = Rb[mm] + lo;
-                            tr[mm][rr] = mx_sel(in, sgm[mm] * O * ibl[mm], pad[mm]);
-                            la[mm][rr] = mx_sel(in, lo, 0.f);
-                            omin[mm] = fminf(omin[mm], mx_sel(in, O, INFINITY));
-                            omax[mm] = fmaxf(omax[mm], mx_sel(in, O, -INFINITY));
-                        }
-                    }
-                    const int nv = L - t0;
-                    if (bvalid && nv > 0) {
-                        float rt[4], ll[N][4];
-#pragma unroll
-                        for (int rr = 0; rr < 4; ++rr) {
-                            float v[N], lw[N];
-#pragma unroll
-                            for (int mm = 0; mm < N; ++mm) v[mm] = tr[mm][rr];
-                            rt[rr] = mx_root_lws<N>(RC, v, lw);
-#pragma unroll
-                            for (int mm = 0; mm < N; ++mm) ll[mm][rr] = lw[mm] - la[mm][rr];
-                        }
-                        if (root) mx_store4<VEC>(root + bo * (int64_t)L + t0, nv, rt);
-                        if (saved) {
-#pragma unroll
-                            for (int mm = 0; mm < N; ++mm)
-                                mx_store4<VEC>(saved + ((int64_t)mm * bt.B + bo) * L + t0, nv, ll[mm]);
-                        }
+                for (int rr = 0; rr < 4; ++rr) {
+                    const float lo = lg2(a[rr]);
+                    const float u = fmaf(lo, c2[mm], c1[mm]);
+                    if (FULL) {
+                        su[mm][rr] = u;
+                        la[mm][rr] = lo;
+                        lmin[mm] = fminf(lmin[mm], lo);
+                        lmax[mm] = fmaxf(lmax[mm], lo);
+                    } else {
+                        // (selects, not branches)
+                        const bool in = any[mm] && t0 + rr + klo[mm] <= L - 1;
+                        su[mm][rr] = mx_sel(in, u, spad[mm]);
+                        la[mm][rr] = mx_sel(in, lo, 0.f);
+                        lmin[mm] = fminf(lmin[mm], mx_sel(in, lo, INFINITY));
+                        lmax[mm] = fmaxf(lmax[mm], mx_sel(in, lo, -INFINITY));
                     }
                 }
             }
+            const int nv = L - t0;
+            if (bvalid && (FULL || nv > 0)) {
+                float rt[4], ll[N][4];
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    float v[N], lw[N];
+#pragma unroll
+                    for (int mm = 0; mm < N; ++mm) v[mm] = su[mm][rr];
+                    rt[rr] = mx_root_lws<N>(RC, v, lw);
+#pragma unroll
+                    for (int mm = 0; mm < N; ++mm) ll[mm][rr] = lw[mm] - la[mm][rr];
+                }
+                if (root) mx_store4<VEC && FULL>(root + bo * (int64_t)L + t0, nv, rt);
+                if (saved) {
+#pragma unroll
+                    for (int mm = 0; mm < N; ++mm)
+                        mx_store4<VEC && FULL>(saved + ((int64_t)mm * bt.B + bo) * L + t0, nv, ll[mm]);
+                }
+            }
+        };
+        // x of block k + 4 is loaded two rounds before it is staged (memory
+        // latency under load exceeds one round); the loop is unrolled by two
+        // so that the two prefetch buffers keep static register names
+        float xq0[8 * DD], xq1[8 * DD];
+        stage_load(U, 4, xq0);
+        __syncthreads();        // blocks 0 .. 3 staged
+        auto body = [&](const int k, const float* xn, float* xnext) {
+            // (unconditional: the addresses are clamped, and a conditional load
+            // would be waited for where the branches join)
+            stage_load(U, k + 5, xnext);
+            if (k >= 1 && k <= nround) {
+                // outputs of round k - 1: this wave's tiles tau = vw * 2 / N + i
+                const int kr = k - 1;
+                const bool full = allany && MXROUND * kr + MXROUND + klomax <= L;
+#pragma unroll
+                for (int i = 0; i < 2 / N; ++i) {
+                    if (full) outputs(std::true_type{}, kr, vw * (2 / N) + i);
+                    else outputs(std::false_type{}, kr, vw * (2 / N) + i);
+                }
+            }
             if (k < nround) {
-                stage_write(U0, k + 4, xn[0], sfrag[0]);
-                stage_write(U1, k + 4, xn[1], sfrag[1]);
+                if (unit_full(U, k + 4)) stage_write(std::true_type{}, U, k + 4, xn, sfrag);
+                else stage_write(std::false_type{}, U, k + 4, xn, sfrag);
             }
             __syncthreads();
         };
@@ -726,13 +763,11 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         }
 #pragma unroll
         for (int mm = 0; mm < N; ++mm)
-            if (any[mm] && bvalid && omin[mm] <= omax[mm]) {
-                atomicMin(&sh.omin[mm][bc], (int)floorf(omin[mm]));
-                atomicMax(&sh.omax[mm][bc], (int)ceilf(omax[mm]));
+            if (any[mm] && bvalid && lmin[mm] <= lmax[mm]) {
+                atomicMin(&sh.omin[mm][bc], (int)floorf(Rb[mm] + lmin[mm]));
+                atomicMax(&sh.omax[mm][bc], (int)ceilf(Rb[mm] + lmax[mm]));
             }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-            if (sfrag[i]) atomicOr(&sh.frag[((vt + 128 * N * i) >> 4) & 15], 1);
+        if (sfrag) atomicOr(&sh.frag[(vt >> 4) & 15], 1);
     }
     // ---- exponent ranges of the traces and the references (for the
     // backward), hand-offs
