@@ -653,7 +653,18 @@ DEV MaskInfo mask_info(const float* params, const Instr& I, int L, SH& sh, float
     if (threadIdx.x == 0) { si[0] = L; si[1] = -1; }
     __syncthreads();
     int lo = L, hi = -1;
-    for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    // Without stored weights only the support is needed, and it lies inside
+    // [a - 89/c, b + 89/c]: beyond, a sigmoid's exponential overflows in fp32
+    // (e^x is inf for x > 88.73), the factor is exactly 0 and w_k = max(-eps, 0).
+    int k0 = 0, k1 = L - 1;
+    if (!w && !dwa) {
+        const double a = mp.a, b = mp.b, c = mp.c;
+        if (c > 0.0 && isfinite(a) && isfinite(c) && (unb || isfinite(b))) {
+            k0 = (int)fmax(0.0, fmin((double)L, floor(a - 89.0 / c) - 2.0));
+            if (!unb) k1 = (int)fmin((double)(L - 1), fmax(-1.0, ceil(b + 89.0 / c) + 2.0));
+        }
+    }
+    for (int k = k0 + (int)threadIdx.x; k <= k1; k += blockDim.x) {
         float da, db;
         const float wk = mask_wk(mp, k, dwa ? &da : nullptr, &db);
         if (w) w[k] = wk;
@@ -1858,6 +1869,8 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
     const int Lc = bt.Lcap;
     int64_t item = 0;
     bool first = true;
+    // an empty fix-up list: nothing to do and no counter to clear
+    if (ka.list_mode && *ka.list_count <= 0) return;
     while (next_item(ka, sh, item, first)) {
         first = false;
         const int64_t nitems = ka.list_mode ? min(max((int64_t)*ka.list_count, (int64_t)0), bt.B) : bt.B;
@@ -2151,7 +2164,7 @@ static bool al16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
 hipError_t launch_mx_tables(const DevPlan& plan, const Batch& bt, const float* params, MxTab* tabs, int* counters2,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL(stl_mx_tables, dim3(NKMAX, plan.fused.n), dim3(256), 0, s, plan, params, (int)bt.T, tabs,
+    hipLaunchKernelGGL(stl_mx_tables, dim3(NKMAX, plan.fused.n), dim3(1024), 0, s, plan, params, (int)bt.T, tabs,
                        (int*)nullptr, counters2, (int*)nullptr, (int*)nullptr, bt.B);
     return hipGetLastError();
 }
@@ -2160,7 +2173,7 @@ hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs
                      int* table_saved_flag, int* counters2, bool tables, size_t lds, hipStream_t s)
 {
     if (tables) {
-        hipLaunchKernelGGL(stl_mx_tables, dim3(NKMAX, plan.fused.n), dim3(256), 0, s, plan, ka.params, (int)bt.T,
+        hipLaunchKernelGGL(stl_mx_tables, dim3(NKMAX, plan.fused.n), dim3(1024), 0, s, plan, ka.params, (int)bt.T,
                            (MxTab*)mx.tabs, ka.counter, counters2, mx.handed, table_saved_flag, bt.B);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

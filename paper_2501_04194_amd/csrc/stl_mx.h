@@ -146,7 +146,7 @@ DEV float half_min(float v) { return -half_max(-v); }
 // (and those a saving forward keeps for the backward).  handed, counters
 // and saved_flag may be NULL (a saving forward that takes another path
 // still writes the tables and clears the backward's counters).
-__global__ void __launch_bounds__(256) stl_mx_tables(DevPlan plan, const float* params, int L, MxTab* tabs,
+__global__ void __launch_bounds__(1024) stl_mx_tables(DevPlan plan, const float* params, int L, MxTab* tabs,
                                                      int* counters, int* counters2, int* handed, int* saved_flag,
                                                      int64_t B)
 {
@@ -971,12 +971,18 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         for (int k = 0; k < nbody; ++k) {
             if (k < nround) {
                 const int t0 = MXROUND * k + 16 * hh;
-                // z_j + Q at this lane's outputs
-                float ez[4][4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) ez[j][rr] = mx_zx<DD>(M, xv[j] + rr * DD) + Qb;
+                // 2^{z_j + Q} = f 2^n at this lane's outputs (the products below are
+                // moderate even where the factors are not); f = 0 where j is not an
+                // output.  (Independent of the products: computed while they run.)
+                float fj[4][4];
+                int nj[4][4];
+                auto factor = [&](int j, int rr) {
+                    const int t = t0 + 32 * j + 4 * rq + rr;
+                    const float e = mx_zx<DD>(M, xv[j] + rr * DD) + Qb;
+                    const float fl = floorf(e);
+                    fj[j][rr] = mx_sel(any && bvalid && t < L, ex2(e - fl), 0.f);
+                    nj[j][rr] = (int)fminf(fmaxf(fl, -300.f), 300.f);
+                };
                 const int pr = (t0 + 8 * rq) % MXRING;
                 mxf4 acc[4];
 #pragma unroll
@@ -1001,23 +1007,12 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                     }
                     eh = ehn;
                     el = eln;
+                    // (one factor per step, among the products)
+                    if (s < 15) factor(s >> 2, s & 3);
                 }
-                // 2^{z_j + Q} = f 2^n at this lane's outputs (the products below are
-                // moderate even where the factors are not); f = 0 where j is not an output
+                factor(3, 3);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) mx_load4<DD, VEC>(xo, t0 + MXROUND + 32 * j + 4 * rq, L, xv[j]);
-                float fj[4][4];
-                int nj[4][4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        const int t = t0 + 32 * j + 4 * rq + rr;
-                        const float e = ez[j][rr];
-                        const float fl = floorf(e);
-                        fj[j][rr] = mx_sel(any && bvalid && t < L, ex2(e - fl), 0.f);
-                        nj[j][rr] = (int)fminf(fmaxf(fl, -300.f), 300.f);
-                    }
                 // d/dx factors (times w of the predicate, by the staging waves)
                 float4* ob = (float4*)gbuf + ((((k & 1) * N + m) * 2 + hh) * 4) * 64 + lane;
 #pragma unroll
@@ -1027,34 +1022,47 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                     for (int rr = 0; rr < 4; ++rr) g[rr] = ldexpf(acc[j][rr] * fj[j][rr], nj[j][rr]);
                     ob[j * 64] = make_float4(g[0], g[1], g[2], g[3]);
                 }
-                // derivative sums: K-step dst[d] of every tile, added straight
-                // into this lane's d/da, d/db partials
-                // (the terms of each product are read one product ahead)
+                // derivative sums: K-step dst[d] of every tile, added into this
+                // lane's d/da, d/db partials.  Product i = (d, j) = (i / 4, i % 4);
+                // the terms of each product are read one product ahead, and the
+                // products of i + 1 are issued before the sums of i.
                 bf16x8 dh = ld_bf16x8(hbase + ring_byte(pr, 32 * dst[0])),
                        dl = ld_bf16x8(hbase + ring_byte(pr, 32 * dst[0]) + 16);
+                bf16x8 Dh = ld_bf16x8(dl_m), Dl = ld_bf16x8(dl_m + 64);
+                mxf4 ap = mxf4{0.f, 0.f, 0.f, 0.f};
+                float sum = 0.f;
 #pragma unroll
-                for (int d = 0; d < NDMAX; ++d) {
-                    const bf16x8 Dh = ld_bf16x8(dl_m + d * 128), Dl = ld_bf16x8(dl_m + d * 128 + 64);
-                    float sum = 0.f;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                for (int i = 0; i <= NDMAX * 4; ++i) {
+                    mxf4 an = ap;
+                    if (i < NDMAX * 4) {
+                        const int d = i >> 2;
+                        if ((i & 3) == 0 && d > 0) {
+                            Dh = ld_bf16x8(dl_m + d * 128);
+                            Dl = ld_bf16x8(dl_m + d * 128 + 64);
+                        }
                         bf16x8 dhn = dh, dln = dl;
-                        if (d * 4 + j + 1 < NDMAX * 4) {
-                            const int dn = j < 3 ? d : d + 1, jn = j < 3 ? j + 1 : 0;
-                            const unsigned char* ep = hbase + ring_byte(pr, 32 * (dst[dn] + jn));
+                        if (i + 1 < NDMAX * 4) {
+                            const unsigned char* ep = hbase + ring_byte(pr, 32 * (dst[(i + 1) >> 2] + ((i + 1) & 3)));
                             dhn = ld_bf16x8(ep);
                             dln = ld_bf16x8(ep + 16);
                         }
-                        mxf4 a = mfma(Dh, dh, mxf4{0.f, 0.f, 0.f, 0.f});
-                        a = mfma(Dh, dl, a);
-                        a = mfma(Dl, dh, a);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) sum += ldexpf(a[q] * fj[j][q], nj[j][q]);
+                        an = mfma(Dh, dh, mxf4{0.f, 0.f, 0.f, 0.f});
+                        an = mfma(Dh, dl, an);
+                        an = mfma(Dl, dh, an);
                         dh = dhn;
                         dl = dln;
                     }
-                    pam += isb[d] ? 0.f : sum;
-                    pbm += isb[d] ? sum : 0.f;
+                    if (i > 0) {
+                        const int d = (i - 1) >> 2, j = (i - 1) & 3;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) sum += ldexpf(ap[q] * fj[j][q], nj[j][q]);
+                        if (j == 3) {
+                            pam += isb[d] ? 0.f : sum;
+                            pbm += isb[d] ? sum : 0.f;
+                            sum = 0.f;
+                        }
+                    }
+                    ap = an;
                 }
             }
 #pragma unroll
