@@ -236,9 +236,9 @@ stl_status stl_backward(const stl_plan* plan, const stl_batch* batch, const floa
  * children's traces, the matrix-core kernels log2 of each child's softmax
  * weight at the root minus log2 of its window sum), and for the matrix-core
  * path each trajectory's exponent range and reference ([B][n_mask][3]
- * int32), the masks' weight tables and three counters of the backward's
- * hand-off list; only the header otherwise.  The contents are private to the
- * pair (stl_backward_saved writes the counters back to zero).
+ * int32, the total padded to 256 bytes) and 256 bytes of the masks' window
+ * geometry; only the header otherwise.  The
+ * contents are private to the pair; stl_backward_saved only reads them.
  * A flag is 1 (fp64 fused forward) or 2 (matrix-core forward) where the
  * trajectory's saved data are valid for the backward of the same path.
  *
@@ -268,8 +268,8 @@ stl_status stl_backward_saved(const stl_plan* plan, const stl_batch* batch, cons
  * runs on keeps its own copy until the process ends.  The call allocates
  * nothing.  A batch whose forward workspace (stl_workspace_size) exceeds the
  * array returns STL_E_WORKSPACE before any launch.  Every call on one GPU
- * shares that GPU's copy, which keeps the previous call's contents (the
- * kernels reset the counters they need themselves): calls that overlap on
+ * shares that GPU's copy, which keeps the previous call's contents (every
+ * call writes all the flags and counters it reads): calls that overlap on
  * one GPU, from several streams or host threads, race and must be
  * serialised by the caller.  Results equal stl_forward's bit for bit.
  */

@@ -32,15 +32,11 @@ hipError_t launch_fused(bool bwd, const DevPlan& plan, const struct Batch& bt, c
                         hipStream_t s);
 hipError_t set_max_lds_fused(size_t bytes);
 size_t mask_tab_bytes();
-size_t mx_tab_bytes();
 size_t mx_lds_bytes(int n, int D, bool bwd);
 size_t mx_static_lds();
 hipError_t set_max_lds_mx(size_t bytes);
-hipError_t launch_mx_tables(const DevPlan& plan, const struct Batch& bt, const float* params, struct MxTab* tabs,
-                            int* counters2, hipStream_t s);
 hipError_t launch_mx(bool bwd, const DevPlan& plan, const struct Batch& bt, const struct KArgs& ka,
-                     const struct MxArgs& mx, int* table_saved_flag, int* counters2, bool tables, size_t lds,
-                     hipStream_t s);
+                     const struct MxArgs& mx, size_t lds, hipStream_t s);
 int interval_max_T();
 int pstl_max_BT();
 hipError_t launch_pstl_descent(const float* x, int B, int T, int D, const float* w, float c, int op_sg, float eps,
@@ -116,6 +112,7 @@ struct Geom {
     size_t off_mxtr;        // backward without saved traces: [n][B][T] traces, [B] flags, ranges
     size_t off_mxflag;
     size_t off_mxrange;
+    size_t off_mxheads;     // matrix-core forward: per-mask geometry for the backward
 };
 
 // The matrix-core path takes dense batches of a root that is a smooth
@@ -182,7 +179,7 @@ stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch*
     g->lds_bytes = global ? 0 : lds;
     g->mx = false;
     g->mx_lds = 0;
-    g->off_handed = g->off_mxtr = g->off_mxflag = g->off_mxrange = 0;
+    g->off_handed = g->off_mxtr = g->off_mxflag = g->off_mxrange = g->off_mxheads = 0;
     if (mx_applies(dp, bt, cfg, trace)) {
         // (a backward without saved traces runs the forward kernel first, with the same LDS size)
         const size_t lds = bwd ? std::max(mx_lds_bytes(dp.fused.n, bt->D, false), mx_lds_bytes(dp.fused.n, bt->D, true))
@@ -203,18 +200,15 @@ stl_status geometry(const stl_plan* plan, const stl_batch* bt, const stl_launch*
     g->off_list = 0;
     g->off_tabs = 0;
     if (g->mx) {
-        // fix-up grid of the generic executor, list, hand-off flags, tables
-        if (!global) g->persistent = 1;
+        // fix-up grid of the generic executor (it takes the trajectories whose
+        // hand-off flag is set), hand-off flags
+        g->persistent = 0;
         g->grid = (int)std::max<int64_t>(1, std::min<int64_t>(bt->B, di.cus / 4));
-        g->off_list = off;
-        off += (size_t)bt->B * sizeof(int);
-        off = (off + 255) / 256 * 256;
         g->off_handed = off;
         off += (size_t)bt->B * sizeof(int);
         off = (off + 255) / 256 * 256;
-        g->off_tabs = off;
-        off += (size_t)dp.fused.n * mx_tab_bytes();
-        off = (off + 255) / 256 * 256;
+        g->off_mxheads = off;
+        off += 256;
         if (bwd) {
             // the backward without saved traces first runs the forward into these
             g->off_mxtr = off;
@@ -296,18 +290,13 @@ static size_t saved_traces_bytes(const stl_plan* plan, const stl_batch* bt)
     return (size_t)plan->dev.fused.n * bt->B * bt->T * sizeof(float);
 }
 
-// matrix-core path: after the ranges (256-aligned) the per-mask tables the
-// saving forward computed, then three counters of the backward's hand-off list
-static size_t saved_tables_offset(const stl_plan* plan, const stl_batch* bt)
+// matrix-core path: after the ranges (256-aligned) the per-mask geometry the
+// saving forward derived (256 bytes)
+static size_t saved_heads_offset(const stl_plan* plan, const stl_batch* bt)
 {
     const size_t e = saved_header(bt->B) + saved_traces_bytes(plan, bt) +
                      (size_t)bt->B * plan->dev.fused.n * 3 * sizeof(int32_t);
     return (e + 255) / 256 * 256;
-}
-
-static size_t saved_counters_offset(const stl_plan* plan, const stl_batch* bt)
-{
-    return saved_tables_offset(plan, bt) + ((size_t)plan->dev.fused.n * mx_tab_bytes() + 255) / 256 * 256;
 }
 
 static size_t saved_bytes_needed(const stl_plan* plan, const stl_batch* bt)
@@ -315,7 +304,7 @@ static size_t saved_bytes_needed(const stl_plan* plan, const stl_batch* bt)
     const int n = plan->dev.fused.n;
     const bool mx = mx_applies(plan->dev, bt, nullptr, false);
     const bool fusable = n > 0 && bt->offsets == nullptr && (bt->T <= fused_max_T() || mx);
-    if (mx) return saved_counters_offset(plan, bt) + 256;
+    if (mx) return saved_heads_offset(plan, bt) + 256;
     return saved_header(bt->B) + (fusable ? saved_traces_bytes(plan, bt) : 0);
 }
 
@@ -381,36 +370,26 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
     ka.list_mode = 0;
     ka.part_stride = 1;
     if (g.mx) {
+        // each matrix-core kernel derives its tables from the parameters and
+        // writes every trajectory's hand-off flag; the generic executor then
+        // takes the flagged ones
         MxArgs mx;
-        mx.tabs = (const MxTab*)(wsb + g.off_tabs);
+        mx.heads = (MxHead*)(wsb + g.off_mxheads);
         mx.handed = (int*)(wsb + g.off_handed);
         mx.part = ka.mask_part;
         mx.ranges = nullptr;
-        mx.own_flags = 0;
+        ka.list = nullptr;
         hipError_t e;
-        int* traces_flags = nullptr;
-        int* saved_counters = nullptr;
         if (saved) {
-            traces_flags = (int*)d_saved;
             float* traces = (float*)((char*)d_saved + saved_header(bt->B));
-            ka.saved_flag = traces_flags;
+            ka.saved_flag = (int*)d_saved;
             mx.ranges = (int*)((char*)traces + saved_traces_bytes(plan, bt));
-            // the saving forward's tables serve the backward; the backward's
-            // hand-off list counts through counters kept beside them (cleared
-            // by the forward's tables kernel and by the backward's fix-up)
-            mx.tabs = (const MxTab*)((char*)d_saved + saved_tables_offset(plan, bt));
-            saved_counters = (int*)((char*)d_saved + saved_counters_offset(plan, bt));
+            mx.heads = (MxHead*)((char*)d_saved + saved_heads_offset(plan, bt));
             if (saved == 1) ka.saved = traces;
             else ka.saved_in = traces;
         }
-        if (!bwd) {
-            e = launch_mx(false, dp, b, ka, mx, saved == 1 ? traces_flags : nullptr, saved_counters, true, g.mx_lds,
-                          st);
-        } else if (saved == 2) {
-            ka.counter = saved_counters;
-            ka.list_count = saved_counters + 1;
-            mx.own_flags = 1;
-            e = launch_mx(true, dp, b, ka, mx, nullptr, nullptr, false, g.mx_lds, st);
+        if (!bwd || saved == 2) {
+            e = launch_mx(bwd, dp, b, ka, mx, g.mx_lds, st);
         } else {
             // no saved traces: the forward fills workspace copies first
             KArgs kf = ka;
@@ -419,19 +398,18 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
             kf.saved = (float*)(wsb + g.off_mxtr);
             kf.saved_flag = (int*)(wsb + g.off_mxflag);
             mf.ranges = (int*)(wsb + g.off_mxrange);
-            e = launch_mx(false, dp, b, kf, mf, kf.saved_flag, nullptr, true, g.mx_lds, st);
+            e = launch_mx(false, dp, b, kf, mf, g.mx_lds, st);
             if (e == hipSuccess) {
                 KArgs kb = ka;
                 kb.saved_in = kf.saved;
                 kb.saved_flag = kf.saved_flag;
-                e = launch_mx(true, dp, b, kb, mf, nullptr, nullptr, false, g.mx_lds, st);
+                e = launch_mx(true, dp, b, kb, mf, g.mx_lds, st);
             }
         }
         if (e != hipSuccess) return fail(STL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
-        // trajectories the matrix-core kernels handed off go through the generic executor
         KArgs kx = ka;
-        kx.list_mode = 1;
-        kx.persistent = 1;
+        kx.scan = mx.handed;
+        kx.persistent = 0;
         kx.saved = nullptr;
         kx.saved_in = nullptr;
         e = launch_exec(bwd, dp, b, kx, g.grid, g.nt, g.lds_bytes, st);
@@ -442,13 +420,6 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
         }
         return STL_OK;
     }
-    if (saved == 1 && mx_applies(plan->dev, bt, nullptr, false)) {
-        // the buffer has the matrix-core layout: its tables and the backward's
-        // list counters must be valid whichever path this forward takes
-        if (launch_mx_tables(plan->dev, b, params, (MxTab*)((char*)d_saved + saved_tables_offset(plan, bt)),
-                             (int*)((char*)d_saved + saved_counters_offset(plan, bt)), st) != hipSuccess)
-            return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
-    }
     if (saved) {
         int* flags = (int*)d_saved;
         float* traces = (float*)((char*)d_saved + saved_header(bt->B));
@@ -457,6 +428,11 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
         if (saved == 2 && g.fused) ka.saved_in = traces;
         // a forward that does not take the fused path leaves nothing to reuse
         if (saved == 1 && !g.fused && launch_fill_int(flags, bt->B, 0, st) != hipSuccess)
+            return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
+        // (matrix-core layout: geometry marked unusable, so that a matrix-core
+        // backward hands every trajectory to the generic executor)
+        if (saved == 1 && mx_applies(plan->dev, bt, nullptr, false) &&
+            launch_fill_int((int*)((char*)d_saved + saved_heads_offset(plan, bt)), 64, 0, st) != hipSuccess)
             return fail(STL_E_HIP, "launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
     // (the fused path's table kernel resets the counters itself)

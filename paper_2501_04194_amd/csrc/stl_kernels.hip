@@ -123,6 +123,7 @@ struct Shared {
     int flag[MAX_NT];
     int ints[8];
     float f[8];
+    int scan_pos, scan_min;      // flag-scan fix-up: next row index of this work-group, first set flag
 };
 
 // storage index maps for scanned arrays: identity, or one pad element after
@@ -641,29 +642,69 @@ DEV float mask_wk(const MaskP& m, int k, float* dwa = nullptr, float* dwb = null
     return wk;
 }
 
-// Weights for k in [0, L) (stored when w != NULL), the support {w > 0} and
+// Offsets that can hold the support {w > 0}: it lies inside [a - 89/c,
+// b + 89/c], beyond which a sigmoid's exponential overflows in fp32 (e^x is
+// inf for x > 88.73), the factor is exactly 0 and w_k = max(-eps, 0).
+DEV void mask_window(const MaskP& mp, int L, int& k0, int& k1)
+{
+    k0 = 0;
+    k1 = L - 1;
+    const double a = mp.a, b = mp.b, c = mp.c;
+    if (c > 0.0 && isfinite(a) && isfinite(c) && (mp.unb || isfinite(b))) {
+        k0 = (int)fmax(0.0, fmin((double)L, floor(a - 89.0 / c) - 2.0));
+        if (!mp.unb) k1 = (int)fmin((double)(L - 1), fmax(-1.0, ceil(b + 89.0 / c) + 2.0));
+    }
+}
+
 // the core where both sigmoid derivatives are below 2^-24 (|c(k-a)|,
-// |c(k-b)| > 17), over which w is constant to fp32 rounding.
+// |c(k-b)| > 17), over which w is constant to fp32 rounding, given the
+// support [klo, khi]
+DEV MaskInfo mask_core(const MaskP& mp, int klo, int khi)
+{
+    MaskInfo mi;
+    mi.klo = klo;
+    mi.khi = khi;
+    mi.any = mi.klo <= mi.khi;
+    const float a = mp.a, b = mp.b, c = mp.c;
+    if (c > 0.f && mi.any) {
+        mi.clo = max(mi.klo, (int)fminf(ceilf(a + 17.f / c), 2e9f));
+        mi.chi = mp.unb ? mi.khi : min(mi.khi, (int)fmaxf(floorf(b - 17.f / c), -2e9f));
+    } else {
+        mi.clo = 1;
+        mi.chi = 0;
+    }
+    if (mi.clo > mi.chi) { mi.clo = 1; mi.chi = 0; mi.wc = 0.f; }
+    else mi.wc = mask_wk(mp, (mi.clo + mi.chi) / 2);
+    return mi;
+}
+
+// min / max over the wave (an atomic with a value per lane becomes a scalar
+// loop over the lanes, which the work-group's waves share: reduce first)
+DEV int wave_imin(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+DEV int wave_imax(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Weights for k in [0, L) (stored when w != NULL), the support {w > 0} and
+// the core.  Without stored weights only the support's window is searched.
 template <class SH>
 DEV MaskInfo mask_info(const float* params, const Instr& I, int L, SH& sh, float* w, float* dwa, float* dwb)
 {
     const MaskP mp = mask_params(params + I.mask, I.flags & F_MASK_UNB);
-    const bool unb = mp.unb;
     int* si = sh.ints;
     if (threadIdx.x == 0) { si[0] = L; si[1] = -1; }
     __syncthreads();
     int lo = L, hi = -1;
-    // Without stored weights only the support is needed, and it lies inside
-    // [a - 89/c, b + 89/c]: beyond, a sigmoid's exponential overflows in fp32
-    // (e^x is inf for x > 88.73), the factor is exactly 0 and w_k = max(-eps, 0).
     int k0 = 0, k1 = L - 1;
-    if (!w && !dwa) {
-        const double a = mp.a, b = mp.b, c = mp.c;
-        if (c > 0.0 && isfinite(a) && isfinite(c) && (unb || isfinite(b))) {
-            k0 = (int)fmax(0.0, fmin((double)L, floor(a - 89.0 / c) - 2.0));
-            if (!unb) k1 = (int)fmin((double)(L - 1), fmax(-1.0, ceil(b + 89.0 / c) + 2.0));
-        }
-    }
+    if (!w && !dwa) mask_window(mp, L, k0, k1);
     for (int k = k0 + (int)threadIdx.x; k <= k1; k += blockDim.x) {
         float da, db;
         const float wk = mask_wk(mp, k, dwa ? &da : nullptr, &db);
@@ -671,23 +712,14 @@ DEV MaskInfo mask_info(const float* params, const Instr& I, int L, SH& sh, float
         if (dwa) { dwa[k] = da; dwb[k] = db; }
         if (wk > 0.f) { lo = min(lo, k); hi = max(hi, k); }
     }
-    atomicMin(&si[0], lo);
-    atomicMax(&si[1], hi);
-    __syncthreads();
-    MaskInfo mi;
-    mi.klo = si[0];
-    mi.khi = si[1];
-    mi.any = mi.klo <= mi.khi;
-    const float a = mp.a, b = mp.b, c = mp.c;
-    if (c > 0.f && mi.any) {
-        mi.clo = max(mi.klo, (int)fminf(ceilf(a + 17.f / c), 2e9f));
-        mi.chi = unb ? mi.khi : min(mi.khi, (int)fmaxf(floorf(b - 17.f / c), -2e9f));
-    } else {
-        mi.clo = 1;
-        mi.chi = 0;
+    lo = wave_imin(lo);
+    hi = wave_imax(hi);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&si[0], lo);
+        atomicMax(&si[1], hi);
     }
-    if (mi.clo > mi.chi) { mi.clo = 1; mi.chi = 0; mi.wc = 0.f; }
-    else mi.wc = mask_wk(mp, (mi.clo + mi.chi) / 2);
+    __syncthreads();
+    const MaskInfo mi = mask_core(mp, si[0], si[1]);
     __syncthreads();
     return mi;
 }
@@ -1840,8 +1872,29 @@ DEV void exec_adj(const Env& e, const Instr& I, float* mask_part)
 struct MaskTab;
 
 
-DEV bool next_item(const KArgs& ka, Shared& sh, int64_t& item, bool first)
+DEV bool next_item(const KArgs& ka, Shared& sh, int64_t& item, bool first, int64_t B)
 {
+    if (ka.scan) {
+        // the rows blockIdx.x + i gridDim.x whose flag is set, in order of i
+        // (the flags of up to blockDim.x rows are read at once)
+        __syncthreads();
+        const int64_t nrow = B > (int64_t)blockIdx.x ? (B - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+        for (int64_t i0 = first ? 0 : (int64_t)sh.scan_pos; i0 < nrow; i0 += blockDim.x) {
+            if (threadIdx.x == 0) sh.scan_min = INT_MAX;
+            __syncthreads();
+            const int64_t i = i0 + threadIdx.x;
+            if (i < nrow && ka.scan[blockIdx.x + i * gridDim.x] != 0) atomicMin(&sh.scan_min, (int)i);
+            __syncthreads();
+            const int f = sh.scan_min;
+            __syncthreads();
+            if (f != INT_MAX) {
+                item = (int64_t)blockIdx.x + (int64_t)f * gridDim.x;
+                if (threadIdx.x == 0) sh.scan_pos = f + 1;
+                return true;
+            }
+        }
+        return false;
+    }
     if (!ka.persistent) {
         item = blockIdx.x;
         return first;
@@ -1871,7 +1924,7 @@ __global__ void __launch_bounds__(MAX_NT) stl_exec_kernel(DevPlan plan, Batch bt
     bool first = true;
     // an empty fix-up list: nothing to do and no counter to clear
     if (ka.list_mode && *ka.list_count <= 0) return;
-    while (next_item(ka, sh, item, first)) {
+    while (next_item(ka, sh, item, first, bt.B)) {
         first = false;
         const int64_t nitems = ka.list_mode ? min(max((int64_t)*ka.list_count, (int64_t)0), bt.B) : bt.B;
         if (item >= nitems) break;
@@ -2126,8 +2179,6 @@ hipError_t launch_reduce_params(const float* part, int64_t B, const DevPlan& pla
 
 // ------------------------------------------------------------------ matrix-core path
 
-size_t mx_tab_bytes() { return sizeof(MxTab); }
-
 // dynamic LDS of the matrix-core kernels: the rings (n masks x 16 rows), the
 // result buffers, and the backward's derivative tiles
 size_t mx_lds_bytes(int n, int D, bool bwd)
@@ -2156,28 +2207,12 @@ hipError_t set_max_lds_mx(size_t bytes)
 
 static bool al16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
 
-// tables (saved_flag: marked valid for a saving forward, else NULL;
-// counters2: a second counter triple to clear, else NULL), then
 // the forward or backward kernel over groups of 16 trajectories.  The
 // 16-byte load / store variants need T a multiple of 4 and 16-byte aligned
 // arrays (x; forward: root and saved values; backward: G, saved values, dx).
-hipError_t launch_mx_tables(const DevPlan& plan, const Batch& bt, const float* params, MxTab* tabs, int* counters2,
-                            hipStream_t s)
+hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs& ka, const MxArgs& mx, size_t lds,
+                     hipStream_t s)
 {
-    hipLaunchKernelGGL(stl_mx_tables, dim3(NKMAX, plan.fused.n), dim3(1024), 0, s, plan, params, (int)bt.T, tabs,
-                       (int*)nullptr, counters2, (int*)nullptr, (int*)nullptr, bt.B);
-    return hipGetLastError();
-}
-
-hipError_t launch_mx(bool bwd, const DevPlan& plan, const Batch& bt, const KArgs& ka, const MxArgs& mx,
-                     int* table_saved_flag, int* counters2, bool tables, size_t lds, hipStream_t s)
-{
-    if (tables) {
-        hipLaunchKernelGGL(stl_mx_tables, dim3(NKMAX, plan.fused.n), dim3(1024), 0, s, plan, ka.params, (int)bt.T,
-                           (MxTab*)mx.tabs, ka.counter, counters2, mx.handed, table_saved_flag, bt.B);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
     // (forward: 2n matrix and 4n staging waves; backward: 2n of each)
     const dim3 grid((unsigned)((bt.B + MXG - 1) / MXG)), block((bwd ? 256 : 384) * plan.fused.n);
     const bool d2 = bt.D == 2;

@@ -62,23 +62,25 @@ constexpr int MX_MAXN = 2;              // mask nodes under the root
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float mxf4;
 
-// Per-mask tables, computed once per call by stl_mx_tables.  Tiles are
-// stored in the lane layout of the MFMA A operand (16 rows x 32 columns,
-// lane l holds row l % 16, columns 8 (l / 16) .. + 7), 16 bytes per lane.
-struct MxTab {
+// Per-mask quantities of the matrix-core path.  Every work-group of both
+// kernels derives them from the mask's parameters at its start (the same
+// values everywhere), then builds its weight tiles from per-offset weights
+// in LDS.  Tiles are in the lane layout of the MFMA A operand (16 rows x 32
+// columns, lane l holds row l % 16, columns 8 (l / 16) .. + 7).
+struct MxHead {
     int ok;                    // 0: the window needs more than NKMAX K-steps
     int any;                   // the support {w > 0} is non-empty
     int klo, khi, clo, chi;    // support and constant core (clo > chi: no core)
     int kf, kb;                // tile origins: klo rounded down, khi rounded up to a multiple of 4
     int NK;                    // K-steps of an output tile
     float lscale;              // log2 of the weight scale (the core weight, or 1)
-    int flo_f[NKMAX];          // tile s of the forward (backward) product has a
-    int flo_b[NKMAX];          //   non-zero lo part
-    int fd[NKMAX];             // backward K-step s has d/da (bit 0) / d/db (bit 1) weights
-    uint4 Wf[NKMAX][2][64];    // forward tiles [s][hi, lo][lane]: row t, column j: w(kf + 32 s + j - t)
-    uint4 Wb[NKMAX][2][64];    // backward tiles: row j, column t: w(kb - 32 s + j - t)
-    uint4 Dt[NKMAX][2][2][64]; // derivative tiles [s][d/da, d/db][hi, lo][lane], backward layout
+    double scale;
 };
+
+// offsets one set of tiles reads: forward tiles w(kf + 32 s + j - t) at
+// entry 32 s + j - t + 15; backward tiles w(kb - 32 s + t - j) at entry
+// 32 (NKMAX - 1 - s) + t - j + 31 (t < 16 rows, j < 32 columns)
+constexpr int MXWT = 32 * NKMAX + 16;
 
 // round to nearest even float -> bf16 bits (finite inputs)
 DEV unsigned bf16_bits(float f)
@@ -114,14 +116,6 @@ DEV mxf4 mfma(const bf16x8& a, const bf16x8& b, mxf4 c)
 
 DEV bf16x8 ld_bf16x8(const void* p) { return *(const bf16x8*)p; }
 
-DEV bf16x8 tile_ld(const uint4* p)
-{
-    const uint4 u = *p;
-    bf16x8 r;
-    __builtin_memcpy(&r, &u, 16);
-    return r;
-}
-
 // max / min over each 32-lane half of the wave
 DEV float half_max(float v)
 {
@@ -137,99 +131,117 @@ DEV float half_min(float v) { return -half_max(-v); }
 
 // ------------------------------------------------------------------ tables
 
-// One work-group per (K-step s, mask node m): the forward, backward and
-// derivative tiles of step s (work-group s = 0 also writes the support and
-// core).  The work-groups also clear the hand-off flags (and, for a saving
-// forward, mark every trajectory's saved traces valid with the value 2:
-// traces written by this path, with their exponent ranges; the fp64 fused
-// kernels write 1 and no ranges); work-group (0, 0) resets the counters
-// (and those a saving forward keeps for the backward).  handed, counters
-// and saved_flag may be NULL (a saving forward that takes another path
-// still writes the tables and clears the backward's counters).
-__global__ void __launch_bounds__(1024) stl_mx_tables(DevPlan plan, const float* params, int L, MxTab* tabs,
-                                                     int* counters, int* counters2, int* handed, int* saved_flag,
-                                                     int64_t B)
+DEV MaskP mx_mask_params(const DevPlan* Pk, const float* params, int m)
 {
-    __shared__ TabShared sh;
-    const int tid = threadIdx.x;
-    const int s = blockIdx.x, m = blockIdx.y;
-    const int flat = m * gridDim.x + s, nblk = gridDim.x * gridDim.y;
-    for (int64_t b = (int64_t)flat * blockDim.x + tid; b < B; b += (int64_t)nblk * blockDim.x) {
-        if (handed) handed[b] = 0;
-        if (saved_flag) saved_flag[b] = 2;
+    const Instr& I = Pk->ins[Pk->fused.ins[m]];
+    return mask_params(params + I.mask, I.flags & F_MASK_UNB);
+}
+
+// support, core and tile geometry of the N masks into sh.hd (collective over
+// the work-group; the support search of mask_info over both masks' windows
+// at once, one offset per thread)
+template <int N, class SH>
+DEV void mx_heads(const DevPlan* Pk, const float* params, int L, SH& sh)
+{
+    MaskP mp[N];
+    int k0[N], k1[N], n[N];
+#pragma unroll
+    for (int mm = 0; mm < N; ++mm) {
+        mp[mm] = mx_mask_params(Pk, params, mm);
+        mask_window(mp[mm], L, k0[mm], k1[mm]);
+        n[mm] = max(k1[mm] - k0[mm] + 1, 0);
     }
-    if (flat == 0 && counters && tid < 3) counters[tid] = 0;
-    if (flat == 0 && counters2 && tid < 3) counters2[tid] = 0;
-    const Instr& I = plan.ins[plan.fused.ins[m]];
-    MxTab& T = tabs[m];
-    const MaskInfo mi = mask_info(params, I, L, sh, nullptr, nullptr, nullptr);
-    const bool core = mi.any && mi.clo <= mi.chi;
-    const int kf = mi.klo & ~3, kb = (mi.khi + 3) & ~3;
-    const int NK = mi.any ? (16 + kb - kf + 31) / 32 : 0;
-    const double scale = core ? (double)mi.wc : 1.0;
-    const MaskP mp = mask_params(params + I.mask, I.flags & F_MASK_UNB);
-    if (s == 0 && tid == 0) {
-        T.ok = NK <= NKMAX;
-        T.any = mi.any;
-        T.klo = mi.klo;
-        T.khi = mi.khi;
-        T.clo = core ? mi.clo : 1;
-        T.chi = core ? mi.chi : 0;
-        T.kf = kf;
-        T.kb = kb;
-        T.NK = NK;
-        T.lscale = (float)log2(scale);
+    if (threadIdx.x < 2 * N) sh.ints[threadIdx.x] = (threadIdx.x & 1) ? -1 : L;
+    __syncthreads();
+    int lo[N], hi[N];
+#pragma unroll
+    for (int mm = 0; mm < N; ++mm) {
+        lo[mm] = L;
+        hi[mm] = -1;
     }
-    if (NK > NKMAX) return;                      // uniform over the work-group
-    const bool live = s < NK;                    // steps past NK: zero tiles
-    auto in_core = [&](int k) { return core && k >= mi.clo && k <= mi.chi; };
-    // weight of offset k divided by the scale (core offsets: exactly 1)
-    auto wk = [&](int k) -> double {
-        if (!live || k < mi.klo || k > mi.khi) return 0.0;
-        if (in_core(k)) return 1.0;
-        return (double)mask_wk(mp, k) / scale;
-    };
-    bool lf = false, lb = false, nza = false, nzb = false;
-    for (int e = tid; e < 512; e += blockDim.x) {
-        const int l = e >> 3, v = e & 7;
-        const int row = l & 15, col = 8 * (l >> 4) + v;
-        unsigned h, lo;
-        split2(wk(kf + 32 * s + col - row), h, lo);
-        ((unsigned short*)&T.Wf[s][0][l])[v] = (unsigned short)h;
-        ((unsigned short*)&T.Wf[s][1][l])[v] = (unsigned short)lo;
-        lf |= lo != 0;
-        const int k = kb - 32 * s + row - col;
-        split2(wk(k), h, lo);
-        ((unsigned short*)&T.Wb[s][0][l])[v] = (unsigned short)h;
-        ((unsigned short*)&T.Wb[s][1][l])[v] = (unsigned short)lo;
-        lb |= lo != 0;
-        // derivative weights (bands only: the core contributes nothing to
-        // d/da, d/db to fp32 rounding)
-        float da = 0.f, db = 0.f;
-        if (live && k >= mi.klo && k <= mi.khi && !in_core(k)) mask_wk(mp, k, &da, &db);
-        nza |= da != 0.f;
-        nzb |= db != 0.f;
-        split2((double)da, h, lo);
-        ((unsigned short*)&T.Dt[s][0][0][l])[v] = (unsigned short)h;
-        ((unsigned short*)&T.Dt[s][0][1][l])[v] = (unsigned short)lo;
-        split2((double)db, h, lo);
-        ((unsigned short*)&T.Dt[s][1][0][l])[v] = (unsigned short)h;
-        ((unsigned short*)&T.Dt[s][1][1][l])[v] = (unsigned short)lo;
+    for (int i = threadIdx.x; i < n[0] + (N > 1 ? n[N - 1] : 0); i += blockDim.x) {
+        const int mm = (N > 1 && i >= n[0]) ? N - 1 : 0;
+        const int k = k0[mm] + (mm ? i - n[0] : i);
+        if (mask_wk(mp[mm], k) > 0.f) {
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                if (q == mm) {
+                    lo[q] = min(lo[q], k);
+                    hi[q] = max(hi[q], k);
+                }
+        }
     }
-    lf = __syncthreads_or(lf);
-    lb = __syncthreads_or(lb);
-    nza = __syncthreads_or(nza);
-    nzb = __syncthreads_or(nzb);
-    if (tid == 0) {
-        T.flo_f[s] = lf;
-        T.flo_b[s] = lb;
-        T.fd[s] = (nza ? 1 : 0) | (nzb ? 2 : 0);
+#pragma unroll
+    for (int mm = 0; mm < N; ++mm) {
+        lo[mm] = wave_imin(lo[mm]);
+        hi[mm] = wave_imax(hi[mm]);
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&sh.ints[2 * mm], lo[mm]);
+            atomicMax(&sh.ints[2 * mm + 1], hi[mm]);
+        }
     }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        const int mm = threadIdx.x;
+        const MaskInfo mi = mask_core(mp[mm], sh.ints[2 * mm], sh.ints[2 * mm + 1]);
+        const bool core = mi.any && mi.clo <= mi.chi;
+        MxHead h;
+        h.any = mi.any;
+        h.klo = mi.klo;
+        h.khi = mi.khi;
+        h.clo = core ? mi.clo : 1;
+        h.chi = core ? mi.chi : 0;
+        h.kf = mi.klo & ~3;
+        h.kb = (mi.khi + 3) & ~3;
+        h.NK = mi.any ? (16 + h.kb - h.kf + 31) / 32 : 0;
+        h.ok = h.NK <= NKMAX;
+        h.scale = core ? (double)mi.wc : 1.0;
+        h.lscale = core ? lg2(mi.wc) : 0.f;
+        sh.hd[mm] = h;
+    }
+    __syncthreads();
+}
+
+
+// weight of offset k divided by the scale (0 outside the support, exactly 1
+// in the core), as packed bf16 hi (low half) and lo parts
+DEV unsigned mx_wpack(const MxHead& h, const MaskP& mp, int k)
+{
+    double w = 0.0;
+    if (k >= h.klo && k <= h.khi) w = (k >= h.clo && k <= h.chi) ? 1.0 : (double)mask_wk(mp, k) / h.scale;
+    unsigned hi, lo;
+    split2(w, hi, lo);
+    return hi | (lo << 16);
+}
+
+// the hi and lo tiles of lane `lane` from packed per-offset weights: entry
+// e0 + j - t for row t, column j (zero tiles where !live)
+DEV void mx_tile(const unsigned* wt, int e0, int lane, bool live, bf16x8& h, bf16x8& l, int sgn = 1)
+{
+    const int t = lane & 15, j0 = 8 * (lane >> 4);
+    uint4 uh, ul;
+    unsigned* ph = (unsigned*)&uh;
+    unsigned* pl = (unsigned*)&ul;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const unsigned u0 = live ? wt[e0 + sgn * (j0 + 2 * w - t)] : 0u;
+        const unsigned u1 = live ? wt[e0 + sgn * (j0 + 2 * w + 1 - t)] : 0u;
+        ph[w] = (u0 & 0xFFFFu) | (u1 << 16);
+        pl[w] = (u0 >> 16) | (u1 & 0xFFFF0000u);
+    }
+    __builtin_memcpy(&h, &uh, 16);
+    __builtin_memcpy(&l, &ul, 16);
 }
 
 // ------------------------------------------------------------------ kernels
 
 struct MxShared {
+    MxHead hd[MX_MAXN];          // per mask
+    int ints[8];                 // support search
+    unsigned wt[MX_MAXN][MXWT];  // packed per-offset weights (forward or backward tile offsets)
+    unsigned dt[MX_MAXN][2][MXWT];      // backward: d/da, d/db weights of the same offsets
+    unsigned char nzd[MX_MAXN][MXWT];   // backward: bit 0 (1): d/da (d/db) weight non-zero
+    int fd[MX_MAXN][NKMAX];      // backward: K-step s has d/da (bit 0) / d/db (bit 1) weights
     float R[MX_MAXN][MXG];       // forward: reference of the terms; backward: Q
     float C[MX_MAXN][MXG];       // backward: constant of the adjoint terms' exponent
     int frag[MXG];               // trajectory handed to the generic executor
@@ -242,14 +254,11 @@ struct MxShared {
     float pp[MX_MAXN][2][2][MXG];       // backward: d/da, d/db partials per matrix wave
 };
 
-// (the list index is checked against B: a counter that was not cleared must
-// not turn into a write out of bounds)
-DEV void mx_handoff(const KArgs& ka, const MxArgs& mx, int64_t b, int64_t B)
+// trajectory b goes to the generic executor (which finds it by its flag);
+// its saved traces are not valid
+DEV void mx_handoff(const KArgs& ka, const MxArgs& mx, int64_t b)
 {
-    if (atomicExch(&mx.handed[b], 1) == 0) {
-        const int i = atomicAdd(ka.list_count, 1);
-        if (i >= 0 && i < B) ka.list[i] = (int)b;
-    }
+    mx.handed[b] = 1;
     if (ka.saved_flag) ka.saved_flag[b] = 0;
 }
 
@@ -463,13 +472,37 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int L = (int)bt.T;
     const int64_t g0 = (int64_t)blockIdx.x * MXG;
+    const bool matrix = wv < 2 * N;
+    const int vt = tid - 128 * N;                // staging thread index
+    // ---- the reference sample (positions i * ceil(L / 32), i < 32, one per
+    // staging thread and row it serves) is read first: it needs no mask data
+    const int hs = vt >> 5, l32 = lane & 31;
+    float xs[2 / N][DD];
+    if (!matrix) {
+        const int j = min(L - 1, l32 * ((L + 31) / 32));
+#pragma unroll
+        for (int i = 0; i < 2 / N; ++i) {
+            const int64_t b = g0 + hs + 8 * N * i;
+#pragma unroll
+            for (int d = 0; d < DD; ++d) xs[i][d] = bt.x[((b < bt.B ? b : 0) * L + j) * DD + d];
+        }
+    }
+    // ---- per mask: support, core, tile geometry, and the weights of the
+    // forward tiles' offsets kf - 15 .. kf + 32 NKMAX (packed bf16 hi, lo)
+    mx_heads<N>(Pk, ka.params, L, sh);
+    // (for the backward of the same parameters)
+    if (blockIdx.x == 0 && tid < N && mx.heads) mx.heads[tid] = sh.hd[tid];
     bool ok = true;
 #pragma unroll
-    for (int mm = 0; mm < N; ++mm) ok = ok && mx.tabs[mm].ok;
+    for (int mm = 0; mm < N; ++mm) ok = ok && sh.hd[mm].ok;
     if (!ok) {
         // the masks do not fit the matrix-core path: the generic executor takes every trajectory
-        if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid, bt.B);
+        if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
         return;
+    }
+    for (int i = tid; i < N * MXWT; i += blockDim.x) {
+        const int mm = i / MXWT, e = i % MXWT;
+        sh.wt[mm][e] = mx_wpack(sh.hd[mm], mx_mask_params(Pk, ka.params, mm), sh.hd[mm].kf - 15 + e);
     }
     // (ordered before every use by the barrier that follows the references)
     if (tid < MXG) {
@@ -497,7 +530,7 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     auto unit = [&](int u) {
         Unit U;
         const int um = __builtin_amdgcn_readfirstlane(u >> 8), ur = (u >> 4) & 15, ug = u & 15;
-        const MxTab& TU = mx.tabs[um];
+        const MxHead& TU = sh.hd[um];
         const int64_t b = g0 + ur;
         U.M = mx_mask<DD>(Pk, ka.params, um);
         U.xb = bt.x + (b < bt.B ? b : 0) * (int64_t)L * DD;
@@ -547,19 +580,16 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     // each): round k's sums in body k, its outputs in body k + 1; an even
     // count lets the staging waves unroll by two with no conditional body
     const int nbody = (nround + 2) & ~1;
-    const bool matrix = wv < 2 * N;
+    __syncthreads();            // heads and per-offset weights known
     if (matrix) {
         // ---------------------------------------------------------- matrix waves
-        // (the weight tiles are read while the staging waves compute the
+        // (the weight tiles are built while the staging waves compute the
         // references and stage blocks 0 .. 3)
         const int m = wv >> 1, hh = wv & 1;
-        const MxTab& T = mx.tabs[m];
+        const int NKm = sh.hd[m].NK;
         bf16x8 Wh[NKMAX], Wl[NKMAX];
 #pragma unroll
-        for (int s = 0; s < NKMAX; ++s) {
-            Wh[s] = tile_ld(&T.Wf[s][0][lane]);
-            Wl[s] = tile_ld(&T.Wf[s][1][lane]);
-        }
+        for (int s = 0; s < NKMAX; ++s) mx_tile(sh.wt[m], 32 * s + 15, lane, s < NKm, Wh[s], Wl[s]);
 #pragma unroll
         for (int s = 0; s < NKMAX; ++s) {
             mx_pin(Wh[s]);
@@ -611,23 +641,13 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         }
     } else {
         // ---------------------------------------------------------- staging waves
-        const int vw = wv - 2 * N, vt = tid - 128 * N;
+        const int vw = wv - 2 * N;
         Unit U = unit(vt);
         bool sfrag = false;
-        // ---- references: midpoint of the exponents over a strided sample of
-        // each trajectory (positions i * ceil(L / 32), i < 32, one load per
-        // thread for every mask), reduced over each half-wave; the loads of
-        // blocks 0 .. 3 are in flight meanwhile
+        // ---- references: midpoint of the exponents over the sample of each
+        // trajectory, reduced over each half-wave; the loads of blocks 0 .. 3
+        // are in flight meanwhile
         {
-            const int hs = vt >> 5, l32 = lane & 31;
-            const int j = min(L - 1, l32 * ((L + 31) / 32));
-            float xs[2 / N][DD];
-#pragma unroll
-            for (int i = 0; i < 2 / N; ++i) {
-                const int64_t b = g0 + hs + 8 * N * i;
-#pragma unroll
-                for (int d = 0; d < DD; ++d) xs[i][d] = bt.x[((b < bt.B ? b : 0) * L + j) * DD + d];
-            }
             float xv[4][8 * DD];
 #pragma unroll
             for (int blk = 0; blk < 4; ++blk) stage_load(U, blk, xv[blk]);
@@ -659,7 +679,7 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         int klomax = 0;
 #pragma unroll
         for (int mm = 0; mm < N; ++mm) {
-            const MxTab& T = mx.tabs[mm];
+            const MxHead& T = sh.hd[mm];
             const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, mm);
             Rb[mm] = sh.R[mm][bc] + T.lscale;
             c2[mm] = RC.sg * M.sg / (M.beta * LOG2E);
@@ -781,7 +801,17 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
             rp[2] = (int)sh.R[mm][r];
         }
     }
-    if (tid < MXG && sh.frag[tid] && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid, bt.B);
+    // this group's rows: hand-off flag (no other work-group touches them), and
+    // for a saving forward the saved traces' flag (2: written by this path,
+    // with their exponent ranges)
+    if (tid < MXG && g0 + tid < bt.B) {
+        if (sh.frag[tid]) {
+            mx_handoff(ka, mx, g0 + tid);
+        } else {
+            mx.handed[g0 + tid] = 0;
+            if (ka.saved_flag) ka.saved_flag[g0 + tid] = 2;
+        }
+    }
 }
 
 // Backward, with the forward's two roles: matrix waves (2 per mask) compute
@@ -800,27 +830,69 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int L = (int)bt.T;
     const int64_t g0 = (int64_t)blockIdx.x * MXG;
-    // this group's hand-off flags (no other work-group touches them), when
-    // no tables kernel ran before this kernel in the same call
-    if (mx.own_flags && tid < MXG && g0 + tid < bt.B) mx.handed[g0 + tid] = 0;
+    // this group's hand-off flags (no other work-group touches them) are
+    // cleared by the thread that then decides the row's hand-off (stores are
+    // left to the end: a wait for a load would also wait for them)
+    auto finish_row = [&](int r, bool hand) {
+        if (g0 + r >= bt.B) return;
+        mx.handed[g0 + r] = 0;
+        if (hand) mx_handoff(ka, mx, g0 + r);
+    };
+    // ---- per mask: support, core, tile geometry; the weights of the
+    // backward tiles' offsets kb - 32 NKMAX - 31 .. kb + 15 and their d/da,
+    // d/db (bands only: the core contributes nothing to d/da, d/db to fp32
+    // rounding)
+    // (the forward's heads: the same parameters give the same values)
+    if (mx.heads) {
+        if (tid < N) sh.hd[tid] = mx.heads[tid];
+        __syncthreads();
+    } else {
+        mx_heads<N>(Pk, ka.params, L, sh);
+    }
     bool ok = true;
 #pragma unroll
-    for (int mm = 0; mm < N; ++mm) ok = ok && mx.tabs[mm].ok;
+    for (int mm = 0; mm < N; ++mm) ok = ok && sh.hd[mm].ok;
     if (!ok) {
-        if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid, bt.B);
+        if (tid < MXG) finish_row(tid, true);
         return;
     }
-    // ---- per mask: the list of derivative tiles (K-step, kind)
     if (tid == 0) sh.over = 0;
     if (tid < MXG) sh.frag[tid] = 0;
     __syncthreads();
+    for (int i = tid; i < N * MXWT; i += blockDim.x) {
+        const int mm = i / MXWT, e = i % MXWT;
+        const MxHead& h = sh.hd[mm];
+        const MaskP mp = mx_mask_params(Pk, ka.params, mm);
+        const int k = h.kb - 32 * (NKMAX - 1) - 31 + e;
+        sh.wt[mm][e] = mx_wpack(h, mp, k);
+        float da = 0.f, db = 0.f;
+        if (k >= h.klo && k <= h.khi && !(k >= h.clo && k <= h.chi)) mask_wk(mp, k, &da, &db);
+        unsigned hi, lo;
+        split2((double)da, hi, lo);
+        sh.dt[mm][0][e] = hi | (lo << 16);
+        split2((double)db, hi, lo);
+        sh.dt[mm][1][e] = hi | (lo << 16);
+        sh.nzd[mm][e] = (unsigned char)((da != 0.f ? 1 : 0) | (db != 0.f ? 2 : 0));
+    }
+    __syncthreads();
+    // K-step s reads entries 32 (NKMAX - 1 - s) .. + 46: it has d/da (d/db)
+    // weights where one of them does
+    if (tid < N * NKMAX) {
+        const int mm = tid / NKMAX, st = tid % NKMAX;
+        int f = 0;
+        if (st < sh.hd[mm].NK)
+            for (int e = 0; e < 47; ++e) f |= sh.nzd[mm][32 * (NKMAX - 1 - st) + e];
+        sh.fd[mm][st] = f;
+    }
+    __syncthreads();
+    // ---- per mask: the list of derivative tiles (K-step, kind)
     if (tid < N) {
-        const MxTab& T = mx.tabs[tid];
+        const int NKt = sh.hd[tid].NK;
         int nd = 0;
         bool over = false;
-        for (int s = 0; s < min(T.NK, NKMAX); ++s)
+        for (int s = 0; s < min(NKt, NKMAX); ++s)
             for (int w = 0; w < 2; ++w)
-                if ((T.fd[s] >> w) & 1) {
+                if ((sh.fd[tid][s] >> w) & 1) {
                     if (nd < NDMAX) {
                         sh.dstep[tid][nd] = s;
                         sh.dwhich[tid][nd] = w;
@@ -848,7 +920,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                     if ((float)hi - (float)lo > 2.f * MX_HALF) frag = true;
                     else Q = -floorf(0.5f * ((float)lo + (float)hi));
                 }
-                C = ((float)(-rp[2]) - Q) - mx.tabs[mm].lscale;
+                C = ((float)(-rp[2]) - Q) - sh.hd[mm].lscale;
             }
             if (frag) atomicOr(&sh.frag[r], 1);
         }
@@ -874,7 +946,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     auto unit = [&](int u) {
         Unit U;
         const int um = u >> 8, ur = (u >> 4) & 15, ug = u & 15;
-        const MxTab& TU = mx.tabs[um];
+        const MxHead& TU = sh.hd[um];
         const int64_t b = g0 + ur;
         const bool row = b < bt.B && !sh.frag[ur] && !over;
         U.G = ka.G + (row ? b : 0) * (int64_t)L;
@@ -919,11 +991,14 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     // tiles in unused slots)
     float* gbuf = (float*)(mxs + N * MXG * MXRS);       // [2][N][2][4][64][4] d/dx factors
     uint4* dlds = (uint4*)(mxs + N * MXG * MXRS + mx_xch_bytes(N, DD, true));
-    for (int e = tid; e < N * NDMAX * 2 * 64; e += blockDim.x) {
-        const int mm = e / (NDMAX * 128), d = (e / 128) % NDMAX, hl = (e / 64) & 1, l = e & 63;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (d < sh.nd[mm]) v = mx.tabs[mm].Dt[sh.dstep[mm][d]][sh.dwhich[mm][d]][hl][l];
-        dlds[e] = v;
+    for (int e = tid; e < N * NDMAX * 64; e += blockDim.x) {
+        const int mm = e / (NDMAX * 64), d = (e / 64) % NDMAX, l = e & 63;
+        bf16x8 th, tl;
+        const bool use = d < sh.nd[mm];
+        const int st = use ? sh.dstep[mm][d] : 0;
+        mx_tile(sh.dt[mm][use ? sh.dwhich[mm][d] : 0], 32 * (NKMAX - 1 - st) + 31, l, use, th, tl, -1);
+        __builtin_memcpy(&dlds[(mm * NDMAX + d) * 128 + l], &th, 16);
+        __builtin_memcpy(&dlds[(mm * NDMAX + d) * 128 + 64 + l], &tl, 16);
     }
     const int nround = (L + MXROUND - 1) / MXROUND;
     const int nbody = (nround + 2) & ~1;        // as in the forward: even, both roles alike
@@ -935,15 +1010,12 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     if (matrix) {
         // ---------------------------------------------------------- matrix waves
         const int m = wv >> 1, hh = wv & 1;
-        const MxTab& T = mx.tabs[m];
         const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, m);
-        const bool any = T.any;
+        const bool any = sh.hd[m].any;
+        const int NKm = sh.hd[m].NK;
         bf16x8 Wh[NKMAX], Wl[NKMAX];
 #pragma unroll
-        for (int s = 0; s < NKMAX; ++s) {
-            Wh[s] = tile_ld(&T.Wb[s][0][lane]);
-            Wl[s] = tile_ld(&T.Wb[s][1][lane]);
-        }
+        for (int s = 0; s < NKMAX; ++s) mx_tile(sh.wt[m], 32 * (NKMAX - 1 - s) + 31, lane, s < NKm, Wh[s], Wl[s], -1);
 #pragma unroll
         for (int s = 0; s < NKMAX; ++s) {
             mx_pin(Wh[s]);
@@ -1157,7 +1229,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
             if (slot >= 0) mx.part[(bq * P.n_masks + slot) * 2 + ab] = s;
         }
     }
-    if (tid < MXG && (sh.frag[tid] || over) && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid, bt.B);
+    if (tid < MXG) finish_row(tid, sh.frag[tid] || over);
 }
 
 }  // namespace stlmi

@@ -124,18 +124,18 @@ struct KArgs {
     float* saved;          // fused forward: mask-node traces out ([n][B][T]) or NULL
     const float* saved_in; // fused backward: mask-node traces in, or NULL (recompute)
     int* saved_flag;       // [B]: 1 where the saved traces of a trajectory are valid
+    const int* scan;       // [B] or NULL: the generic executor takes the trajectories whose flag is set
     int part_stride;       // rows of mask_part per trajectory (1; a caller with more rows per
                            // trajectory has the generic executor clear the others)
 };
 
 // Launch arguments of the matrix-core smooth-mask kernels (stl_mx.h).
-struct MxTab;
+struct MxHead;
 struct MxArgs {
-    const MxTab* tabs;
-    int* handed;           // [B] 1 once a trajectory is on the hand-off list
+    MxHead* heads;         // [n] per-mask geometry: written by the forward, read by the backward (NULL: derive)
+    int* handed;           // [B] written by every call: 1 where the generic executor takes the trajectory
     int* ranges;           // [B][n][3] floor(min), ceil(max) of O over each trajectory's trace, reference R
     float* part;           // [B][n_masks][2] d/da, d/db partials
-    int own_flags;         // backward: each work-group clears its rows' hand-off flags (no tables kernel ran)
 };
 
 }  // namespace stlmi

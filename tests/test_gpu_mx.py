@@ -94,7 +94,7 @@ def test_mx_hands_off_wide_range_and_wide_masks():
 def test_mx_saved_equals_recompute_and_is_deterministic():
     """Saved pair vs recompute, bit for bit, with two trajectories handed to
     the generic executor; the saved backward runs twice after one forward
-    (its hand-off list counters must be back at zero for the second call)."""
+    (each call rewrites every hand-off flag it reads)."""
     import torch
     spec, params, x = W.workload(2, B=40, T=1200)
     x[5, 600:, 0] += 25.0
