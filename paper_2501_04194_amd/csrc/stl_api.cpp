@@ -374,6 +374,11 @@ static stl_status run(const stl_plan* plan, const stl_batch* bt, const float* pa
         // writes every trajectory's hand-off flag; the generic executor then
         // takes the flagged ones
         MxArgs mx;
+        for (int m = 0; m < 2; ++m) {
+            const bool has = m < dp.fused.n;
+            mx.moff[m] = has ? dp.ins[dp.fused.ins[m]].mask : 0;
+            mx.munb[m] = has ? ((dp.ins[dp.fused.ins[m]].flags & F_MASK_UNB) != 0) : 0;
+        }
         mx.heads = (MxHead*)(wsb + g.off_mxheads);
         mx.handed = (int*)(wsb + g.off_handed);
         mx.part = ka.mask_part;

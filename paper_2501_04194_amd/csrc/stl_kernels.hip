@@ -659,7 +659,7 @@ DEV void mask_window(const MaskP& mp, int L, int& k0, int& k1)
 // the core where both sigmoid derivatives are below 2^-24 (|c(k-a)|,
 // |c(k-b)| > 17), over which w is constant to fp32 rounding, given the
 // support [klo, khi]
-DEV MaskInfo mask_core(const MaskP& mp, int klo, int khi)
+DEV MaskInfo mask_core(const MaskP& mp, int klo, int khi, int mid_known = INT_MIN, float w_known = 0.f)
 {
     MaskInfo mi;
     mi.klo = klo;
@@ -673,8 +673,9 @@ DEV MaskInfo mask_core(const MaskP& mp, int klo, int khi)
         mi.clo = 1;
         mi.chi = 0;
     }
+    // (w at the midpoint, unless the caller has it already)
     if (mi.clo > mi.chi) { mi.clo = 1; mi.chi = 0; mi.wc = 0.f; }
-    else mi.wc = mask_wk(mp, (mi.clo + mi.chi) / 2);
+    else mi.wc = (mi.clo + mi.chi) / 2 == mid_known ? w_known : mask_wk(mp, (mi.clo + mi.chi) / 2);
     return mi;
 }
 

@@ -131,59 +131,88 @@ DEV float half_min(float v) { return -half_max(-v); }
 
 // ------------------------------------------------------------------ tables
 
-DEV MaskP mx_mask_params(const DevPlan* Pk, const float* params, int m)
+static_assert(MX_MAXN <= 2, "MxArgs carries the window parameters of two masks");
+
+// (from the launch arguments: one dependent read fewer than through the plan)
+DEV MaskP mx_mask_params(const MxArgs& mx, const float* params, int m)
 {
-    const Instr& I = Pk->ins[Pk->fused.ins[m]];
-    return mask_params(params + I.mask, I.flags & F_MASK_UNB);
+    return mask_params(params + mx.moff[m], mx.munb[m] != 0);
 }
 
 // support, core and tile geometry of the N masks into sh.hd (collective over
 // the work-group; the support search of mask_info over both masks' windows
 // at once, one offset per thread)
 template <int N, class SH>
-DEV void mx_heads(const DevPlan* Pk, const float* params, int L, SH& sh)
+DEV void mx_heads(const MxArgs& mx, const float* params, int L, SH& sh)
 {
+    // (every mask's parameters are requested before any is used)
     MaskP mp[N];
+#pragma unroll
+    for (int mm = 0; mm < N; ++mm) mp[mm] = mx_mask_params(mx, params, mm);
     int k0[N], k1[N], n[N];
 #pragma unroll
     for (int mm = 0; mm < N; ++mm) {
-        mp[mm] = mx_mask_params(Pk, params, mm);
         mask_window(mp[mm], L, k0[mm], k1[mm]);
         n[mm] = max(k1[mm] - k0[mm] + 1, 0);
     }
+#pragma unroll
+    for (int mm = 0; mm < N; ++mm)
+        if (threadIdx.x == mm) sh.mp[mm] = mp[mm];
     if (threadIdx.x < 2 * N) sh.ints[threadIdx.x] = (threadIdx.x & 1) ? -1 : L;
     __syncthreads();
+    // the core weight at the core's midpoint, computed beside the search for
+    // the usual case of a core that the support does not clip (a bounded
+    // mask's core is then [ceil(a + 17/c), floor(b - 17/c)])
+    // (by the last wave, which has the fewest offsets to search)
+    if (threadIdx.x >= blockDim.x - 64 && threadIdx.x < blockDim.x - 64 + N) {
+        const int mm = threadIdx.x - (blockDim.x - 64);
+        const MaskP m = sh.mp[mm];
+        int mid = INT_MIN;
+        if (!m.unb && m.c > 0.f) {
+            const int clo = (int)fminf(ceilf(m.a + 17.f / m.c), 2e9f);
+            const int chi = (int)fmaxf(floorf(m.b - 17.f / m.c), -2e9f);
+            if (clo <= chi) mid = (int)(((int64_t)clo + chi) / 2);
+        }
+        sh.ints[2 * N + 2 * mm] = mid;
+        sh.ints[2 * N + 2 * mm + 1] = __float_as_int(mid != INT_MIN ? mask_wk(m, mid) : 0.f);
+    }
+    // support bounds: offset k0 + i of the masks' windows laid end to end is
+    // thread i's (k grows with the lane, so a wave's bounds are its first and
+    // last lane with w > 0)
     int lo[N], hi[N];
 #pragma unroll
     for (int mm = 0; mm < N; ++mm) {
         lo[mm] = L;
         hi[mm] = -1;
     }
-    for (int i = threadIdx.x; i < n[0] + (N > 1 ? n[N - 1] : 0); i += blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    for (int i0 = threadIdx.x - lane; i0 < n[0] + (N > 1 ? n[N - 1] : 0); i0 += blockDim.x) {
+        const int i = i0 + lane;
         const int mm = (N > 1 && i >= n[0]) ? N - 1 : 0;
         const int k = k0[mm] + (mm ? i - n[0] : i);
-        if (mask_wk(mp[mm], k) > 0.f) {
+        const bool pos = i < n[0] + (N > 1 ? n[N - 1] : 0) && mask_wk(mm ? mp[N - 1] : mp[0], k) > 0.f;
 #pragma unroll
-            for (int q = 0; q < N; ++q)
-                if (q == mm) {
-                    lo[q] = min(lo[q], k);
-                    hi[q] = max(hi[q], k);
-                }
+        for (int q = 0; q < N; ++q) {
+            const unsigned long long bq = __ballot(pos && mm == q);
+            if (bq) {
+                const int fl = __builtin_ctzll(bq), ll = 63 - __builtin_clzll(bq);
+                const int base = k0[q] - (q ? n[0] : 0) + i0;
+                lo[q] = min(lo[q], base + fl);
+                hi[q] = max(hi[q], base + ll);
+            }
         }
     }
 #pragma unroll
-    for (int mm = 0; mm < N; ++mm) {
-        lo[mm] = wave_imin(lo[mm]);
-        hi[mm] = wave_imax(hi[mm]);
-        if ((threadIdx.x & 63) == 0) {
+    for (int mm = 0; mm < N; ++mm)
+        if (lane == 0) {
             atomicMin(&sh.ints[2 * mm], lo[mm]);
             atomicMax(&sh.ints[2 * mm + 1], hi[mm]);
         }
-    }
     __syncthreads();
     if (threadIdx.x < N) {
         const int mm = threadIdx.x;
-        const MaskInfo mi = mask_core(mp[mm], sh.ints[2 * mm], sh.ints[2 * mm + 1]);
+        const MaskInfo mi = mask_core(sh.mp[mm], sh.ints[2 * mm], sh.ints[2 * mm + 1], sh.ints[2 * N + 2 * mm],
+                                      __int_as_float(sh.ints[2 * N + 2 * mm + 1]));
         const bool core = mi.any && mi.clo <= mi.chi;
         MxHead h;
         h.any = mi.any;
@@ -201,7 +230,6 @@ DEV void mx_heads(const DevPlan* Pk, const float* params, int L, SH& sh)
     }
     __syncthreads();
 }
-
 
 // weight of offset k divided by the scale (0 outside the support, exactly 1
 // in the core), as packed bf16 hi (low half) and lo parts
@@ -237,7 +265,8 @@ DEV void mx_tile(const unsigned* wt, int e0, int lane, bool live, bf16x8& h, bf1
 
 struct MxShared {
     MxHead hd[MX_MAXN];          // per mask
-    int ints[8];                 // support search
+    MaskP mp[MX_MAXN];           // per mask: window parameters
+    int ints[4 * MX_MAXN];       // support search: bounds, then a precomputed core weight
     unsigned wt[MX_MAXN][MXWT];  // packed per-offset weights (forward or backward tile offsets)
     unsigned dt[MX_MAXN][2][MXWT];      // backward: d/da, d/db weights of the same offsets
     unsigned char nzd[MX_MAXN][MXWT];   // backward: bit 0 (1): d/da (d/db) weight non-zero
@@ -489,7 +518,7 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     }
     // ---- per mask: support, core, tile geometry, and the weights of the
     // forward tiles' offsets kf - 15 .. kf + 32 NKMAX (packed bf16 hi, lo)
-    mx_heads<N>(Pk, ka.params, L, sh);
+    mx_heads<N>(mx, ka.params, L, sh);
     // (for the backward of the same parameters)
     if (blockIdx.x == 0 && tid < N && mx.heads) mx.heads[tid] = sh.hd[tid];
     bool ok = true;
@@ -499,19 +528,6 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         // the masks do not fit the matrix-core path: the generic executor takes every trajectory
         if (tid < MXG && g0 + tid < bt.B) mx_handoff(ka, mx, g0 + tid);
         return;
-    }
-    for (int i = tid; i < N * MXWT; i += blockDim.x) {
-        const int mm = i / MXWT, e = i % MXWT;
-        sh.wt[mm][e] = mx_wpack(sh.hd[mm], mx_mask_params(Pk, ka.params, mm), sh.hd[mm].kf - 15 + e);
-    }
-    // (ordered before every use by the barrier that follows the references)
-    if (tid < MXG) {
-        sh.frag[tid] = 0;
-#pragma unroll
-        for (int mm = 0; mm < N; ++mm) {
-            sh.omin[mm][tid] = INT_MAX;
-            sh.omax[mm][tid] = INT_MIN;
-        }
     }
     // ---- staging units: unit u = (mask u / 256, row (u / 16) % 16, 8-position
     // group u % 16) of a block; position p of mask m holds the term of x at
@@ -574,6 +590,26 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         *(bf16x8*)q = h;
         *(bf16x8*)(q + 16) = l;
     };
+    // x of blocks 0 .. 3 is requested as soon as the windows are known
+    Unit U = unit(matrix ? 0 : vt);
+    float xv[4][8 * DD];
+    if (!matrix) {
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) stage_load(U, blk, xv[blk]);
+    }
+    for (int i = tid; i < N * MXWT; i += blockDim.x) {
+        const int mm = i / MXWT, e = i % MXWT;
+        sh.wt[mm][e] = mx_wpack(sh.hd[mm], sh.mp[mm], sh.hd[mm].kf - 15 + e);
+    }
+    // (ordered before every use by the barrier that follows the references)
+    if (tid < MXG) {
+        sh.frag[tid] = 0;
+#pragma unroll
+        for (int mm = 0; mm < N; ++mm) {
+            sh.omin[mm][tid] = INT_MAX;
+            sh.omax[mm][tid] = INT_MIN;
+        }
+    }
     float* accb = (float*)(mxs + N * MXG * MXRS);                   // [2][N][2][4][64][4] window sums
     const int nround = (L + MXROUND - 1) / MXROUND;
     // bodies of the loop below (both roles run the same number, one barrier
@@ -642,15 +678,11 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     } else {
         // ---------------------------------------------------------- staging waves
         const int vw = wv - 2 * N;
-        Unit U = unit(vt);
         bool sfrag = false;
         // ---- references: midpoint of the exponents over the sample of each
         // trajectory, reduced over each half-wave; the loads of blocks 0 .. 3
         // are in flight meanwhile
         {
-            float xv[4][8 * DD];
-#pragma unroll
-            for (int blk = 0; blk < 4; ++blk) stage_load(U, blk, xv[blk]);
 #pragma unroll
             for (int i = 0; i < 2 / N; ++i) {
                 const int r = hs + 8 * N * i;
@@ -844,10 +876,13 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     // rounding)
     // (the forward's heads: the same parameters give the same values)
     if (mx.heads) {
-        if (tid < N) sh.hd[tid] = mx.heads[tid];
+        if (tid < N) {
+            sh.hd[tid] = mx.heads[tid];
+            sh.mp[tid] = mx_mask_params(mx, ka.params, tid);
+        }
         __syncthreads();
     } else {
-        mx_heads<N>(Pk, ka.params, L, sh);
+        mx_heads<N>(mx, ka.params, L, sh);
     }
     bool ok = true;
 #pragma unroll
@@ -862,7 +897,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     for (int i = tid; i < N * MXWT; i += blockDim.x) {
         const int mm = i / MXWT, e = i % MXWT;
         const MxHead& h = sh.hd[mm];
-        const MaskP mp = mx_mask_params(Pk, ka.params, mm);
+        const MaskP mp = sh.mp[mm];
         const int k = h.kb - 32 * (NKMAX - 1) - 31 + e;
         sh.wt[mm][e] = mx_wpack(h, mp, k);
         float da = 0.f, db = 0.f;

@@ -133,6 +133,8 @@ struct KArgs {
 struct MxHead;
 struct MxArgs {
     MxHead* heads;         // [n] per-mask geometry: written by the forward, read by the backward (NULL: derive)
+    int moff[2];           // per mask (at most two): offset of its window parameters a, b, c, eps in params
+    int munb[2];           //   and whether the window is unbounded (read here, not through the plan)
     int* handed;           // [B] written by every call: 1 where the generic executor takes the trajectory
     int* ranges;           // [B][n][3] floor(min), ceil(max) of O over each trajectory's trace, reference R
     float* part;           // [B][n_masks][2] d/da, d/db partials
