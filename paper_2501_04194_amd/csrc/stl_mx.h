@@ -261,15 +261,54 @@ DEV void mx_tile(const unsigned* wt, int e0, int lane, bool live, bf16x8& h, bf1
     __builtin_memcpy(&l, &ul, 16);
 }
 
+// the packed weight of entry e into the four-entry groups that hold it
+// (group i holds entries i .. i + 3)
+DEV void mx_wq_put(uint4* wq, int e, unsigned v)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (e - q >= 0) ((unsigned*)&wq[e - q])[q] = v;
+}
+
+// mx_tile from four-entry groups: two 16-byte reads per tile instead of
+// eight 4-byte reads (entries ascend with the column for sgn = 1, descend
+// for sgn = -1)
+DEV void mx_tile4(const uint4* wq, int e0, int lane, bool live, bf16x8& h, bf16x8& l, int sgn = 1)
+{
+    const int t = lane & 15, j0 = 8 * (lane >> 4);
+    unsigned u[8];
+    if (sgn > 0) {
+        const uint4 q0 = wq[e0 + j0 - t], q1 = wq[e0 + j0 - t + 4];
+        u[0] = q0.x; u[1] = q0.y; u[2] = q0.z; u[3] = q0.w;
+        u[4] = q1.x; u[5] = q1.y; u[6] = q1.z; u[7] = q1.w;
+    } else {
+        const int e1 = e0 + t - j0;
+        const uint4 q0 = wq[e1 - 3], q1 = wq[e1 - 7];
+        u[0] = q0.w; u[1] = q0.z; u[2] = q0.y; u[3] = q0.x;
+        u[4] = q1.w; u[5] = q1.z; u[6] = q1.y; u[7] = q1.x;
+    }
+    uint4 uh, ul;
+    unsigned* ph = (unsigned*)&uh;
+    unsigned* pl = (unsigned*)&ul;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const unsigned u0 = live ? u[2 * w] : 0u, u1 = live ? u[2 * w + 1] : 0u;
+        ph[w] = (u0 & 0xFFFFu) | (u1 << 16);
+        pl[w] = (u0 >> 16) | (u1 & 0xFFFF0000u);
+    }
+    __builtin_memcpy(&h, &uh, 16);
+    __builtin_memcpy(&l, &ul, 16);
+}
+
 // ------------------------------------------------------------------ kernels
 
 struct MxShared {
     MxHead hd[MX_MAXN];          // per mask
     MaskP mp[MX_MAXN];           // per mask: window parameters
     int ints[4 * MX_MAXN];       // support search: bounds, then a precomputed core weight
-    unsigned wt[MX_MAXN][MXWT];  // packed per-offset weights (forward or backward tile offsets)
+    uint4 wq[MX_MAXN][MXWT];     // packed per-offset weights (forward or backward tile offsets), in
+                                 //   groups of four consecutive entries
     unsigned dt[MX_MAXN][2][MXWT];      // backward: d/da, d/db weights of the same offsets
-    unsigned char nzd[MX_MAXN][MXWT];   // backward: bit 0 (1): d/da (d/db) weight non-zero
     int fd[MX_MAXN][NKMAX];      // backward: K-step s has d/da (bit 0) / d/db (bit 1) weights
     float R[MX_MAXN][MXG];       // forward: reference of the terms; backward: Q
     float C[MX_MAXN][MXG];       // backward: constant of the adjoint terms' exponent
@@ -599,7 +638,7 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     }
     for (int i = tid; i < N * MXWT; i += blockDim.x) {
         const int mm = i / MXWT, e = i % MXWT;
-        sh.wt[mm][e] = mx_wpack(sh.hd[mm], sh.mp[mm], sh.hd[mm].kf - 15 + e);
+        mx_wq_put(sh.wq[mm], e, mx_wpack(sh.hd[mm], sh.mp[mm], sh.hd[mm].kf - 15 + e));
     }
     // (ordered before every use by the barrier that follows the references)
     if (tid < MXG) {
@@ -625,7 +664,7 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
         const int NKm = sh.hd[m].NK;
         bf16x8 Wh[NKMAX], Wl[NKMAX];
 #pragma unroll
-        for (int s = 0; s < NKMAX; ++s) mx_tile(sh.wt[m], 32 * s + 15, lane, s < NKm, Wh[s], Wl[s]);
+        for (int s = 0; s < NKMAX; ++s) mx_tile4(sh.wq[m], 32 * s + 15, lane, s < NKm, Wh[s], Wl[s]);
 #pragma unroll
         for (int s = 0; s < NKMAX; ++s) {
             mx_pin(Wh[s]);
@@ -891,15 +930,32 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         if (tid < MXG) finish_row(tid, true);
         return;
     }
+    // G and l of blocks 0 .. 3 are requested as soon as the windows are
+    // known (rows of trajectories handed off are read too: their terms are
+    // masked where they are staged)
+    float gv0[4][8], lv0[4][8];
+    {
+        const int um = tid >> 8, ur = (tid >> 4) & 15, ug = tid & 15;
+        const int64_t b = g0 + ur < bt.B ? g0 + ur : 0;
+        const float* Gp = ka.G + b * (int64_t)L;
+        const float* lp = ka.saved_in + ((int64_t)um * bt.B + b) * L;
+        const int t0u = 8 * ug - sh.hd[um].kb;
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            mx_load8<1, VEC>(Gp, MXBLK * blk + t0u, L, gv0[blk]);
+            mx_load8<1, VEC>(lp, MXBLK * blk + t0u, L, lv0[blk]);
+        }
+    }
     if (tid == 0) sh.over = 0;
     if (tid < MXG) sh.frag[tid] = 0;
+    if (tid < N * NKMAX) sh.fd[tid / NKMAX][tid % NKMAX] = 0;
     __syncthreads();
     for (int i = tid; i < N * MXWT; i += blockDim.x) {
         const int mm = i / MXWT, e = i % MXWT;
         const MxHead& h = sh.hd[mm];
         const MaskP mp = sh.mp[mm];
         const int k = h.kb - 32 * (NKMAX - 1) - 31 + e;
-        sh.wt[mm][e] = mx_wpack(h, mp, k);
+        mx_wq_put(sh.wq[mm], e, mx_wpack(h, mp, k));
         float da = 0.f, db = 0.f;
         if (k >= h.klo && k <= h.khi && !(k >= h.clo && k <= h.chi)) mask_wk(mp, k, &da, &db);
         unsigned hi, lo;
@@ -907,37 +963,37 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         sh.dt[mm][0][e] = hi | (lo << 16);
         split2((double)db, hi, lo);
         sh.dt[mm][1][e] = hi | (lo << 16);
-        sh.nzd[mm][e] = (unsigned char)((da != 0.f ? 1 : 0) | (db != 0.f ? 2 : 0));
+        // K-step s reads entries 32 (NKMAX - 1 - s) .. + 46: it has d/da
+        // (d/db) weights where one of them does
+        const int nz = (da != 0.f ? 1 : 0) | (db != 0.f ? 2 : 0);
+        if (nz) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int st = NKMAX - 1 - e / 32 + q;     // the steps whose entries include e
+                if (st >= 0 && st < NKMAX && e - 32 * (NKMAX - 1 - st) <= 46) atomicOr(&sh.fd[mm][st], nz);
+            }
+        }
     }
     __syncthreads();
-    // K-step s reads entries 32 (NKMAX - 1 - s) .. + 46: it has d/da (d/db)
-    // weights where one of them does
-    if (tid < N * NKMAX) {
-        const int mm = tid / NKMAX, st = tid % NKMAX;
-        int f = 0;
-        if (st < sh.hd[mm].NK)
-            for (int e = 0; e < 47; ++e) f |= sh.nzd[mm][32 * (NKMAX - 1 - st) + e];
-        sh.fd[mm][st] = f;
-    }
-    __syncthreads();
-    // ---- per mask: the list of derivative tiles (K-step, kind)
-    if (tid < N) {
-        const int NKt = sh.hd[tid].NK;
-        int nd = 0;
-        bool over = false;
-        for (int s = 0; s < min(NKt, NKMAX); ++s)
-            for (int w = 0; w < 2; ++w)
-                if ((sh.fd[tid][s] >> w) & 1) {
-                    if (nd < NDMAX) {
-                        sh.dstep[tid][nd] = s;
-                        sh.dwhich[tid][nd] = w;
-                        ++nd;
-                    } else {
-                        over = true;
-                    }
-                }
-        sh.nd[tid] = nd;
-        if (over) sh.over = 1;
+    // ---- per mask: the list of derivative tiles (K-step, kind) in order of
+    // (s, kind); lane (m, s, kind) of the first wave finds its place by a
+    // count of the set flags before it
+    if (tid < 64) {
+        const int mm = tid / (2 * NKMAX), s = (tid / 2) % NKMAX, w = tid & 1;
+        const bool f = mm < N && s < min(sh.hd[mm < N ? mm : 0].NK, NKMAX) && ((sh.fd[mm < N ? mm : 0][s] >> w) & 1);
+        const unsigned long long bal = __ballot(f);
+        const unsigned long long below = bal & ((1ull << tid) - 1ull) & ~((1ull << (mm * 2 * NKMAX)) - 1ull);
+        const int idx = __popcll(below);
+        if (f && idx < NDMAX) {
+            sh.dstep[mm][idx] = s;
+            sh.dwhich[mm][idx] = w;
+        }
+        if (mm < N && s == 0 && w == 0) {
+            const unsigned long long mine = (bal >> (mm * 2 * NKMAX)) & ((1ull << (2 * NKMAX)) - 1ull);
+            const int total = __popcll(mine);
+            sh.nd[mm] = min(total, NDMAX);
+            if (total > NDMAX) sh.over = 1;
+        }
     }
     // ---- per trajectory: saved data valid; the reference Q (from the
     // forward's range of O) and the constant C = -(R + lscale) - Q of the
@@ -1016,11 +1072,8 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     };
     {
         const Unit U = unit(tid);
-        float gv[4][8], lv[4][8];
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) stage_load(U, blk, gv[blk], lv[blk]);
-#pragma unroll
-        for (int blk = 0; blk < 4; ++blk) stage_write(U, blk, gv[blk], lv[blk]);
+        for (int blk = 0; blk < 4; ++blk) stage_write(U, blk, gv0[blk], lv0[blk]);
     }
     // derivative tiles of every mask in LDS ([n][NDMAX][hi, lo][lane], zero
     // tiles in unused slots)
@@ -1050,7 +1103,8 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         const int NKm = sh.hd[m].NK;
         bf16x8 Wh[NKMAX], Wl[NKMAX];
 #pragma unroll
-        for (int s = 0; s < NKMAX; ++s) mx_tile(sh.wt[m], 32 * (NKMAX - 1 - s) + 31, lane, s < NKm, Wh[s], Wl[s], -1);
+        for (int s = 0; s < NKMAX; ++s)
+            mx_tile4(sh.wq[m], 32 * (NKMAX - 1 - s) + 31, lane, s < NKm, Wh[s], Wl[s], -1);
 #pragma unroll
         for (int s = 0; s < NKMAX; ++s) {
             mx_pin(Wh[s]);
