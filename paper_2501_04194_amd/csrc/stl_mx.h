@@ -31,18 +31,21 @@
 // a multiple of 4 such a group lies wholly inside or outside the trajectory
 // and is loaded with 16-byte loads.
 //
-// Work decomposition: a work-group takes 16 trajectories from start to end,
-// four waves per mask node.  The terms (or adjoint terms) of each mask
-// stream through an LDS ring of 640 positions per trajectory, 128 positions
-// (one block) at a time: in round k the waves compute outputs
-// [128 k, 128 k + 128) from blocks k .. k+3 while the loads of block k+4 are
-// in flight, then write it over block k-1.  Each wave computes two output
-// tiles t and t + 32, which read the same E blocks one K-step apart, so every
-// E read feeds six products.  The reference R of a trajectory's terms is the
-// midpoint of its exponents over a strided sample; every staged exponent is
-// checked to lie within 100 of it (so that nothing over- or underflows), and
-// a trajectory that fails is handed to the generic executor.  The backward's
-// reference Q comes from the range of O the forward recorded.
+// Work decomposition: a work-group takes 16 trajectories from start to end.
+// It first derives each mask's support, core and tile geometry from the
+// parameters and builds its weight tiles in LDS (no table kernel).  The
+// terms (or adjoint terms) of each mask stream through an LDS ring of 640
+// positions per trajectory, 128 positions (one block) at a time: in round k
+// the matrix waves compute outputs [128 k, 128 k + 128) from blocks
+// k .. k+3 (four 16-output tiles per wave, which read the same staged terms
+// one K-step apart, so every ring read feeds up to 12 products), while the
+// staging waves turn round k-1's sums into outputs and stage block k+4 over
+// block k-1.  The reference R of a trajectory's terms is the midpoint of its
+// exponents over a strided sample; every staged exponent is checked to lie
+// within 100 of it (so that nothing over- or underflows), and a trajectory
+// that fails is flagged for the generic executor, which runs after the
+// kernel in the same call.  The backward's reference Q comes from the range
+// of O the forward recorded.
 #pragma once
 
 namespace stlmi {
