@@ -1171,8 +1171,10 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                     }
                     eh = ehn;
                     el = eln;
-                    // (one factor per step, among the products)
+                    // (one factor per step, among the products: the scheduler
+                    // keeps each step's instructions together)
                     if (s < 15) factor(s >> 2, s & 3);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
                 factor(3, 3);
 #pragma unroll
