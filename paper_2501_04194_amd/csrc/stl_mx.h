@@ -662,61 +662,68 @@ __global__ void __launch_bounds__(384 * N, 1) stl_mx_fwd(DevPlan plan, Batch bt,
     if (matrix) {
         // ---------------------------------------------------------- matrix waves
         // (the weight tiles are built while the staging waves compute the
-        // references and stage blocks 0 .. 3)
+        // references and stage blocks 0 .. 3).  The K-loop is compiled for
+        // KS = NKMAX and KS = NKMAX - 1 steps and chosen by the window
+        // (uniform): a window of fewer steps skips the last step's products.
         const int m = wv >> 1, hh = wv & 1;
-        const int NKm = sh.hd[m].NK;
-        bf16x8 Wh[NKMAX], Wl[NKMAX];
+        const int NKm = __builtin_amdgcn_readfirstlane(sh.hd[m].NK);
+        auto run = [&](auto ks) {
+            constexpr int KS = decltype(ks)::value;
+            bf16x8 Wh[KS], Wl[KS];
 #pragma unroll
-        for (int s = 0; s < NKMAX; ++s) mx_tile4(sh.wq[m], 32 * s + 15, lane, s < NKm, Wh[s], Wl[s]);
+            for (int s = 0; s < KS; ++s) mx_tile4(sh.wq[m], 32 * s + 15, lane, s < NKm, Wh[s], Wl[s]);
 #pragma unroll
-        for (int s = 0; s < NKMAX; ++s) {
-            mx_pin(Wh[s]);
-            mx_pin(Wl[s]);
-        }
-        __syncthreads();        // references known
-        __syncthreads();        // blocks 0 .. 3 staged
-        const int bc = lane & 15, rq = lane >> 4;
-        const unsigned char* ebase = mxs + (m * MXG + bc) * MXRS;
-        for (int k = 0; k < nbody; ++k) {
-            if (k < nround) {
-                const int t0 = MXROUND * k + 16 * hh;
-                const int pr = (t0 + 8 * rq) % MXRING;
-                mxf4 acc[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[j] = mxf4{0.f, 0.f, 0.f, 0.f};
-                // each K-step's terms are read one step ahead of their products
-                bf16x8 eh = ld_bf16x8(ebase + ring_byte(pr, 0)), el = ld_bf16x8(ebase + ring_byte(pr, 0) + 16);
-#pragma unroll
-                for (int s = 0; s < NKMAX + 3; ++s) {
-                    bf16x8 ehn = eh, eln = el;
-                    if (s + 1 < NKMAX + 3) {
-                        const unsigned char* ep = ebase + ring_byte(pr, 32 * (s + 1));
-                        ehn = ld_bf16x8(ep);
-                        eln = ld_bf16x8(ep + 16);
-                    }
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int st = s - j;
-                        if (st >= 0 && st < NKMAX) {
-                            acc[j] = mfma(Wh[st], eh, acc[j]);
-                            acc[j] = mfma(Wh[st], el, acc[j]);
-                            acc[j] = mfma(Wl[st], eh, acc[j]);
-                        }
-                    }
-                    eh = ehn;
-                    el = eln;
-                }
-                float4* ob = (float4*)accb + ((((k & 1) * N + m) * 2 + hh) * 4) * 64 + lane;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) ob[j * 64] = make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
-            }
-#pragma unroll
-            for (int s = 0; s < NKMAX; ++s) {
+            for (int s = 0; s < KS; ++s) {
                 mx_pin(Wh[s]);
                 mx_pin(Wl[s]);
             }
-            __syncthreads();
-        }
+            __syncthreads();        // references known
+            __syncthreads();        // blocks 0 .. 3 staged
+            const int bc = lane & 15, rq = lane >> 4;
+            const unsigned char* ebase = mxs + (m * MXG + bc) * MXRS;
+            for (int k = 0; k < nbody; ++k) {
+                if (k < nround) {
+                    const int t0 = MXROUND * k + 16 * hh;
+                    const int pr = (t0 + 8 * rq) % MXRING;
+                    mxf4 acc[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[j] = mxf4{0.f, 0.f, 0.f, 0.f};
+                    // each K-step's terms are read one step ahead of their products
+                    bf16x8 eh = ld_bf16x8(ebase + ring_byte(pr, 0)), el = ld_bf16x8(ebase + ring_byte(pr, 0) + 16);
+#pragma unroll
+                    for (int s = 0; s < KS + 3; ++s) {
+                        bf16x8 ehn = eh, eln = el;
+                        if (s + 1 < KS + 3) {
+                            const unsigned char* ep = ebase + ring_byte(pr, 32 * (s + 1));
+                            ehn = ld_bf16x8(ep);
+                            eln = ld_bf16x8(ep + 16);
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int st = s - j;
+                            if (st >= 0 && st < KS) {
+                                acc[j] = mfma(Wh[st], eh, acc[j]);
+                                acc[j] = mfma(Wh[st], el, acc[j]);
+                                acc[j] = mfma(Wl[st], eh, acc[j]);
+                            }
+                        }
+                        eh = ehn;
+                        el = eln;
+                    }
+                    float4* ob = (float4*)accb + ((((k & 1) * N + m) * 2 + hh) * 4) * 64 + lane;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) ob[j * 64] = make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+                }
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    mx_pin(Wh[s]);
+                    mx_pin(Wl[s]);
+                }
+                __syncthreads();
+            }
+        };
+        if (NKm < NKMAX) run(std::integral_constant<int, NKMAX - 1>{});
+        else run(std::integral_constant<int, NKMAX>{});
     } else {
         // ---------------------------------------------------------- staging waves
         const int vw = wv - 2 * N;
