@@ -601,7 +601,7 @@ def main():
         "wall_s": t_wall,
         "roofline": {"bound": "hbm",
                      "kernel": ("stl_mx_bwd + hand-off fix-up (the stl_backward_saved call)" if dom_is_bwd
-                                else "stl_mx_tables + stl_mx_fwd + hand-off fix-up (the stl_forward_saving call)"),
+                                else "stl_mx_fwd + hand-off fix-up (the stl_forward_saving call)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_step": BYTES_BWD if dom_is_bwd else BYTES_FWD},
