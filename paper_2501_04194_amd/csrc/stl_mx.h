@@ -986,10 +986,10 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
     }
     __syncthreads();
     // ---- per mask: the list of derivative tiles (K-step, kind) in order of
-    // (s, kind); lane (m, s, kind) of the first wave finds its place by a
-    // count of the set flags before it
+    // (kind, s): the d/da tiles first; lane (m, kind, s) of the first wave
+    // finds its place by a count of the set flags before it
     if (tid < 64) {
-        const int mm = tid / (2 * NKMAX), s = (tid / 2) % NKMAX, w = tid & 1;
+        const int mm = tid / (2 * NKMAX), w = (tid / NKMAX) & 1, s = tid % NKMAX;
         const bool f = mm < N && s < min(sh.hd[mm < N ? mm : 0].NK, NKMAX) && ((sh.fd[mm < N ? mm : 0][s] >> w) & 1);
         const unsigned long long bal = __ballot(f);
         const unsigned long long below = bal & ((1ull << tid) - 1ull) & ~((1ull << (mm * 2 * NKMAX)) - 1ull);
@@ -1195,48 +1195,60 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                     for (int rr = 0; rr < 4; ++rr) g[rr] = ldexpf(acc[j][rr] * fj[j][rr], nj[j][rr]);
                     ob[j * 64] = make_float4(g[0], g[1], g[2], g[3]);
                 }
-                // derivative sums: K-step dst[d] of every tile, added into this
-                // lane's d/da, d/db partials.  Product i = (d, j) = (i / 4, i % 4);
-                // the terms of each product are read one product ahead, and the
-                // products of i + 1 are issued before the sums of i.
+                // derivative sums: product (d, j) of tile d and the terms of
+                // K-step dst[d] + j goes into accumulator j.  The weighted sum
+                // over this lane's outputs is linear, so each kind's products
+                // are summed on the matrix cores and weighted once: the tiles
+                // are listed d/da first (na of them), and the d/da sums are
+                // taken where the d/db tiles begin.  Terms are read one product
+                // ahead.
+                int na = 0;
+#pragma unroll
+                for (int d = 0; d < NDMAX; ++d) na += (d < nd && !isb[d]) ? 1 : 0;
+                na = __builtin_amdgcn_readfirstlane(na);
+                auto wsum = [&](const mxf4* a) {
+                    float r = 0.f;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) r += ldexpf(a[j][q] * fj[j][q], nj[j][q]);
+                    return r;
+                };
+                mxf4 ad[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) ad[j] = mxf4{0.f, 0.f, 0.f, 0.f};
                 bf16x8 dh = ld_bf16x8(hbase + ring_byte(pr, 32 * dst[0])),
                        dl = ld_bf16x8(hbase + ring_byte(pr, 32 * dst[0]) + 16);
-                bf16x8 Dh = ld_bf16x8(dl_m), Dl = ld_bf16x8(dl_m + 64);
-                mxf4 ap = mxf4{0.f, 0.f, 0.f, 0.f};
-                float sum = 0.f;
+                bf16x8 Dh, Dl;
 #pragma unroll
-                for (int i = 0; i <= NDMAX * 4; ++i) {
-                    mxf4 an = ap;
-                    if (i < NDMAX * 4) {
-                        const int d = i >> 2;
-                        if ((i & 3) == 0 && d > 0) {
-                            Dh = ld_bf16x8(dl_m + d * 128);
-                            Dl = ld_bf16x8(dl_m + d * 128 + 64);
-                        }
-                        bf16x8 dhn = dh, dln = dl;
-                        if (i + 1 < NDMAX * 4) {
-                            const unsigned char* ep = hbase + ring_byte(pr, 32 * (dst[(i + 1) >> 2] + ((i + 1) & 3)));
-                            dhn = ld_bf16x8(ep);
-                            dln = ld_bf16x8(ep + 16);
-                        }
-                        an = mfma(Dh, dh, mxf4{0.f, 0.f, 0.f, 0.f});
-                        an = mfma(Dh, dl, an);
-                        an = mfma(Dl, dh, an);
-                        dh = dhn;
-                        dl = dln;
-                    }
-                    if (i > 0) {
-                        const int d = (i - 1) >> 2, j = (i - 1) & 3;
+                for (int i = 0; i < NDMAX * 4; ++i) {
+                    const int d = i >> 2, j = i & 3;
+                    if (j == 0) {
+                        Dh = ld_bf16x8(dl_m + d * 128);
+                        Dl = ld_bf16x8(dl_m + d * 128 + 64);
+                        if (d > 0 && d == na) {
+                            // (uniform) the d/da tiles are done
+                            pam += wsum(ad);
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) sum += ldexpf(ap[q] * fj[j][q], nj[j][q]);
-                        if (j == 3) {
-                            pam += isb[d] ? 0.f : sum;
-                            pbm += isb[d] ? sum : 0.f;
-                            sum = 0.f;
+                            for (int j2 = 0; j2 < 4; ++j2) ad[j2] = mxf4{0.f, 0.f, 0.f, 0.f};
                         }
                     }
-                    ap = an;
+                    bf16x8 dhn = dh, dln = dl;
+                    if (i + 1 < NDMAX * 4) {
+                        const unsigned char* ep = hbase + ring_byte(pr, 32 * (dst[(i + 1) >> 2] + ((i + 1) & 3)));
+                        dhn = ld_bf16x8(ep);
+                        dln = ld_bf16x8(ep + 16);
+                    }
+                    ad[j] = mfma(Dh, dh, ad[j]);
+                    ad[j] = mfma(Dh, dl, ad[j]);
+                    ad[j] = mfma(Dl, dh, ad[j]);
+                    dh = dhn;
+                    dl = dln;
                 }
+                // (the last kind's sums: d/db, or d/da when every listed tile is one)
+                const float last = wsum(ad);
+                pam += na >= nd ? last : 0.f;
+                pbm += na >= nd ? 0.f : last;
             }
 #pragma unroll
             for (int s = 0; s < NKMAX; ++s) {
