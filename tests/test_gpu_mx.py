@@ -73,6 +73,26 @@ def test_mx_shapes(case, T):
     check_formula(specs[case], x, params=params, what="mx shape %d T=%d" % (case, T))
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_mx_random_windows(seed):
+    """Two masks with seeded windows and sigmoid slopes: the derivative bands
+    (about 34 / c offsets wide) cover one to three K-steps each, so the
+    backward's lists of d/da and d/db tiles split differently between the
+    kinds, or exceed the list and hand off (d/d bounds compared too)."""
+    rng = np.random.default_rng(300 + seed)
+    T = 640 if seed % 2 else 639
+    x = np.cumsum(rng.normal(size=(17, T, 2)) * 0.05, axis=1).astype(np.float32)
+    slopes = [0.6, 1.0, 1.7, 3.0]
+    params = {}
+    kids = []
+    for m, (kind, pred) in enumerate([("eventually", lin([1.0, 0.0])), ("always", lin([0.0, -1.0], -0.2))]):
+        a = float(rng.uniform(0.0, 150.0))
+        params["a%d" % m], params["b%d" % m] = a, a + float(rng.uniform(15.0, 300.0))
+        kids.append(mask(kind, pred, "a%d" % m, "b%d" % m, c=slopes[int(rng.integers(4))]))
+    spec = {"op": "and" if seed % 3 else "or", "smooth": True, "beta": 10.0, "children": kids}
+    check_formula(spec, x, params=params, what="mx random windows %d" % seed)
+
+
 def test_mx_hands_off_wide_range_and_wide_masks():
     """A trajectory whose exponent range exceeds the staged limit, a mask
     wider than the tiles (b - a = 500) and one whose derivative bands need
