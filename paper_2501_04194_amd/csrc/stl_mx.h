@@ -1110,16 +1110,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         const int m = wv >> 1, hh = wv & 1;
         const MxMask<DD> M = mx_mask<DD>(Pk, ka.params, m);
         const bool any = sh.hd[m].any;
-        const int NKm = sh.hd[m].NK;
-        bf16x8 Wh[NKMAX], Wl[NKMAX];
-#pragma unroll
-        for (int s = 0; s < NKMAX; ++s)
-            mx_tile4(sh.wq[m], 32 * (NKMAX - 1 - s) + 31, lane, s < NKm, Wh[s], Wl[s], -1);
-#pragma unroll
-        for (int s = 0; s < NKMAX; ++s) {
-            mx_pin(Wh[s]);
-            mx_pin(Wl[s]);
-        }
+        const int NKm = __builtin_amdgcn_readfirstlane(sh.hd[m].NK);
         const int nd = sh.nd[m];
         int dst[NDMAX];
         bool isb[NDMAX];
@@ -1134,6 +1125,19 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
         const unsigned char* hbase = mxs + (m * MXG + bc) * MXRS;
         const float Qb = sh.R[m][bc];
         float pam = 0.f, pbm = 0.f;
+        // The K-loop is compiled for KS = NKMAX and KS = NKMAX - 1 steps and
+        // chosen by the window (uniform), as in the forward.
+        auto run = [&](auto ks) {
+        constexpr int KS = decltype(ks)::value;
+        bf16x8 Wh[KS], Wl[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            mx_tile4(sh.wq[m], 32 * (NKMAX - 1 - s) + 31, lane, s < NKm, Wh[s], Wl[s], -1);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            mx_pin(Wh[s]);
+            mx_pin(Wl[s]);
+        }
         // x at this lane's outputs of the four tiles, loaded one round ahead
         // (unconditionally: the addresses are clamped)
         float xv[4][4 * DD];
@@ -1160,9 +1164,9 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                 for (int j = 0; j < 4; ++j) acc[j] = mxf4{0.f, 0.f, 0.f, 0.f};
                 bf16x8 eh = ld_bf16x8(hbase + ring_byte(pr, 0)), el = ld_bf16x8(hbase + ring_byte(pr, 0) + 16);
 #pragma unroll
-                for (int s = 0; s < NKMAX + 3; ++s) {
+                for (int s = 0; s < KS + 3; ++s) {
                     bf16x8 ehn = eh, eln = el;
-                    if (s + 1 < NKMAX + 3) {
+                    if (s + 1 < KS + 3) {
                         const unsigned char* ep = hbase + ring_byte(pr, 32 * (s + 1));
                         ehn = ld_bf16x8(ep);
                         eln = ld_bf16x8(ep + 16);
@@ -1170,7 +1174,7 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int st = s - j;
-                        if (st >= 0 && st < NKMAX) {
+                        if (st >= 0 && st < KS) {
                             acc[j] = mfma(Wh[st], eh, acc[j]);
                             acc[j] = mfma(Wh[st], el, acc[j]);
                             acc[j] = mfma(Wl[st], eh, acc[j]);
@@ -1179,8 +1183,12 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                     eh = ehn;
                     el = eln;
                     // (one factor per step, among the products: the scheduler
-                    // keeps each step's instructions together)
+                    // keeps each step's instructions together; the last step
+                    // also takes those of the steps a shorter loop lacks)
                     if (s < 15) factor(s >> 2, s & 3);
+                    if (s == KS + 2)
+#pragma unroll
+                        for (int q = KS + 3; q < 15; ++q) factor(q >> 2, q & 3);
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 factor(3, 3);
@@ -1251,12 +1259,15 @@ __global__ void __launch_bounds__(256 * N, 1) stl_mx_bwd(DevPlan plan, Batch bt,
                 pbm += na >= nd ? 0.f : last;
             }
 #pragma unroll
-            for (int s = 0; s < NKMAX; ++s) {
+            for (int s = 0; s < KS; ++s) {
                 mx_pin(Wh[s]);
                 mx_pin(Wl[s]);
             }
             __syncthreads();
         }
+        };
+        if (NKm < NKMAX) run(std::integral_constant<int, NKMAX - 1>{});
+        else run(std::integral_constant<int, NKMAX>{});
         // ---- d/da, d/db partials: lanes of one trajectory (l, l + 16, l + 32,
         // l + 48), then the mask's two matrix waves in order
         pam *= M.sg / M.beta;
