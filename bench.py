@@ -97,17 +97,16 @@ MFMA_PEAK_TFLOPS = 2500.0     # dense bf16
 MFMA_FLOP = 2 * 16 * 16 * 32  # one v_mfma_f32_16x16x32_bf16
 
 
-def mfma_executed(B, T, fwd_ms, bwd_ms, n_masks=2, nkmax=12, nk_fwd=11, ndmax=4):
+def mfma_executed(B, T, fwd_ms, bwd_ms, n_masks=2, nk=11, ndmax=4):
     """bf16 matrix-core throughput of the two calls as executed: per group of
     16 trajectories and round of 128 outputs, two matrix waves per mask run
-    4 tiles x nk_fwd K-steps x 3 products (forward: its K-loop is compiled for
-    12 and for 11 steps, and the smooth-mask workload's windows fit in 11),
-    and 4 tiles x nkmax K-steps x 3 plus ndmax x 4 x 3 derivative products
-    (backward)."""
+    4 tiles x nk K-steps x 3 products (both K-loops are compiled for 12 and
+    for 11 steps, and the smooth-mask workload's windows fit in 11), plus
+    ndmax x 4 x 3 derivative products in the backward."""
     groups, rounds = -(-B // 16), -(-T // 128)
     per = groups * rounds * 2 * n_masks * MFMA_FLOP
-    f = per * 4 * nk_fwd * 3
-    b = per * (4 * nkmax * 3 + ndmax * 4 * 3)
+    f = per * 4 * nk * 3
+    b = per * (4 * nk * 3 + ndmax * 4 * 3)
     tf = {"forward": f / (fwd_ms * 1e-3) / 1e12, "backward": b / (bwd_ms * 1e-3) / 1e12}
     return {"unit": "TFLOP/s", "peak": MFMA_PEAK_TFLOPS, "forward": tf["forward"], "backward": tf["backward"],
             "frac_backward": tf["backward"] / MFMA_PEAK_TFLOPS, "flop_per_step": f + b}
